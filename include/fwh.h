@@ -1,0 +1,165 @@
+/*
+ * fwh.h -- C ABI of the MI355X (gfx950) library for the wind-tunnel FW-H
+ * far-field integral: permeable surface, Farassat 1A after the Garrick-triangle
+ * change of frame and the angle-of-attack rotation, nondimensional (Sec. II C-D
+ * of Zhang, Yu, Liu, Li, "An MPI-OpenMP mixing parallel open source FW-H code
+ * for aeroacoustics calculation").
+ *
+ * What is computed.  For panels p (centre y_p, unit outward normal n_p, area
+ * dS_p), observers o (position x_o) and source frames tau_n = tau0 + n*dtau,
+ * n = 0..N-1, given density rho, velocity u (full values, nondimensional by the
+ * mean flow) and the pressure pulsation p' (by rho0 U0^2) on every panel at
+ * every frame (inputs listed at the end of Sec. II C):
+ *   Q   = (-U0_i + rho u_i) n_i,  L_i = p' n_i + rho (u_i - U0_i) u_j n_j
+ *                                               Eqs. (Qn_New_nd), (Li_New_nd), (U_0_nd)
+ *   Qdot, Ldot_i: 2nd-order differences in source time, one-sided at the
+ *   first and last frame (Sec. III B, "compute Noise");
+ *   R, Rhat, M_R: Garrick distance and radiation direction with the AoA
+ *   rotation, Eqs. (R_New)..(R2_New), surface Mach vector M = -M0 U0hat;
+ *   delay R/c0 = M0 R (Eq. (tau2));
+ *   observer window t_start = tau0 + max_p delay, t_end = tau_{N-1} + min_p
+ *   delay (Eqs. (t_start), (t_end), per observer), observer samples
+ *   t_k = t_start + k dtau, k < N_t = floor((t_end - t_start)/dtau + 1e-9) + 1;
+ *   p'(o, k) = sum_p s_{p,o}(t_k - delay), with s the natural cubic spline
+ *   (Sec. III B, "interp pressure signal") of the integrand of
+ *   Eqs. (pT_WT_nd) + (pL_WT_nd).
+ * In this frame every pair has a fixed delay, so the evaluation is a
+ * fixed fractional-delay gather-sum over panels.
+ *
+ * Layouts (row-major, element counts):
+ *   geometry (host):  y [P][3], normal [P][3], dS [P], x_obs [O][3]      (double)
+ *   surface data (device, time-major, one frame after another as a solver
+ *   writes them): rho [N][P], u [3][N][P], p' [N][P]       (FWH_F64 or FWH_F32)
+ *   output (device):  p_out [O][n_t_max]; entries k >= N_t(o) are written 0.
+ *                     double in FWH_MODE_F64, float otherwise.
+ *   adjoint input:    grad_p [O][n_t_max], same type as p_out; entries
+ *                     k >= N_t(o) are ignored.
+ *   gradients:        g_rho [N][P], g_u [3][N][P], g_p [N][P], same type as
+ *                     the surface data.
+ *
+ * Ownership.  Every device buffer belongs to the caller, including the
+ * workspace whose size fwh_plan_create reports; the library never allocates
+ * device memory.  The plan keeps host copies of the geometry and, after
+ * fwh_setup, the device address of the workspace, which must stay valid and
+ * untouched by the caller until fwh_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t (0 = legacy default stream); all work is
+ * enqueued on it.  fwh_setup synchronises `stream` once (it reads two doubles
+ * per observer back to size the observer window).  fwh_forward and
+ * fwh_adjoint do not synchronise.  Forward and adjoint calls on one plan share
+ * workspace regions (coefficients and scratch), so the caller must order all
+ * calls on one plan (one stream, or events between streams); plans with
+ * different workspaces are independent.
+ *
+ * Errors.  Every call returns FWH_OK (0) or a negative code; fwh_last_error()
+ * returns a message for the calling thread's most recent failure.  Nothing is
+ * thrown across the ABI and nothing aborts.
+ */
+#ifndef FWH_H
+#define FWH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWH_OK          0
+#define FWH_EINVAL     -1   /* null pointer, bad enum, non-finite or non-positive geometry */
+#define FWH_EDOMAIN    -2   /* Mach number outside (0, 1), dtau <= 0 */
+#define FWH_EWINDOW    -3   /* some observer has t_end < t_start (record shorter than the delay spread) */
+#define FWH_ESIZE      -4   /* P, O < 1, N < 4, or sizes beyond the supported range */
+#define FWH_EWORKSPACE -5   /* workspace null, too small, or not 256-byte aligned */
+#define FWH_EHIP       -6   /* a HIP runtime call or kernel launch failed */
+#define FWH_ESTATE     -7   /* call out of order (e.g. forward before setup) */
+
+/* data types of surface data and gradients */
+#define FWH_F64  0
+#define FWH_F32  1
+
+/* arithmetic/storage modes */
+#define FWH_MODE_F64   0   /* plain FP64 form: FP64 tables, coefficients and gather */
+#define FWH_MODE_F32   1   /* FP32 gather with FP32 coefficient storage; FP64 geometry, delays and taps */
+#define FWH_MODE_BF16  2   /* FP32 gather with BF16 (round-to-nearest-even) coefficient storage */
+
+typedef struct {
+    int64_t n_panels;        /* P >= 1 */
+    int64_t n_obs;           /* O >= 1 */
+    int64_t n_tau;           /* N >= 4 source frames */
+    const double *y;         /* host [P][3] panel centres */
+    const double *normal;    /* host [P][3] unit outward normals */
+    const double *dS;        /* host [P] panel areas, > 0 */
+    const double *x_obs;     /* host [O][3] observer positions */
+    double mach;             /* M0 = U0/c0, 0 < M0 < 1 */
+    double aoa_deg;          /* angle of attack (degrees) of the mean flow in the x1-x2 plane */
+    double dtau;             /* source (and observer) time step, > 0 */
+    double tau0;             /* time of frame 0 */
+    int32_t mode;            /* FWH_MODE_* */
+} fwh_setup_args;
+
+typedef struct fwh_plan fwh_plan;
+
+/* Validate the arguments, copy the geometry into a new plan and report the
+ * device workspace size in bytes.  Host only: no HIP call.  Sec. II C lists the
+ * inputs (coordinates, normals, areas; Mach number, AoA, time step), Sec. III A
+ * the control parameters (Mach number, AoA, time step, number of observers,
+ * number of frames).  On failure *out is NULL. */
+int fwh_plan_create(const fwh_setup_args *args, fwh_plan **out, size_t *workspace_bytes);
+
+/* Bind the caller-owned device workspace (>= workspace_bytes, 256-byte
+ * aligned) and run the setup on `stream`: pair delays, per-observer window
+ * (Eqs. (t_start), (t_end), via a device max/min reduction read back to the
+ * host), then per-pair fractional-delay taps and integrand weights
+ * (Eqs. (R_New)..(R2_New), (tau2), (pT_WT_nd), (pL_WT_nd)).  Synchronises
+ * `stream`.  FWH_EWINDOW if a window is empty. */
+int fwh_setup(fwh_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Observer window of a set-up plan (host values): t_start [O], n_t [O]
+ * (samples per observer) and their maximum (row length of p_out).  Any
+ * output pointer may be NULL. */
+int fwh_obs_window(const fwh_plan *plan, double *t_start, int64_t *n_t, int64_t *n_t_max);
+
+/* Forward: source terms, derivatives and spline coefficients (once per
+ * panel, observer-independent), then the gather-sum over panels into
+ * p_out [O][n_t_max] (Sec. III B-C: "compute Noise", "interp pressure signal",
+ * surface integration).  in_dtype: FWH_F64 or FWH_F32 for rho, u, p'. */
+int fwh_forward(fwh_plan *plan, int32_t in_dtype, const void *rho, const void *u, const void *p_prime,
+                void *p_out, void *stream);
+
+/* Adjoint of fwh_forward (not in the paper): given grad_p = dJ/dp'(o, k)
+ * [O][n_t_max], write dJ/drho, dJ/du, dJ/dp' (time-major, in_dtype).  The
+ * forward inputs are needed for the nonlinear source terms.  The transposed
+ * gather is panel-major and uses no atomics, so results are deterministic. */
+int fwh_adjoint(fwh_plan *plan, int32_t in_dtype, const void *rho, const void *u, const void *p_prime,
+                const void *grad_p, void *g_rho, void *g_u, void *g_p, void *stream);
+
+/* Per-stage timing (the analogue of the per-phase times of Table I): when
+ * enabled, every stage launched on a plan is bracketed by a pair of HIP events
+ * recorded on the call's stream.  fwh_profile_read waits for the recorded
+ * events of one stage, returns their summed elapsed time (ms) and the number of
+ * launches, and forgets them.  Stages: */
+#define FWH_STAGE_SETUP       0   /* delays, window reduction, tables (device work only) */
+#define FWH_STAGE_SOURCE      1   /* source terms, derivatives, spline coefficients */
+#define FWH_STAGE_GATHER      2   /* forward gather-sum over panels */
+#define FWH_STAGE_REDUCE      3   /* sum of panel-split partials (FP32/BF16 modes) */
+#define FWH_STAGE_ADJ_GATHER  4   /* transposed gather */
+#define FWH_STAGE_SOURCE_ADJ  5   /* transpose of the source stage and chain rule */
+#define FWH_NUM_STAGES        6
+int fwh_profile_enable(fwh_plan *plan, int enable);
+int fwh_profile_read(fwh_plan *plan, int32_t stage, double *total_ms, int64_t *launches);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+void fwh_destroy(fwh_plan *plan);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *fwh_last_error(void);
+
+/* Library version string. */
+const char *fwh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWH_H */

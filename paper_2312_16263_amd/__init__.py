@@ -1,0 +1,244 @@
+"""Python binding of libfwh (the gfx950 FW-H far-field library, C ABI in
+include/fwh.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libfwh.so``.  PyTorch provides device memory (the workspace and the output
+tensors) and the current HIP stream.  If the library is missing, every entry
+point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwh.so")
+
+FWH_OK, FWH_EINVAL, FWH_EDOMAIN, FWH_EWINDOW, FWH_ESIZE, FWH_EWORKSPACE, FWH_EHIP, FWH_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+FWH_F64, FWH_F32 = 0, 1
+MODE_F64, MODE_F32, MODE_BF16 = 0, 1, 2
+MODES = {"f64": MODE_F64, "f32": MODE_F32, "bf16": MODE_BF16}
+ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW: "FWH_EWINDOW",
+               FWH_ESIZE: "FWH_ESIZE", FWH_EWORKSPACE: "FWH_EWORKSPACE", FWH_EHIP: "FWH_EHIP",
+               FWH_ESTATE: "FWH_ESTATE"}
+
+# names declared in include/fwh.h
+EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_profile_enable",
+            "fwh_profile_read", "fwh_destroy", "fwh_last_error", "fwh_version"]
+STAGES = {"setup": 0, "source": 1, "gather": 2, "reduce": 3, "adj_gather": 4, "source_adj": 5}
+
+
+class FwhError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SetupArgs(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int64), ("n_obs", ctypes.c_int64), ("n_tau", ctypes.c_int64),
+                ("y", ctypes.POINTER(ctypes.c_double)), ("normal", ctypes.POINTER(ctypes.c_double)),
+                ("dS", ctypes.POINTER(ctypes.c_double)), ("x_obs", ctypes.POINTER(ctypes.c_double)),
+                ("mach", ctypes.c_double), ("aoa_deg", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("tau0", ctypes.c_double), ("mode", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfwh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libfwh.so not found at {LIB_PATH}; build it with __graft_entry__.build() "
+                               "or python paper_2312_16263_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.fwh_plan_create.argtypes = [ctypes.POINTER(SetupArgs), ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.fwh_plan_create.restype = ctypes.c_int
+        L.fwh_setup.argtypes = [vp, vp, sz, vp]
+        L.fwh_setup.restype = ctypes.c_int
+        L.fwh_obs_window.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fwh_obs_window.restype = ctypes.c_int
+        L.fwh_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.fwh_forward.restype = ctypes.c_int
+        L.fwh_adjoint.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fwh_adjoint.restype = ctypes.c_int
+        L.fwh_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.fwh_profile_enable.restype = ctypes.c_int
+        L.fwh_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.fwh_profile_read.restype = ctypes.c_int
+        L.fwh_destroy.argtypes = [vp]
+        L.fwh_destroy.restype = None
+        L.fwh_last_error.argtypes = []
+        L.fwh_last_error.restype = ctypes.c_char_p
+        L.fwh_version.argtypes = []
+        L.fwh_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != FWH_OK:
+        raise FwhError(code, lib().fwh_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Window:
+    t_start: np.ndarray
+    n_t: np.ndarray
+    n_t_max: int
+
+
+class Plan:
+    """A set-up FW-H plan on the current CUDA(HIP) device.
+
+    y, normal [P,3], dS [P], x_obs [O,3]: geometry (host arrays);
+    mach, aoa_deg, dtau, tau0, n_tau: flow and time grid; mode: 'f64' | 'f32' | 'bf16'.
+    """
+
+    def __init__(self, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0, n_tau, mode="f32", device=None):
+        import torch
+        L = lib()
+        self._keep = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (y, normal, dS, x_obs)]
+        yy, nn, ds, xx = self._keep
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        args = SetupArgs(yy.shape[0], xx.shape[0], int(n_tau), _dptr(yy), _dptr(nn), _dptr(ds), _dptr(xx),
+                         float(mach), float(aoa_deg), float(dtau), float(tau0), self.mode)
+        h = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(L.fwh_plan_create(ctypes.byref(args), ctypes.byref(h), ctypes.byref(nbytes)))
+        self._h = h
+        self.P, self.O, self.N = yy.shape[0], xx.shape[0], int(n_tau)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.setup()
+        self.out_dtype = torch.float64 if self.mode == MODE_F64 else torch.float32
+
+    def setup(self):
+        """(Re-)run the device setup: delays, observer window, pair tables."""
+        import torch
+        L = lib()
+        with torch.cuda.device(self.device):
+            _check(L.fwh_setup(self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        ts = np.empty(self.O)
+        nt = np.empty(self.O, dtype=np.int64)
+        ntm = ctypes.c_int64()
+        _check(L.fwh_obs_window(self._h, _dptr(ts), nt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                ctypes.byref(ntm)))
+        self.window = Window(ts, nt, int(ntm.value))
+
+    def profile(self, enable: bool = True):
+        """Bracket every stage of this plan with HIP events on its stream."""
+        _check(lib().fwh_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total_ms, launches)} of the events recorded since the last read."""
+        out = {}
+        for name, st in STAGES.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            _check(lib().fwh_profile_read(self._h, st, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, int(n.value))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fwh_destroy(h)
+            self._h = None
+
+    def _in_dtype(self, t):
+        import torch
+        if t.dtype == torch.float64:
+            return FWH_F64
+        if t.dtype == torch.float32:
+            return FWH_F32
+        raise TypeError(f"surface data must be float64 or float32, got {t.dtype}")
+
+    def _check_inputs(self, rho, u, pp):
+        for name, t, shape in (("rho", rho, (self.N, self.P)), ("u", u, (3, self.N, self.P)),
+                               ("p", pp, (self.N, self.P))):
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+            if not t.is_contiguous() or t.device != self.device:
+                raise ValueError(f"{name} must be contiguous on {self.device}")
+        if not (rho.dtype == u.dtype == pp.dtype):
+            raise TypeError("rho, u and p must have one dtype")
+
+    def forward(self, rho, u, pp, out=None):
+        """p'(o, k) as a [O, n_t_max] tensor (float64 in mode f64, float32 otherwise)."""
+        import torch
+        self._check_inputs(rho, u, pp)
+        if out is None:
+            out = torch.empty((self.O, self.window.n_t_max), dtype=self.out_dtype, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().fwh_forward(self._h, self._in_dtype(rho), ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(pp.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return out
+
+    def adjoint(self, rho, u, pp, grad_p, out=None):
+        """(dJ/drho, dJ/du, dJ/dp') for grad_p = dJ/dp' [O, n_t_max]."""
+        import torch
+        self._check_inputs(rho, u, pp)
+        grad_p = grad_p.to(self.out_dtype).contiguous()
+        if tuple(grad_p.shape) != (self.O, self.window.n_t_max):
+            raise ValueError(f"grad_p has shape {tuple(grad_p.shape)}, expected {(self.O, self.window.n_t_max)}")
+        if out is None:
+            out = (torch.empty_like(rho), torch.empty_like(u), torch.empty_like(pp))
+        g_r, g_u, g_p = out
+        with torch.cuda.device(self.device):
+            _check(lib().fwh_adjoint(self._h, self._in_dtype(rho), ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(pp.data_ptr()),
+                                     ctypes.c_void_p(grad_p.data_ptr()), ctypes.c_void_p(g_r.data_ptr()),
+                                     ctypes.c_void_p(g_u.data_ptr()), ctypes.c_void_p(g_p.data_ptr()),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return g_r, g_u, g_p
+
+
+def _autograd_function():
+    import torch
+
+    class FwhFunction(torch.autograd.Function):
+        """p' = FW-H(rho, u, p) on a set-up plan; backward runs the hand-written
+        transposed gather and source adjoint (fwh_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, plan, rho, u, pp):
+            ctx.plan = plan
+            ctx.save_for_backward(rho, u, pp)
+            return plan.forward(rho, u, pp)
+
+        @staticmethod
+        def backward(ctx, grad):
+            rho, u, pp = ctx.saved_tensors
+            g_r, g_u, g_p = ctx.plan.adjoint(rho, u, pp, grad.contiguous())
+            return None, g_r, g_u, g_p
+
+    return FwhFunction
+
+
+_fn = None
+
+
+def fwh_apply(plan: Plan, rho, u, pp):
+    """Differentiable forward: torch.autograd sees p' as a function of (rho, u, p)."""
+    global _fn
+    if _fn is None:
+        _fn = _autograd_function()
+    return _fn.apply(plan, rho, u, pp)
+
+
+def version() -> str:
+    return lib().fwh_version().decode()

@@ -1,0 +1,395 @@
+// Host side of the C ABI declared in include/fwh.h: argument validation,
+// workspace layout, the observer window (Eqs. (t_start), (t_end)) and the
+// launch sequence of setup, forward and adjoint.  No device memory is
+// allocated here: every device buffer, including the workspace, is the caller's.
+#include "../../include/fwh.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fwh_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct fwh_plan {
+    int64_t P = 0, O = 0, N = 0, NS = 0;
+    double mach = 0, aoa_deg = 0, dtau = 0, tau0 = 0;
+    int mode = 0;
+    fwh::Flow flow{};
+    std::vector<double> y, normal, dS, x_obs, cp;
+    // window (valid after setup)
+    std::vector<double> t_start;
+    std::vector<int64_t> n_t;
+    std::vector<int32_t> n_t32;
+    int64_t n_t_max = 0;
+    int splits = 1;
+    bool ready = false;
+    // workspace layout (byte offsets) and binding
+    size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
+    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_rec_po = 0;
+    size_t off_coef = 0, off_scr = 0, off_part = 0, ws_bytes = 0;
+    char *ws = nullptr;
+    // optional per-stage event timing
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[FWH_NUM_STAGES];
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+int layout(fwh_plan *pl) {
+    const size_t P = (size_t)pl->P, O = (size_t)pl->O, N = (size_t)pl->N, NS = (size_t)pl->NS;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    pl->off_y = take(P * 3 * sizeof(double));
+    pl->off_n = take(P * 3 * sizeof(double));
+    pl->off_dS = take(P * sizeof(double));
+    pl->off_x = take(O * 3 * sizeof(double));
+    pl->off_D = take(O * P * sizeof(double));
+    pl->off_dmm = take(O * 2 * sizeof(double));
+    pl->off_ts = take(O * sizeof(double));
+    pl->off_nt = take(O * sizeof(int32_t));
+    pl->off_cp = take(N * sizeof(double));
+    if (pl->mode == FWH_MODE_F64) {
+        pl->off_K64 = take(O * P * 8 * sizeof(double));
+        pl->off_W64 = take(O * P * 4 * sizeof(double));
+        pl->off_N0 = take(O * P * sizeof(int32_t));
+    } else {
+        pl->off_rec_op = take(O * P * sizeof(fwh::PairRec));
+        pl->off_rec_po = take(O * P * sizeof(fwh::PairRec));
+    }
+    // coefficient channels (forward) and coefficient adjoints (adjoint) share one region
+    const size_t real_sz = pl->mode == FWH_MODE_F64 ? sizeof(double) : sizeof(float);
+    pl->off_coef = take(8 * P * NS * real_sz);
+    // time-major scratch of the source stage, forward and adjoint
+    pl->off_scr = take(8 * N * P * real_sz);
+    if (pl->mode != FWH_MODE_F64) pl->off_part = take((size_t)fwh::kMaxPanelSplits * O * N * sizeof(double));
+    pl->ws_bytes = off;
+    return FWH_OK;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Brackets one stage with events when profiling is on.
+struct StageScope {
+    fwh_plan *pl;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageScope(fwh_plan *p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
+        if (pl->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+    }
+    ~StageScope() {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            pl->events[stage].emplace_back(a, b);
+        }
+    }
+};
+
+int hip_fail(const char *what, hipError_t e) {
+    return fail(FWH_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwh_plan_create(const fwh_setup_args *a, fwh_plan **out, size_t *workspace_bytes) {
+    g_last_error.clear();
+    if (out) *out = nullptr;
+    if (!a || !out) return fail(FWH_EINVAL, "fwh_plan_create: null argument");
+    if (a->n_panels < 1 || a->n_obs < 1 || a->n_tau < 4)
+        return fail(FWH_ESIZE, "fwh_plan_create: need n_panels >= 1, n_obs >= 1, n_tau >= 4 (got %lld, %lld, %lld)",
+                    (long long)a->n_panels, (long long)a->n_obs, (long long)a->n_tau);
+    if (a->n_tau > 65535 || a->n_panels > (int64_t)1 << 30 || a->n_obs > (int64_t)1 << 24 ||
+        a->n_panels * a->n_obs > (int64_t)1 << 36)
+        return fail(FWH_ESIZE, "fwh_plan_create: sizes beyond the supported range (n_tau <= 65535, P*O <= 2^36)");
+    if (!a->y || !a->normal || !a->dS || !a->x_obs) return fail(FWH_EINVAL, "fwh_plan_create: null geometry pointer");
+    if (a->mode != FWH_MODE_F64 && a->mode != FWH_MODE_F32 && a->mode != FWH_MODE_BF16)
+        return fail(FWH_EINVAL, "fwh_plan_create: unknown mode %d", (int)a->mode);
+    if (!(std::isfinite(a->mach) && a->mach > 0.0 && a->mach < 1.0))
+        return fail(FWH_EDOMAIN, "fwh_plan_create: Mach number must be in (0, 1), got %g", a->mach);
+    if (!(std::isfinite(a->dtau) && a->dtau > 0.0))
+        return fail(FWH_EDOMAIN, "fwh_plan_create: dtau must be positive, got %g", a->dtau);
+    if (!std::isfinite(a->tau0) || !std::isfinite(a->aoa_deg))
+        return fail(FWH_EINVAL, "fwh_plan_create: tau0 and aoa_deg must be finite");
+    for (int64_t p = 0; p < a->n_panels; ++p) {
+        const double *y = a->y + 3 * p, *n = a->normal + 3 * p;
+        if (!finite3(y) || !finite3(n) || !std::isfinite(a->dS[p]))
+            return fail(FWH_EINVAL, "fwh_plan_create: non-finite geometry at panel %lld", (long long)p);
+        if (!(a->dS[p] > 0.0)) return fail(FWH_EINVAL, "fwh_plan_create: dS must be > 0 (panel %lld)", (long long)p);
+        const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (std::fabs(nn - 1.0) > 1e-6)
+            return fail(FWH_EINVAL, "fwh_plan_create: normal of panel %lld is not unit (|n| = %g)", (long long)p, nn);
+    }
+    for (int64_t o = 0; o < a->n_obs; ++o)
+        if (!finite3(a->x_obs + 3 * o))
+            return fail(FWH_EINVAL, "fwh_plan_create: non-finite observer %lld", (long long)o);
+
+    fwh_plan *pl = new (std::nothrow) fwh_plan();
+    if (!pl) return fail(FWH_EINVAL, "fwh_plan_create: out of host memory");
+    pl->P = a->n_panels;
+    pl->O = a->n_obs;
+    pl->N = a->n_tau;
+    pl->NS = fwh::coef_row_stride(a->n_tau);
+    pl->mach = a->mach;
+    pl->aoa_deg = a->aoa_deg;
+    pl->dtau = a->dtau;
+    pl->tau0 = a->tau0;
+    pl->mode = a->mode;
+    const double aoa = a->aoa_deg * (kPi / 180.0);
+    pl->flow.M0 = a->mach;
+    pl->flow.ca = std::cos(aoa);
+    pl->flow.sa = std::sin(aoa);
+    pl->flow.beta2 = 1.0 - a->mach * a->mach;
+    pl->flow.dtau = a->dtau;
+    pl->flow.tau0 = a->tau0;
+    pl->y.assign(a->y, a->y + 3 * a->n_panels);
+    pl->normal.assign(a->normal, a->normal + 3 * a->n_panels);
+    pl->dS.assign(a->dS, a->dS + a->n_panels);
+    pl->x_obs.assign(a->x_obs, a->x_obs + 3 * a->n_obs);
+    // Thomas pivots of the constant (1, 4, 1) system of the spline prefilter
+    pl->cp.assign((size_t)a->n_tau, 0.0);
+    pl->cp[1] = 0.25;
+    for (int64_t r = 2; r < a->n_tau; ++r) pl->cp[r] = 1.0 / (4.0 - pl->cp[r - 1]);
+    layout(pl);
+    *out = pl;
+    if (workspace_bytes) *workspace_bytes = pl->ws_bytes;
+    return FWH_OK;
+}
+
+int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_setup: null plan");
+    if (!workspace) return fail(FWH_EWORKSPACE, "fwh_setup: null workspace");
+    if (workspace_bytes < pl->ws_bytes)
+        return fail(FWH_EWORKSPACE, "fwh_setup: workspace of %zu bytes, need %zu", workspace_bytes, pl->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(FWH_EWORKSPACE, "fwh_setup: workspace must be %zu-byte aligned", kAlign);
+    hipStream_t st = as_stream(stream_);
+    pl->ready = false;
+    pl->ws = static_cast<char *>(workspace);
+    const int64_t P = pl->P, O = pl->O, N = pl->N;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(pl->at<double>(pl->off_y), pl->y.data(), P * 3 * sizeof(double), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(pl->at<double>(pl->off_n), pl->normal.data(), P * 3 * sizeof(double), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(pl->at<double>(pl->off_dS), pl->dS.data(), P * sizeof(double), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(pl->at<double>(pl->off_x), pl->x_obs.data(), O * 3 * sizeof(double), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(pl->at<double>(pl->off_cp), pl->cp.data(), N * sizeof(double), hipMemcpyHostToDevice, st)))
+        return hip_fail("fwh_setup: copy of the geometry", e);
+    StageScope scope_a(pl, FWH_STAGE_SETUP, st);
+    if ((e = fwh::launch_delay(pl->at<double>(pl->off_y), pl->at<double>(pl->off_x), P, O, pl->flow,
+                               pl->at<double>(pl->off_D), st)))
+        return hip_fail("fwh_setup: delay kernel", e);
+    if ((e = fwh::launch_minmax(pl->at<double>(pl->off_D), P, O, pl->at<double>(pl->off_dmm), st)))
+        return hip_fail("fwh_setup: min/max kernel", e);
+    std::vector<double> dmm((size_t)(2 * O));
+    if ((e = hipMemcpyAsync(dmm.data(), pl->at<double>(pl->off_dmm), 2 * O * sizeof(double), hipMemcpyDeviceToHost, st)))
+        return hip_fail("fwh_setup: read-back of the delay extremes", e);
+    if ((e = hipStreamSynchronize(st))) return hip_fail("fwh_setup: stream synchronize", e);
+    // observer window, Eqs. (t_start), (t_end) per observer with a general tau0
+    pl->t_start.assign((size_t)O, 0.0);
+    pl->n_t.assign((size_t)O, 0);
+    pl->n_t32.assign((size_t)O, 0);
+    pl->n_t_max = 0;
+    for (int64_t o = 0; o < O; ++o) {
+        const double ts = pl->tau0 + dmm[2 * o];
+        const double te = pl->tau0 + (double)(N - 1) * pl->dtau + dmm[2 * o + 1];
+        pl->t_start[o] = ts;
+        if (!(te >= ts))
+            return fail(FWH_EWINDOW,
+                        "fwh_setup: observer %lld has an empty window (t_end %.17g < t_start %.17g): the record is "
+                        "shorter than the delay spread over the surface",
+                        (long long)o, te, ts);
+        const int64_t nt = (int64_t)std::floor((te - ts) / pl->dtau + 1e-9) + 1;
+        pl->n_t[o] = nt;
+        pl->n_t32[o] = (int32_t)nt;
+        if (nt > pl->n_t_max) pl->n_t_max = nt;
+    }
+    if ((e = hipMemcpyAsync(pl->at<double>(pl->off_ts), pl->t_start.data(), O * sizeof(double), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(pl->at<int32_t>(pl->off_nt), pl->n_t32.data(), O * sizeof(int32_t), hipMemcpyHostToDevice, st)))
+        return hip_fail("fwh_setup: copy of the window", e);
+    const bool f64 = pl->mode == FWH_MODE_F64;
+    StageScope scope_b(pl, FWH_STAGE_SETUP, st);
+    if ((e = fwh::launch_tables(f64 ? 0 : 1, pl->at<double>(pl->off_y), pl->at<double>(pl->off_dS),
+                                pl->at<double>(pl->off_x), pl->at<double>(pl->off_ts), pl->at<int32_t>(pl->off_nt), P,
+                                O, N, pl->flow, f64 ? pl->at<double>(pl->off_K64) : nullptr,
+                                f64 ? pl->at<double>(pl->off_W64) : nullptr, f64 ? pl->at<int32_t>(pl->off_N0) : nullptr,
+                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op),
+                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_po), st)))
+        return hip_fail("fwh_setup: table kernel", e);
+    // panel splits of the tuned gather: enough workgroups to fill 256 CUs a few times over
+    const int64_t blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
+                           ((pl->n_t_max + fwh::kGatherK - 1) / fwh::kGatherK);
+    int64_t s = (2048 + blocks - 1) / blocks;
+    if (s > fwh::kMaxPanelSplits) s = fwh::kMaxPanelSplits;
+    if (s > (P + 255) / 256) s = (P + 255) / 256;
+    if (s < 1) s = 1;
+    pl->splits = (int)s;
+    pl->ready = true;
+    return FWH_OK;
+}
+
+int fwh_obs_window(const fwh_plan *pl, double *t_start, int64_t *n_t, int64_t *n_t_max) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_obs_window: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_obs_window: plan is not set up");
+    if (t_start) std::memcpy(t_start, pl->t_start.data(), pl->O * sizeof(double));
+    if (n_t) std::memcpy(n_t, pl->n_t.data(), pl->O * sizeof(int64_t));
+    if (n_t_max) *n_t_max = pl->n_t_max;
+    return FWH_OK;
+}
+
+int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, const void *pp, void *p_out,
+                void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_forward: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_forward: plan is not set up");
+    if (!rho || !u || !pp || !p_out) return fail(FWH_EINVAL, "fwh_forward: null data pointer");
+    if (in_dtype != FWH_F64 && in_dtype != FWH_F32) return fail(FWH_EINVAL, "fwh_forward: bad in_dtype %d", in_dtype);
+    hipStream_t st = as_stream(stream_);
+    const int coef_type = pl->mode == FWH_MODE_F64 ? 0 : (pl->mode == FWH_MODE_F32 ? 1 : 2);
+    hipError_t e;
+    {
+        StageScope sc(pl, FWH_STAGE_SOURCE, st);
+        e = fwh::launch_source(in_dtype == FWH_F64 ? 0 : 1, coef_type, rho, u, pp, pl->at<double>(pl->off_n), pl->P,
+                               pl->N, pl->NS, pl->flow, pl->at<double>(pl->off_cp), pl->ws + pl->off_scr,
+                               pl->ws + pl->off_coef, st);
+    }
+    if (e) return hip_fail("fwh_forward: source kernel", e);
+    if (pl->mode == FWH_MODE_F64) {
+        StageScope sc(pl, FWH_STAGE_GATHER, st);
+        e = fwh::launch_gather_f64(pl->at<double>(pl->off_K64), pl->at<double>(pl->off_W64),
+                                   pl->at<int32_t>(pl->off_N0), pl->at<int32_t>(pl->off_nt),
+                                   pl->at<double>(pl->off_coef), pl->P, pl->O, pl->NS, pl->n_t_max,
+                                   static_cast<double *>(p_out), st);
+    } else {
+        {
+            StageScope sc(pl, FWH_STAGE_GATHER, st);
+            e = fwh::launch_gather_tuned(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
+                                         pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
+                                         pl->at<double>(pl->off_part), st);
+        }
+        if (!e) {
+            StageScope sc(pl, FWH_STAGE_REDUCE, st);
+            e = fwh::launch_reduce_splits(pl->at<double>(pl->off_part), pl->splits, pl->O * pl->n_t_max,
+                                          static_cast<float *>(p_out), st);
+        }
+    }
+    if (e) return hip_fail("fwh_forward: gather kernel", e);
+    return FWH_OK;
+}
+
+int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, const void *pp, const void *grad_p,
+                void *g_rho, void *g_u, void *g_p, void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_adjoint: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_adjoint: plan is not set up");
+    if (!rho || !u || !pp || !grad_p || !g_rho || !g_u || !g_p)
+        return fail(FWH_EINVAL, "fwh_adjoint: null data pointer");
+    if (in_dtype != FWH_F64 && in_dtype != FWH_F32) return fail(FWH_EINVAL, "fwh_adjoint: bad in_dtype %d", in_dtype);
+    hipStream_t st = as_stream(stream_);
+    hipError_t e;
+    const bool f64 = pl->mode == FWH_MODE_F64;
+    {
+    StageScope sc(pl, FWH_STAGE_ADJ_GATHER, st);
+    if (f64)
+        e = fwh::launch_adj_gather_f64(pl->at<double>(pl->off_K64), pl->at<double>(pl->off_W64),
+                                       pl->at<int32_t>(pl->off_N0), pl->at<int32_t>(pl->off_nt),
+                                       static_cast<const double *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
+                                       pl->at<double>(pl->off_coef), st);
+    else
+        e = fwh::launch_adj_gather_tuned(pl->at<fwh::PairRec>(pl->off_rec_po), pl->at<int32_t>(pl->off_nt),
+                                         static_cast<const float *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
+                                         pl->at<float>(pl->off_coef), st);
+    }
+    if (e) return hip_fail("fwh_adjoint: transposed gather", e);
+    {
+        StageScope sc(pl, FWH_STAGE_SOURCE_ADJ, st);
+        e = fwh::launch_source_adjoint(f64 ? 0 : 1, in_dtype == FWH_F64 ? 0 : 1, pl->ws + pl->off_coef, rho, u,
+                                       pl->at<double>(pl->off_n), pl->P, pl->N, pl->NS, pl->flow,
+                                       pl->at<double>(pl->off_cp), pl->ws + pl->off_scr, g_rho, g_u, g_p, st);
+    }
+    if (e) return hip_fail("fwh_adjoint: source adjoint", e);
+    (void)pp;
+    return FWH_OK;
+}
+
+int fwh_profile_enable(fwh_plan *pl, int enable) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_profile_enable: null plan");
+    pl->profiling = enable != 0;
+    return FWH_OK;
+}
+
+int fwh_profile_read(fwh_plan *pl, int32_t stage, double *total_ms, int64_t *launches) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_profile_read: null plan");
+    if (stage < 0 || stage >= FWH_NUM_STAGES) return fail(FWH_EINVAL, "fwh_profile_read: bad stage %d", stage);
+    double sum = 0.0;
+    int64_t n = 0;
+    int status = FWH_OK;
+    for (auto &ab : pl->events[stage]) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(ab.second);
+        if (!e) e = hipEventElapsedTime(&ms, ab.first, ab.second);
+        if (e && status == FWH_OK) status = hip_fail("fwh_profile_read", e);
+        sum += ms;
+        ++n;
+        (void)hipEventDestroy(ab.first);
+        (void)hipEventDestroy(ab.second);
+    }
+    pl->events[stage].clear();
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = n;
+    return status;
+}
+
+void fwh_destroy(fwh_plan *pl) {
+    if (!pl) return;
+    for (auto &v : pl->events)
+        for (auto &ab : v) {
+            (void)hipEventDestroy(ab.first);
+            (void)hipEventDestroy(ab.second);
+        }
+    delete pl;
+}
+
+const char *fwh_last_error(void) { return g_last_error.c_str(); }
+
+const char *fwh_version(void) { return "fwh-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

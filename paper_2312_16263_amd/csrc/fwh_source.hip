@@ -1,0 +1,367 @@
+// Source stage (gfx950): per panel and source frame, the source terms of
+// Eqs. (Qn_New_nd), (Li_New_nd); their 2nd-order source-time derivatives
+// (one-sided at the first and last frame, central elsewhere; Sec. III B); and the
+// B-spline coefficients of the natural cubic spline through each of the 8
+// resulting series (the observer-independent half of the "interp pressure
+// signal" step).  Plus the exact transpose of this stage for the adjoint.
+//
+// The natural cubic spline through f_0..f_{N-1} is sum_n c_n B((tau - tau_n)/dtau)
+// with B the uniform cubic B-spline; natural end conditions give c_0 = f_0,
+// c_{N-1} = f_{N-1}, c_{-1} = 2c_0 - c_1, c_N = 2c_{N-1} - c_{N-2} and, inside,
+// (c_{n-1} + 4 c_n + c_{n+1})/6 = f_n, a constant tridiagonal system solved by
+// the Thomas algorithm with the precomputed pivots cp[r] (cp[1] = 1/4,
+// cp[r] = 1/(4 - cp[r-1])).
+//
+// Layout: one thread per (panel, channel), a wave = 64 consecutive panels of one
+// channel, so every time step is one coalesced load per input variable.  The
+// forward elimination streams the inputs in time order and writes the reduced
+// right-hand sides to a time-major scratch [8][N][P]; back substitution runs in
+// reverse time order and the coefficients go out panel-major [8][P][NS]
+// (time-contiguous rows) through a per-wave LDS transpose.  All arithmetic FP64.
+#include "fwh_internal.h"
+
+namespace fwh {
+namespace {
+
+struct bf16s {
+    uint16_t bits;
+};
+
+template <typename T>
+struct Store;
+template <>
+struct Store<double> {
+    static __device__ __forceinline__ double put(double v) { return v; }
+};
+template <>
+struct Store<float> {
+    static __device__ __forceinline__ float put(double v) { return (float)v; }
+};
+template <>
+struct Store<bf16s> {
+    // double -> float (round to nearest even) -> bfloat16 (round to nearest even)
+    static __device__ __forceinline__ bf16s put(double v) {
+        const float x = (float)v;
+        uint32_t u = __float_as_uint(x);
+        bf16s r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            r.bits = (uint16_t)((u >> 16) | 0x40u);
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            r.bits = (uint16_t)(u >> 16);
+        }
+        return r;
+    }
+};
+
+// Channel c: base quantity (0 = Q, 1..3 = L_i) and whether it is the derivative.
+__device__ __forceinline__ int channel_base(int c) { return c <= 1 ? 0 : (c <= 4 ? c - 1 : c - 4); }
+__device__ __forceinline__ bool channel_deriv(int c) { return c == 0 || (c >= 2 && c <= 4); }
+
+struct PanelFrame {
+    double nx, ny, nz, U0n;
+};
+
+// Source term of the given base at time-major index idx (Eqs. (Qn_New_nd), (Li_New_nd)):
+//   Q = rho u.n - U0.n,  L_i = p' n_i + rho (u_i - U0_i) u.n
+template <typename TIn>
+__device__ __forceinline__ double source_term(int base, const TIn *__restrict__ rho, const TIn *__restrict__ u,
+                                              const TIn *__restrict__ pp, int64_t idx, int64_t NP,
+                                              const PanelFrame &pf, const Flow &f) {
+    const double r = (double)rho[idx];
+    const double u1 = (double)u[idx], u2 = (double)u[NP + idx], u3 = (double)u[2 * NP + idx];
+    const double un = u1 * pf.nx + u2 * pf.ny + u3 * pf.nz;
+    if (base == 0) return r * un - pf.U0n;
+    const double pv = (double)pp[idx];
+    if (base == 1) return pv * pf.nx + r * (u1 - f.ca) * un;
+    if (base == 2) return pv * pf.ny + r * (u2 - f.sa) * un;
+    return pv * pf.nz + r * u3 * un;
+}
+
+template <typename TIn, typename TScr, typename TOut>
+__global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__ rho, const TIn *__restrict__ u,
+                                                         const TIn *__restrict__ pp,
+                                                         const double *__restrict__ normal, int64_t P, int64_t N,
+                                                         int64_t NS, Flow f, const double *__restrict__ cp,
+                                                         TScr *__restrict__ scr, TOut *__restrict__ coef) {
+    constexpr int CH = 128 / (int)sizeof(TOut);  // coefficients per flushed row segment (128 bytes)
+    constexpr int PF = 8;                        // time steps loaded ahead
+    __shared__ TOut stage[4][64][CH + 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int ch = blockIdx.y * 4 + wv;
+    const int base = channel_base(ch);
+    const bool deriv = channel_deriv(ch);
+    const int64_t pbase = (int64_t)blockIdx.x * 64;
+    const int64_t p = pbase + lane;
+    const bool active = p < P;
+    const int64_t pc = active ? p : P - 1;
+    const int64_t NP = N * P;
+    PanelFrame pf;
+    pf.nx = normal[3 * pc];
+    pf.ny = normal[3 * pc + 1];
+    pf.nz = normal[3 * pc + 2];
+    pf.U0n = f.ca * pf.nx + f.sa * pf.ny;
+    const double i2h = 1.0 / (2.0 * f.dtau);
+
+    auto X = [&](int64_t n) { return source_term<TIn>(base, rho, u, pp, n * P + pc, NP, pf, f); };
+
+    // ---- forward sweep: f_n for n = 0..N-1, Thomas row r = n-1 once f_n is known
+    const double X0 = X(0), X1 = X(1), X2 = X(2);
+    const double f0 = deriv ? (-3.0 * X0 + 4.0 * X1 - X2) * i2h : X0;
+    double Xmm = 0.0, Xm = X0, Xc = X1, Xp = X2;
+    double fprev = f0, fN1 = 0.0, dprev = 0.0;
+    TScr *scr_ch = scr + (int64_t)ch * NP;
+    for (int64_t nb = 1; nb < N; nb += PF) {
+        double Xf[PF];
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int64_t n2 = nb + i + 2;
+            Xf[i] = (n2 < N) ? X(n2) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int64_t n = nb + i;
+            if (n < N) {
+                double fn;
+                if (n < N - 1) fn = deriv ? (Xp - Xm) * i2h : Xc;
+                else fn = deriv ? (3.0 * Xc - 4.0 * Xm + Xmm) * i2h : Xc;
+                const int64_t r = n - 1;
+                if (r >= 1) {
+                    double rhs = 6.0 * fprev;
+                    if (r == 1) rhs -= f0;
+                    if (r == N - 2) rhs -= fn;
+                    const double d = (rhs - dprev) * cp[r];
+                    if (active) scr_ch[r * P + p] = (TScr)d;
+                    dprev = d;
+                }
+                if (n == N - 1) fN1 = fn;
+                fprev = fn;
+                Xmm = Xm;
+                Xm = Xc;
+                Xc = Xp;
+                Xp = Xf[i];
+            }
+        }
+    }
+
+    // ---- back substitution in reverse order, coefficients by storage index i:
+    // i = 0: c_{-1}; i = n+1: c_n (n = 0..N-1); i = N+1: c_N; i >= N+2: 0.
+    const double xN2 = dprev;  // x_{N-2} = d'_{N-2}
+    double x = xN2;            // x_{n+1} of the recurrence
+    TOut *coef_ch = coef + (int64_t)ch * P * NS;
+    constexpr int SB = CH < 16 ? CH : 16;  // back-substitution steps loaded ahead
+    for (int64_t b = NS / CH - 1; b >= 0; --b) {
+        const int64_t i0 = b * CH;
+        for (int sb = CH - SB; sb >= 0; sb -= SB) {
+            double dpre[SB];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                const int64_t n = i0 + sb + q - 1;
+                dpre[q] = (n >= 1 && n <= N - 3 && active) ? (double)scr_ch[n * P + p] : 0.0;
+            }
+#pragma unroll
+            for (int q = SB - 1; q >= 0; --q) {
+                const int64_t i = i0 + sb + q;
+                double v;
+                if (i >= N + 2) v = 0.0;
+                else if (i == N + 1) v = 2.0 * fN1 - xN2;
+                else if (i == N) v = fN1;
+                else if (i >= 2) {
+                    const int64_t n = i - 1;
+                    if (n <= N - 3) x = dpre[q] - cp[n] * x;
+                    v = x;
+                } else if (i == 1) v = f0;
+                else v = 2.0 * f0 - x;
+                stage[wv][lane][sb + q] = Store<TOut>::put(v);
+            }
+        }
+        __syncthreads();
+        for (int t = lane; t < 64 * CH; t += 64) {
+            const int r = t / CH, col = t - r * CH;
+            const int64_t prow = pbase + r;
+            if (prow < P) coef_ch[prow * NS + i0 + col] = stage[wv][r][col];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// Transpose of the prefilter for one (panel, channel): coefficient adjoints
+// a_{-1..N} (storage indices 0..N+1) -> adjoints of the channel values f_0..f_{N-1}:
+//   end rows: a_0 += 2 a_{-1}, a_1 -= a_{-1}, a_{N-1} += 2 a_N, a_{N-2} -= a_N;
+//   interior: z = T^{-1} a_{1..N-2} (T = tridiag(1,4,1), symmetric);
+//   fbar_r = 6 z_r (r = 1..N-2), fbar_0 = a_0 - z_1, fbar_{N-1} = a_{N-1} - z_{N-2}.
+// Result written time-major into scr [8][N][P].
+template <typename TR>
+__global__ __launch_bounds__(256) void prefilter_adj_kernel(const TR *__restrict__ cbar, int64_t P, int64_t N,
+                                                            int64_t NS, const double *__restrict__ cp,
+                                                            TR *__restrict__ scr) {
+    constexpr int CH = 128 / (int)sizeof(TR);
+    constexpr int PF = 8;
+    __shared__ TR stage[4][64][CH + 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int ch = blockIdx.y * 4 + wv;
+    const int64_t pbase = (int64_t)blockIdx.x * 64;
+    const int64_t p = pbase + lane;
+    const bool active = p < P;
+    const int64_t pc = active ? p : P - 1;
+    const TR *row = cbar + ((int64_t)ch * P + pc) * NS;
+    const TR *cbar_ch = cbar + (int64_t)ch * P * NS;
+    const double am1 = (double)row[0];
+    const double aN = (double)row[N + 1];
+    double a0 = 0.0, aN1 = 0.0, dprev = 0.0;
+    TR *scr_ch = scr + (int64_t)ch * N * P;
+    // forward elimination over rows r = 1..N-2 (storage index r+1), streaming the row through LDS
+    const int64_t nblk = (N + CH - 1) / CH;  // storage indices 0..N cover a_{-1}..a_{N-1}
+    for (int64_t b = 0; b < nblk + 1; ++b) {
+        const int64_t i0 = b * CH;
+        __syncthreads();
+        for (int t = lane; t < 64 * CH; t += 64) {
+            const int r = t / CH, col = t - r * CH;
+            const int64_t prow = pbase + r;
+            stage[wv][r][col] = (prow < P && i0 + col < NS) ? cbar_ch[prow * NS + i0 + col] : (TR)0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < CH; ++q) {
+            const int64_t i = i0 + q;
+            const int64_t r = i - 1;  // coefficient index
+            double a = (double)stage[wv][lane][q];
+            if (r == 0) a0 = a + 2.0 * am1;
+            if (r == N - 1) aN1 = a + 2.0 * aN;
+            if (r >= 1 && r <= N - 2) {
+                if (r == 1) a -= am1;
+                if (r == N - 2) a -= aN;
+                const double d = (a - dprev) * cp[r];
+                if (active) scr_ch[r * P + p] = (TR)d;
+                dprev = d;
+            }
+        }
+    }
+    // back substitution, fbar written in place
+    double z = dprev;  // z_{N-2}
+    const double zN2 = z;
+    if (active) scr_ch[(N - 2) * P + p] = (TR)(6.0 * zN2);
+    for (int64_t rb = N - 3; rb >= 1; rb -= PF) {
+        double dpre[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int64_t r = rb - q;
+            dpre[q] = (r >= 1 && active) ? (double)scr_ch[r * P + p] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int64_t r = rb - q;
+            if (r >= 1) {
+                z = dpre[q] - cp[r] * z;
+                if (active) scr_ch[r * P + p] = (TR)(6.0 * z);
+            }
+        }
+    }
+    const double z1 = (N - 2 >= 1) ? z : 0.0;  // after the loop z = z_1
+    if (active) {
+        scr_ch[p] = (TR)(a0 - z1);
+        scr_ch[(N - 1) * P + p] = (TR)(aN1 - zN2);
+    }
+}
+
+// Per (frame n, panel p): source-term adjoints
+//   Qbar = fbar_Q + D^T fbar_Qdot,  Lbar_i = fbar_Li + D^T fbar_Ldot_i
+// (D the derivative matrix: central rows 1..N-2, one-sided rows 0 and N-1), then the
+// chain rule through Q = rho u.n - U0.n and L_i = p' n_i + rho (u_i - U0_i) u.n:
+//   drho = u.n (Qbar + Lbar.w),  du = rho n (Qbar + Lbar.w) + rho u.n Lbar,
+//   dp' = Lbar.n,  with w = u - U0.
+template <typename TR, typename TIn>
+__global__ __launch_bounds__(256) void source_adj_chain_kernel(const TR *__restrict__ scr,
+                                                               const TIn *__restrict__ rho,
+                                                               const TIn *__restrict__ u,
+                                                               const double *__restrict__ normal, int64_t P,
+                                                               int64_t N, Flow f, TIn *__restrict__ g_rho,
+                                                               TIn *__restrict__ g_u, TIn *__restrict__ g_p) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = blockIdx.y;
+    if (p >= P) return;
+    const int64_t NP = N * P;
+    const double i2h = 1.0 / (2.0 * f.dtau);
+    auto S = [&](int c, int64_t m) { return (double)scr[(int64_t)c * NP + m * P + p]; };
+    auto DT = [&](int c) {  // (D^T v)_n for channel c
+        double s = 0.0;
+        if (n - 1 >= 1 && n - 1 <= N - 2) s += S(c, n - 1);
+        if (n + 1 >= 1 && n + 1 <= N - 2) s -= S(c, n + 1);
+        if (n <= 2) s += (n == 0 ? -3.0 : (n == 1 ? 4.0 : -1.0)) * S(c, 0);
+        if (n >= N - 3) s += (n == N - 1 ? 3.0 : (n == N - 2 ? -4.0 : 1.0)) * S(c, N - 1);
+        return s * i2h;
+    };
+    const double Qb = S(1, n) + DT(0);
+    double Lb[3];
+    for (int i = 0; i < 3; ++i) Lb[i] = S(5 + i, n) + DT(2 + i);
+    const double nx = normal[3 * p], ny = normal[3 * p + 1], nz = normal[3 * p + 2];
+    const int64_t idx = n * P + p;
+    const double r = (double)rho[idx];
+    const double u1 = (double)u[idx], u2 = (double)u[NP + idx], u3 = (double)u[2 * NP + idx];
+    const double un = u1 * nx + u2 * ny + u3 * nz;
+    const double Lw = Lb[0] * (u1 - f.ca) + Lb[1] * (u2 - f.sa) + Lb[2] * u3;
+    const double q = Qb + Lw;
+    g_rho[idx] = (TIn)(un * q);
+    g_u[idx] = (TIn)(r * nx * q + r * un * Lb[0]);
+    g_u[NP + idx] = (TIn)(r * ny * q + r * un * Lb[1]);
+    g_u[2 * NP + idx] = (TIn)(r * nz * q + r * un * Lb[2]);
+    g_p[idx] = (TIn)(Lb[0] * nx + Lb[1] * ny + Lb[2] * nz);
+}
+
+template <typename TIn, typename TScr, typename TOut>
+hipError_t source_launch_t(const void *rho, const void *u, const void *pp, const double *normal, int64_t P, int64_t N,
+                           int64_t NS, Flow f, const double *cp, void *scratch, void *coef, hipStream_t stream) {
+    dim3 grid((unsigned)((P + 63) / 64), 2);
+    source_fwd_kernel<TIn, TScr, TOut><<<grid, dim3(256), 0, stream>>>(
+        (const TIn *)rho, (const TIn *)u, (const TIn *)pp, normal, P, N, NS, f, cp, (TScr *)scratch, (TOut *)coef);
+    return hipGetLastError();
+}
+
+template <typename TR, typename TIn>
+hipError_t source_adj_launch_t(const void *cbar, const void *rho, const void *u, const double *normal, int64_t P,
+                               int64_t N, int64_t NS, Flow f, const double *cp, void *scratch, void *g_rho, void *g_u,
+                               void *g_p, hipStream_t stream) {
+    dim3 grid1((unsigned)((P + 63) / 64), 2);
+    prefilter_adj_kernel<TR><<<grid1, dim3(256), 0, stream>>>((const TR *)cbar, P, N, NS, cp, (TR *)scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 grid2((unsigned)((P + 255) / 256), (unsigned)N);
+    source_adj_chain_kernel<TR, TIn><<<grid2, dim3(256), 0, stream>>>((const TR *)scratch, (const TIn *)rho,
+                                                                      (const TIn *)u, normal, P, N, f, (TIn *)g_rho,
+                                                                      (TIn *)g_u, (TIn *)g_p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_source(int in_dtype, int coef_type, const void *rho, const void *u, const void *pp,
+                         const double *normal, int64_t P, int64_t N, int64_t NS, Flow f, const double *cp,
+                         void *scratch, void *coef, hipStream_t stream) {
+    if (in_dtype == 0) {
+        if (coef_type == 0) return source_launch_t<double, double, double>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+        if (coef_type == 1) return source_launch_t<double, float, float>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+        return source_launch_t<double, float, bf16s>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+    }
+    if (coef_type == 0) return source_launch_t<float, double, double>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+    if (coef_type == 1) return source_launch_t<float, float, float>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+    return source_launch_t<float, float, bf16s>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+}
+
+hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, const void *rho, const void *u,
+                                 const double *normal, int64_t P, int64_t N, int64_t NS, Flow f, const double *cp,
+                                 void *scratch, void *g_rho, void *g_u, void *g_p, hipStream_t stream) {
+    if (real_type == 0) {
+        if (in_dtype == 0)
+            return source_adj_launch_t<double, double>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+        return source_adj_launch_t<double, float>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+    }
+    if (in_dtype == 0)
+        return source_adj_launch_t<float, double>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+    return source_adj_launch_t<float, float>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+}
+
+}  // namespace fwh

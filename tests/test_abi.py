@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/fwh.h declares, and fwh_plan_create / fwh_setup /
+fwh_forward reject bad arguments with the documented codes before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2312_16263_amd as fwh
+from workloads import surfaces
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fwh.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(fwh_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = fwh.lib()
+    names = header_functions()
+    assert set(names) == set(fwh.EXPORTED), names
+    for n in names:
+        assert hasattr(L, n), n
+    assert "gfx950" in fwh.version()
+
+
+def _args(**kw):
+    s = surfaces.sphere(1.0, 4, 8)
+    x = surfaces.observer_circle(3, 10.0)
+    d = dict(y=s.y, normal=s.normal, dS=s.dS, x_obs=x, mach=0.3, aoa_deg=5.0, dtau=0.01, tau0=0.0, n_tau=64,
+             mode=fwh.MODE_F32)
+    d.update(kw)
+    keep = [np.ascontiguousarray(np.asarray(d[k], dtype=np.float64)) for k in ("y", "normal", "dS", "x_obs")]
+    a = fwh.SetupArgs(keep[0].shape[0], keep[3].shape[0], d["n_tau"], fwh._dptr(keep[0]), fwh._dptr(keep[1]),
+                      fwh._dptr(keep[2]), fwh._dptr(keep[3]), d["mach"], d["aoa_deg"], d["dtau"], d["tau0"], d["mode"])
+    return a, keep
+
+
+def _create(a):
+    h = ctypes.c_void_p()
+    nb = ctypes.c_size_t()
+    code = fwh.lib().fwh_plan_create(ctypes.byref(a), ctypes.byref(h), ctypes.byref(nb))
+    return code, h, nb.value
+
+
+@pytest.mark.parametrize("mode", [fwh.MODE_F64, fwh.MODE_F32, fwh.MODE_BF16])
+def test_plan_create_reports_workspace(mode):
+    a, keep = _args(mode=mode)
+    code, h, nb = _create(a)
+    assert code == fwh.FWH_OK
+    assert nb > 0 and nb % 256 == 0
+    fwh.lib().fwh_destroy(h)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(mach=0.0), fwh.FWH_EDOMAIN), (dict(mach=1.0), fwh.FWH_EDOMAIN), (dict(mach=float("nan")), fwh.FWH_EDOMAIN),
+    (dict(dtau=0.0), fwh.FWH_EDOMAIN), (dict(dtau=-1.0), fwh.FWH_EDOMAIN),
+    (dict(n_tau=3), fwh.FWH_ESIZE), (dict(n_tau=70000), fwh.FWH_ESIZE),
+    (dict(mode=7), fwh.FWH_EINVAL), (dict(aoa_deg=float("inf")), fwh.FWH_EINVAL),
+])
+def test_plan_create_rejects(kw, code):
+    a, keep = _args(**kw)
+    c, h, nb = _create(a)
+    assert c == code
+    assert not h.value
+    assert len(fwh.lib().fwh_last_error()) > 0
+
+
+def test_plan_create_rejects_bad_geometry():
+    s = surfaces.sphere(1.0, 4, 8)
+    dS = s.dS.copy()
+    dS[3] = 0.0
+    a, keep = _args(dS=dS)
+    assert _create(a)[0] == fwh.FWH_EINVAL
+    n = s.normal.copy()
+    n[2] *= 1.5
+    a, keep = _args(normal=n)
+    assert _create(a)[0] == fwh.FWH_EINVAL
+    y = s.y.copy()
+    y[0, 1] = np.nan
+    a, keep = _args(y=y)
+    assert _create(a)[0] == fwh.FWH_EINVAL
+    assert fwh.lib().fwh_plan_create(None, None, None) == fwh.FWH_EINVAL
+
+
+def test_setup_and_forward_state_checks():
+    a, keep = _args()
+    code, h, nb = _create(a)
+    assert code == fwh.FWH_OK
+    L = fwh.lib()
+    assert L.fwh_setup(h, None, nb, None) == fwh.FWH_EWORKSPACE
+    assert L.fwh_setup(h, ctypes.c_void_p(256), nb - 1, None) == fwh.FWH_EWORKSPACE
+    assert L.fwh_setup(h, ctypes.c_void_p(257), nb, None) == fwh.FWH_EWORKSPACE
+    dummy = ctypes.c_void_p(1 << 20)
+    assert L.fwh_forward(h, fwh.FWH_F64, dummy, dummy, dummy, dummy, None) == fwh.FWH_ESTATE
+    assert L.fwh_adjoint(h, fwh.FWH_F64, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None) == fwh.FWH_ESTATE
+    assert L.fwh_obs_window(h, None, None, None) == fwh.FWH_ESTATE
+    assert b"not set up" in L.fwh_last_error()
+    L.fwh_destroy(h)
