@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -46,11 +47,12 @@ struct fwh_plan {
     std::vector<int32_t> n_t32;
     int64_t n_t_max = 0;
     int splits = 1;
+    int lds_nw = 0, lds_pt = 0;  // staged window length and panels per stage of the LDS gather (0: not usable)
     bool ready = false;
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
-    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_rec_po = 0;
-    size_t off_coef = 0, off_scr = 0, off_part = 0, ws_bytes = 0;
+    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_rec_po = 0, off_tw = 0, off_wblk = 0;
+    size_t off_coef = 0, off_scr = 0, off_part = 0, off_gpad = 0, ws_bytes = 0;
     char *ws = nullptr;
     // optional per-stage event timing
     bool profiling = false;
@@ -88,13 +90,18 @@ int layout(fwh_plan *pl) {
     } else {
         pl->off_rec_op = take(O * P * sizeof(fwh::PairRec));
         pl->off_rec_po = take(O * P * sizeof(fwh::PairRec));
+        pl->off_tw = take((O + fwh::kObsTile - 1) / fwh::kObsTile * P * sizeof(int2));
+        pl->off_wblk = take((size_t)fwh::tile_window_blocks(pl->P, pl->O) * sizeof(int32_t));
     }
     // coefficient channels (forward) and coefficient adjoints (adjoint) share one region
     const size_t real_sz = pl->mode == FWH_MODE_F64 ? sizeof(double) : sizeof(float);
     pl->off_coef = take(8 * P * NS * real_sz);
     // time-major scratch of the source stage, forward and adjoint
     pl->off_scr = take(8 * N * P * real_sz);
-    if (pl->mode != FWH_MODE_F64) pl->off_part = take((size_t)fwh::kMaxPanelSplits * O * N * sizeof(double));
+    if (pl->mode != FWH_MODE_F64) {
+        pl->off_part = take((size_t)fwh::kMaxPanelSplits * O * N * sizeof(double));
+        pl->off_gpad = take((size_t)O * fwh::adj_pad_row(pl->N, pl->NS) * sizeof(float));
+    }
     pl->ws_bytes = off;
     return FWH_OK;
 }
@@ -251,9 +258,38 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
                                 f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op),
                                 f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_po), st)))
         return hip_fail("fwh_setup: table kernel", e);
-    // panel splits of the tuned gather: enough workgroups to fill 256 CUs a few times over
-    const int64_t blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
-                           ((pl->n_t_max + fwh::kGatherK - 1) / fwh::kGatherK);
+    if (!f64) {
+        // per (observer tile, panel) windows of n0 and their largest width -> LDS staging geometry
+        if ((e = fwh::launch_tile_window(pl->at<fwh::PairRec>(pl->off_rec_op), P, O, pl->at<int2>(pl->off_tw),
+                                         pl->at<int32_t>(pl->off_wblk), st)))
+            return hip_fail("fwh_setup: tile window kernel", e);
+        const int64_t nb = fwh::tile_window_blocks(P, O);
+        std::vector<int32_t> wblk((size_t)nb);
+        if ((e = hipMemcpyAsync(wblk.data(), pl->at<int32_t>(pl->off_wblk), nb * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st)) ||
+            (e = hipStreamSynchronize(st)))
+            return hip_fail("fwh_setup: read-back of the tile windows", e);
+        int wmax = 0;
+        for (int32_t w : wblk) wmax = w > wmax ? w : wmax;
+        const size_t esz = pl->mode == FWH_MODE_F32 ? sizeof(float) : sizeof(uint16_t);
+        // window length per channel group: a multiple of 64 elements (whole wave-wide direct loads)
+        const int nw = ((wmax + fwh::kLdsK + fwh::kLdsHalo + 63) / 64) * 64;
+        // two stage buffers of PT panels: windows of both groups plus the tile's pair records
+        int64_t pt = (int64_t)(fwh::kLdsBudget /
+                               (2 * ((size_t)8 * nw * esz + fwh::kObsTile * sizeof(fwh::PairRec))));
+        if (pt > fwh::kMaxPanelsPerStage) pt = fwh::kMaxPanelsPerStage;
+        pl->lds_nw = nw;
+        pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit: the direct-load gather is used
+        const char *force = std::getenv("FWH_FORCE_DIRECT_GATHER");  // test hook: exercise the direct-load gather
+        if (force && force[0] == '1') pl->lds_pt = 0;
+    }
+    // panel splits of the tuned gathers: enough workgroups to fill 256 CUs a few times over
+    int64_t blocks;
+    if (pl->lds_pt > 0)
+        blocks = ((O + fwh::kObsTile - 1) / fwh::kObsTile) * ((pl->n_t_max + fwh::kLdsK - 1) / fwh::kLdsK);
+    else
+        blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
+                 ((pl->n_t_max + fwh::kGatherK - 1) / fwh::kGatherK);
     int64_t s = (2048 + blocks - 1) / blocks;
     if (s > fwh::kMaxPanelSplits) s = fwh::kMaxPanelSplits;
     if (s > (P + 255) / 256) s = (P + 255) / 256;
@@ -299,9 +335,15 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
     } else {
         {
             StageScope sc(pl, FWH_STAGE_GATHER, st);
-            e = fwh::launch_gather_tuned(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
-                                         pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
-                                         pl->at<double>(pl->off_part), st);
+            if (pl->lds_pt > 0)
+                e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int2>(pl->off_tw),
+                                           pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O, pl->NS,
+                                           pl->n_t_max, pl->splits, pl->lds_nw, pl->lds_pt,
+                                           pl->at<double>(pl->off_part), st);
+            else
+                e = fwh::launch_gather_tuned(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op),
+                                             pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O,
+                                             pl->NS, pl->n_t_max, pl->splits, pl->at<double>(pl->off_part), st);
         }
         if (!e) {
             StageScope sc(pl, FWH_STAGE_REDUCE, st);
@@ -332,9 +374,9 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
                                        static_cast<const double *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
                                        pl->at<double>(pl->off_coef), st);
     else
-        e = fwh::launch_adj_gather_tuned(pl->at<fwh::PairRec>(pl->off_rec_po), pl->at<int32_t>(pl->off_nt),
-                                         static_cast<const float *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
-                                         pl->at<float>(pl->off_coef), st);
+        e = fwh::launch_adj_gather_dpp(pl->at<fwh::PairRec>(pl->off_rec_po), pl->at<int32_t>(pl->off_nt),
+                                       static_cast<const float *>(grad_p), pl->P, pl->O, pl->N, pl->NS, pl->n_t_max,
+                                       pl->at<float>(pl->off_gpad), pl->at<float>(pl->off_coef), st);
     }
     if (e) return hip_fail("fwh_adjoint: transposed gather", e);
     {

@@ -1,6 +1,9 @@
 // Gather kernels (gfx950): the surface sum of Sec. III C as a fixed
 // fractional-delay gather, and its transpose for the adjoint.
 //
+// Coefficients are stored panel-major with the 4 channels of each of the two
+// channel groups interleaved: coef[P][2][NS][4] (channel c = 4 g + cc).
+//
 // After the setup every (observer o, panel p) pair has a fixed delay index
 // s0 = n0 + frac, fixed cubic B-spline taps w_0..w_3 (acting on spline
 // coefficients c[n0+k-1 .. n0+k+2], storage indices n0+k .. n0+k+3) and fixed
@@ -39,7 +42,7 @@ __global__ __launch_bounds__(256) void gather_f64_kernel(const double *__restric
         double s = 0.0;
         for (int jj = 0; jj < 4; ++jj) {
             double g = 0.0;
-            for (int c = 0; c < 8; ++c) g += K64[pr * 8 + c] * coef[((int64_t)c * P + p) * NS + base + jj];
+            for (int c = 0; c < 8; ++c) g += K64[pr * 8 + c] * coef[((p * 2 + (c >> 2)) * NS + base + jj) * 4 + (c & 3)];
             s += W64[pr * 4 + jj] * g;
         }
         acc += s;
@@ -83,7 +86,7 @@ __device__ __forceinline__ float load_coef(const uint16_t *p) { return __uint_as
 
 // Value of lane l+1 (wavefront shift by one lane; lane 63 receives 0).
 __device__ __forceinline__ float from_next_lane(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */, 0xF, 0xF, true));
 }
 
 constexpr int kChunk = 64;  // panels summed in FP32 before adding into the FP64 accumulator
@@ -109,7 +112,6 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
     const int64_t pb = z * p_chunk;
     const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
     const int64_t kl = k0 + kGatherKT * lane;
-    const int64_t chs = P * NS;
     const PairRec *rr = rec + o * P;
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     double accd[4] = {0.0, 0.0, 0.0, 0.0};
@@ -118,12 +120,16 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
         const PairRec r = rr[p];
         int64_t base = (int64_t)r.n0 + kl;
         if (base > NS - 4) base = NS - 4;  // only lanes whose samples are past N_t(o) reach the clamp
-        const TS *cp = coef + p * NS + base;
+        const TS *c0 = coef + ((p * 2) * NS + base) * 4;   // group 0 quads at base .. base+3
+        const TS *c1 = c0 + NS * 4;                        // group 1
         float g[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int i = 0; i < 4; ++i) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g[i] = fmaf(r.K[c], load_coef(cp + c * chs + i), g[i]);
+            for (int cc = 0; cc < 4; ++cc) {
+                g[i] = fmaf(r.K[cc], load_coef(c0 + i * 4 + cc), g[i]);
+                g[i] = fmaf(r.K[4 + cc], load_coef(c1 + i * 4 + cc), g[i]);
+            }
         }
         float G[7];
         G[0] = g[0];
@@ -157,6 +163,311 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
     }
 }
 
+
+// LDS-staged gather.  Block = kLdsWaves waves, observer tile t (kObsPerWave
+// observers per wave), samples k0 .. k0 + kLdsK - 1, panels [z*p_chunk, ...).
+// For each stage of up to PT panels the block copies into LDS, per panel, the
+// coefficient window [lo + k0, lo + k0 + (hi - lo) + kLdsK + kLdsHalo) of the 8
+// channels, interleaved as [2][NW][4] (lo/hi bound n0 over the tile's
+// observers), and the stage's pair records.  Then every wave, for each of its
+// observers and each of the kLdsSub sub-blocks, lets lane l combine the 8
+// channels at window position n0 - lo + 61 m + l (two vector LDS reads),
+// fetches the combined values of lanes l+1..l+3 by three wavefront shifts and
+// applies the four taps.
+template <typename TS>
+struct Quad;
+template <>
+struct Quad<float> {
+    using T = float4;
+    static __device__ __forceinline__ void unpack(const float4 &v, float o[4]) {
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+template <>
+struct Quad<uint16_t> {
+    using T = uint2;  // four bfloat16
+    static __device__ __forceinline__ void unpack(const uint2 &v, float o[4]) {
+        o[0] = __uint_as_float(v.x << 16);
+        o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16);
+        o[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+
+// Element of a staged window: the 4 channels of one group at one time index
+// (16 bytes in FP32, 8 bytes in BF16); copied to LDS by direct global->LDS loads
+// of 16 bytes (FP32) or 4 bytes (BF16) per lane.
+template <typename TS>
+struct Stage;
+template <>
+struct Stage<float> {
+    static constexpr int kBytesPerLoad = 16;  // one element per lane
+    static constexpr int kElemPerLoad = 1;
+};
+template <>
+struct Stage<uint16_t> {
+    static constexpr int kBytesPerLoad = 4;   // half an element per lane
+    static constexpr int kElemPerLoad = 2;
+};
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Direct global -> LDS copy of `count` units of Stage::kBytesPerLoad bytes from
+// src (byte address of unit u: src + u*bytes, clamped to unit `last`) to LDS at
+// dst (unit u at dst + u*bytes), wave w handling 64-unit chunks w, w + 8, ...
+template <int BYTES>  // 16 or 4
+__device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t last, unsigned char *dst, int count,
+                                            int wv, int lane) {
+    for (int ci = wv; ci * 64 < count; ci += kLdsWaves) {
+        int64_t u = (int64_t)ci * 64 + lane;
+        u = u < last ? u : last;
+        if constexpr (BYTES == 16)
+            __builtin_amdgcn_global_load_lds((const void *)(src + u * 16), (lds_ptr_t)(dst + ci * 64 * 16), 16, 0, 0);
+        else
+            __builtin_amdgcn_global_load_lds((const void *)(src + u * 4), (lds_ptr_t)(dst + ci * 64 * 4), 4, 0, 0);
+    }
+}
+
+// LDS-staged gather.  Block = kLdsWaves waves, observer tile t (kObsPerWave
+// observers per wave), samples k0 .. k0 + kLdsK - 1, panels [z*p_chunk, ...) in
+// stages of PT panels, double-buffered: while the waves work on one stage the
+// direct global->LDS loads of the next are in flight.  Per panel a stage holds
+// the coefficient windows [lo + k0, lo + k0 + NW) of both channel groups
+// ([2][NW][4], lo = min n0 over the tile's observers, NW >= max width + kLdsK +
+// kLdsHalo) and the tile's pair records.  Every wave, for each of its observers
+// and each of the kLdsSub sub-blocks, lets lane l combine the 8 channels at
+// window position n0 - lo + 61 m + l (two vector LDS reads), fetches the
+// combined values of lanes l+1..l+3 by three wavefront shifts and applies the
+// four taps.
+template <typename TS>
+__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(const PairRec *__restrict__ rec,
+                                                                    const int2 *__restrict__ tw,
+                                                                    const int32_t *__restrict__ nt,
+                                                                    const TS *__restrict__ coef, int64_t P,
+                                                                    int64_t O, int64_t NS, int64_t nt_max,
+                                                                    int64_t p_chunk, int NW, int PT,
+                                                                    double *__restrict__ partial) {
+    using QT = typename Quad<TS>::T;
+    constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const size_t win_bytes = (size_t)2 * NW * EB;                    // one panel, both groups
+    const size_t buf_bytes = (size_t)PT * (win_bytes + kObsTile * sizeof(PairRec));
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t = blockIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.y * kLdsK;
+    const int64_t z = blockIdx.z;
+    const int64_t pb = z * p_chunk;
+    const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
+    const int64_t obase = t * kObsTile + (int64_t)wv * kObsPerWave;
+    const int2 *twt = tw + t * P;
+    const int64_t ot_last = (O - 1 - t * kObsTile) < kObsTile - 1 ? (O - 1 - t * kObsTile) : kObsTile - 1;
+
+    // issue the loads of the stage starting at panel ps into buffer b
+    auto fill = [&](int64_t ps, int b) {
+        const int np = (int)(pe - ps < PT ? pe - ps : PT);
+        unsigned char *base = smem_raw + (size_t)b * buf_bytes;
+        for (int q = 0; q < np; ++q) {
+            const int64_t p = ps + q;
+            const int64_t start = (int64_t)twt[p].x + k0;
+            const int units = NW * Stage<TS>::kElemPerLoad;
+            for (int g = 0; g < 2; ++g) {
+                const unsigned char *src =
+                    reinterpret_cast<const unsigned char *>(coef + ((p * 2 + g) * NS + start) * 4);
+                // units past the row end are clamped to its last unit (never read by valid outputs)
+                const int64_t last = (NS - start) * Stage<TS>::kElemPerLoad - 1;
+                copy_to_lds<Stage<TS>::kBytesPerLoad>(src, last, base + q * win_bytes + g * NW * EB, units, wv, lane);
+            }
+        }
+        // records: for panel q, observer j of the tile -> 64 bytes at [q][j]
+        unsigned char *rbase = base + (size_t)PT * win_bytes;
+        const int runits = np * kObsTile * 4;  // 16-byte units
+        for (int ci = wv; ci * 64 < runits; ci += kLdsWaves) {
+            int u = ci * 64 + lane;
+            u = u < runits ? u : runits - 1;
+            const int q = u / (kObsTile * 4), r = u - q * (kObsTile * 4);
+            const int64_t jj = (r >> 2) < ot_last ? (r >> 2) : ot_last;
+            const float4 *srec = reinterpret_cast<const float4 *>(rec + (t * kObsTile + jj) * P + ps + q) + (r & 3);
+            __builtin_amdgcn_global_load_lds((const void *)srec, (lds_ptr_t)(rbase + ci * 64 * 16), 16, 0, 0);
+        }
+    };
+
+    float acc[kObsPerWave][kLdsSub];
+    double accd[kObsPerWave][kLdsSub];
+#pragma unroll
+    for (int j = 0; j < kObsPerWave; ++j)
+#pragma unroll
+        for (int m = 0; m < kLdsSub; ++m) {
+            acc[j][m] = 0.f;
+            accd[j][m] = 0.0;
+        }
+    int cnt = 0;
+    int b = 0;
+    if (pb < pe) fill(pb, 0);
+    for (int64_t ps = pb; ps < pe; ps += PT, b ^= 1) {
+        const int np = (int)(pe - ps < PT ? pe - ps : PT);
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
+        __syncthreads();                // ... and every wave's; the other buffer is free
+        if (ps + PT < pe) fill(ps + PT, b ^ 1);
+        const unsigned char *base = smem_raw + (size_t)b * buf_bytes;
+        const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
+        for (int q = 0; q < np; ++q) {
+            const int lo = twt[ps + q].x;
+            const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
+            const QT *L1 = L0 + NW;
+#pragma unroll
+            for (int j = 0; j < kObsPerWave; ++j) {
+                if (obase + j < O) {
+                    const float4 *R = lrec + (q * kObsTile + wv * kObsPerWave + j) * 4;
+                    const float4 Ka = R[0], Kb = R[1], W = R[2];
+                    const int off = __float_as_int(R[3].x) - lo;
+#pragma unroll
+                    for (int m = 0; m < kLdsSub; ++m) {
+                        const int idx = off + m * kLdsLanesOut + lane;
+                        float a[4], c[4];
+                        Quad<TS>::unpack(L0[idx], a);
+                        Quad<TS>::unpack(L1[idx], c);
+                        float g = Ka.x * a[0];
+                        g = fmaf(Ka.y, a[1], g);
+                        g = fmaf(Ka.z, a[2], g);
+                        g = fmaf(Ka.w, a[3], g);
+                        g = fmaf(Kb.x, c[0], g);
+                        g = fmaf(Kb.y, c[1], g);
+                        g = fmaf(Kb.z, c[2], g);
+                        g = fmaf(Kb.w, c[3], g);
+                        const float g1 = from_next_lane(g);
+                        const float g2 = from_next_lane(g1);
+                        const float g3 = from_next_lane(g2);
+                        float ac = acc[j][m];
+                        ac = fmaf(W.x, g, ac);
+                        ac = fmaf(W.y, g1, ac);
+                        ac = fmaf(W.z, g2, ac);
+                        ac = fmaf(W.w, g3, ac);
+                        acc[j][m] = ac;
+                    }
+                }
+            }
+            if (++cnt == kChunk) {
+#pragma unroll
+                for (int j = 0; j < kObsPerWave; ++j)
+#pragma unroll
+                    for (int m = 0; m < kLdsSub; ++m) {
+                        accd[j][m] += (double)acc[j][m];
+                        acc[j][m] = 0.f;
+                    }
+                cnt = 0;
+            }
+        }
+    }
+    if (lane < kLdsLanesOut) {
+#pragma unroll
+        for (int j = 0; j < kObsPerWave; ++j) {
+            const int64_t o = obase + j;
+            if (o < O) {
+                const int64_t ntl = nt[o];
+#pragma unroll
+                for (int m = 0; m < kLdsSub; ++m) {
+                    const int64_t k = k0 + m * kLdsLanesOut + lane;
+                    if (k < nt_max)
+                        partial[(z * O + o) * nt_max + k] = (k < ntl) ? accd[j][m] + (double)acc[j][m] : 0.0;
+                }
+            }
+        }
+    }
+}
+
+// Zero-padded copy of dJ/dp': gpad[o][k + padlo] = gbar[o][k] for 0 <= k < N_t(o), 0 elsewhere.
+__global__ __launch_bounds__(256) void pad_grad_kernel(const float *__restrict__ gbar, const int32_t *__restrict__ nt,
+                                                       int64_t O, int64_t nt_max, int64_t LR, int64_t padlo,
+                                                       float *__restrict__ gpad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= O * LR) return;
+    const int64_t o = i / LR;
+    const int64_t k = i - o * LR - padlo;
+    gpad[i] = (k >= 0 && k < nt[o]) ? gbar[o * nt_max + k] : 0.f;
+}
+
+// Value of lane l-1 (wavefront shift by one lane; lane 0 receives 0).
+__device__ __forceinline__ float from_prev_lane(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138 /* wave_shr:1 */, 0xF, 0xF, true));
+}
+
+// Transposed gather.  A wave owns panel p and coefficient indices
+// i = 61 b + l - 3 (lanes 0..2 only supply shifted values to lanes 3..5).  Per
+// observer, lane l loads gpad at i - n0 (one coalesced load), receives the
+// values at i - n0 - 1 .. i - n0 - 3 from lanes l-1..l-3 by wavefront shifts,
+// applies the four taps and accumulates the 8 channel weights.
+__global__ __launch_bounds__(256) void adj_gather_dpp_kernel(const PairRec *__restrict__ rec_po,
+                                                             const float *__restrict__ gpad, int64_t P, int64_t O,
+                                                             int64_t NS, int64_t LR, int64_t padlo, int64_t nib,
+                                                             float *__restrict__ cbar) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wv;
+    if (wave_id >= P * nib) return;
+    const int64_t p = wave_id / nib;
+    const int64_t b = wave_id - p * nib;
+    const int64_t i = b * kLdsLanesOut + lane - kLdsHalo;
+    const PairRec *rr = rec_po + p * O;
+    const float *g = gpad + i + padlo;
+    float acc[8];
+    double accd[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc[c] = 0.f;
+        accd[c] = 0.0;
+    }
+    // observers in groups of 4: the 4 records and the 4 gpad values are fetched before any is used
+    auto step = [&](const PairRec &r, float v) {
+        const float s1 = from_prev_lane(v);
+        const float s2 = from_prev_lane(s1);
+        const float s3 = from_prev_lane(s2);
+        float h = r.w[0] * v;
+        h = fmaf(r.w[1], s1, h);
+        h = fmaf(r.w[2], s2, h);
+        h = fmaf(r.w[3], s3, h);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fmaf(r.K[c], h, acc[c]);
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            accd[c] += (double)acc[c];
+            acc[c] = 0.f;
+        }
+    };
+    const int64_t O4 = O & ~(int64_t)3;
+    int cnt = 0;
+    for (int64_t o = 0; o < O4; o += 4) {
+        const PairRec r0 = rr[o], r1 = rr[o + 1], r2 = rr[o + 2], r3 = rr[o + 3];
+        const float v0 = g[o * LR - r0.n0];
+        const float v1 = g[(o + 1) * LR - r1.n0];
+        const float v2 = g[(o + 2) * LR - r2.n0];
+        const float v3 = g[(o + 3) * LR - r3.n0];
+        step(r0, v0);
+        step(r1, v1);
+        step(r2, v2);
+        step(r3, v3);
+        cnt += 4;
+        if (cnt >= kChunk) {
+            flush();
+            cnt = 0;
+        }
+    }
+    for (int64_t o = O4; o < O; ++o) {
+        const PairRec r = rr[o];
+        step(r, g[o * LR - r.n0]);
+    }
+    flush();
+    if (lane >= kLdsHalo && i < NS) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cbar[((int64_t)c * P + p) * NS + i] = (float)accd[c];
+    }
+}
+
 // out[o][k] = sum_z partial[z][o][k] in fixed order.
 __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__restrict__ partial, int splits,
                                                             int64_t total, float *__restrict__ out) {
@@ -165,58 +476,6 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__rest
     double s = 0.0;
     for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * total + i];
     out[i] = (float)s;
-}
-
-// A wave owns one panel and 64 consecutive coefficient indices; loop over all
-// observers with uniform record loads; chunks of observers summed in FP32,
-// then into FP64.
-__global__ __launch_bounds__(256) void adj_gather_tuned_kernel(const PairRec *__restrict__ rec_po,
-                                                               const int32_t *__restrict__ nt,
-                                                               const float *__restrict__ gbar, int64_t P, int64_t O,
-                                                               int64_t NS, int64_t nt_max,
-                                                               float *__restrict__ cbar) {
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t p = (int64_t)blockIdx.x * kAdjPanelsPerBlock + wv;
-    if (p >= P) return;
-    const int64_t i = (int64_t)blockIdx.y * 64 + lane;
-    const PairRec *rr = rec_po + p * O;
-    float acc[8];
-    double accd[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc[c] = 0.f;
-        accd[c] = 0.0;
-    }
-    int cnt = 0;
-    for (int64_t o = 0; o < O; ++o) {
-        const PairRec r = rr[o];
-        const int64_t ntl = nt[o];
-        const float *g = gbar + o * nt_max;
-        const int64_t kb = i - r.n0;
-        float h = 0.f;
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int64_t k = kb - jj;
-            const bool ok = k >= 0 && k < ntl;
-            const float v = g[ok ? k : 0];
-            h = fmaf(r.w[jj], ok ? v : 0.f, h);
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fmaf(r.K[c], h, acc[c]);
-        if (++cnt == kChunk) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                accd[c] += (double)acc[c];
-                acc[c] = 0.f;
-            }
-            cnt = 0;
-        }
-    }
-    if (i < NS) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cbar[((int64_t)c * P + p) * NS + i] = (float)(accd[c] + (double)acc[c]);
-    }
 }
 
 }  // namespace
@@ -245,6 +504,22 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
     return hipGetLastError();
 }
 
+hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *tw, const int32_t *nt, const void *coef,
+                             int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
+                             double *partial, hipStream_t stream) {
+    const int64_t p_chunk = (P + splits - 1) / splits;
+    dim3 grid((unsigned)((O + kObsTile - 1) / kObsTile), (unsigned)((nt_max + kLdsK - 1) / kLdsK), (unsigned)splits);
+    const size_t esz = coef_type == 1 ? sizeof(float) : sizeof(uint16_t);
+    const size_t shmem = 2 * (size_t)PT * ((size_t)8 * NW * esz + (size_t)kObsTile * sizeof(PairRec));
+    if (coef_type == 1)
+        gather_lds_kernel<float><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(
+            rec_op, tw, nt, (const float *)coef, P, O, NS, nt_max, p_chunk, NW, PT, partial);
+    else
+        gather_lds_kernel<uint16_t><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(
+            rec_op, tw, nt, (const uint16_t *)coef, P, O, NS, nt_max, p_chunk, NW, PT, partial);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream) {
     reduce_splits_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(partial, splits, total, out);
     return hipGetLastError();
@@ -259,10 +534,17 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
     return hipGetLastError();
 }
 
-hipError_t launch_adj_gather_tuned(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
-                                   int64_t NS, int64_t nt_max, float *cbar, hipStream_t stream) {
-    dim3 grid((unsigned)((P + kAdjPanelsPerBlock - 1) / kAdjPanelsPerBlock), (unsigned)((NS + 63) / 64));
-    adj_gather_tuned_kernel<<<grid, dim3(256), 0, stream>>>(rec_po, nt, gbar, P, O, NS, nt_max, cbar);
+hipError_t launch_adj_gather_dpp(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
+                                 int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream) {
+    const int64_t LR = adj_pad_row(N, NS), padlo = adj_pad_lo(N);
+    pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(gbar, nt, O, nt_max, LR, padlo,
+                                                                                     gpad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nib = (NS + kLdsLanesOut - 1) / kLdsLanesOut;
+    const int64_t waves = P * nib;
+    adj_gather_dpp_kernel<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream>>>(rec_po, gpad, P, O, NS, LR,
+                                                                                     padlo, nib, cbar);
     return hipGetLastError();
 }
 

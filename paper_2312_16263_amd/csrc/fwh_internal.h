@@ -38,10 +38,23 @@ constexpr int kGatherLanesOut = 63;
 constexpr int kGatherKT = 4;
 constexpr int kGatherK = kGatherLanesOut * kGatherKT;  // 252
 constexpr int kGatherObsPerBlock = 4;                   // one observer per wave
-constexpr int kMaxPanelSplits = 16;
+constexpr int kMaxPanelSplits = 32;
 
-// Adjoint gather geometry: a wave covers 64 consecutive coefficient indices of one panel.
-constexpr int kAdjPanelsPerBlock = 4;
+// LDS-staged gather: a block of kLdsWaves waves owns kObsTile consecutive
+// observers (kObsPerWave per wave) and kLdsK consecutive samples (kLdsSub
+// sub-blocks of kLdsLanesOut lanes, one sample per lane; the last kLdsHalo
+// lanes of a sub-block only supply combined values to their left neighbours).
+// Panel coefficient windows are staged PT panels at a time, double-buffered.
+constexpr int kObsTile = 32;
+constexpr int kLdsWaves = 8;
+constexpr int kObsPerWave = kObsTile / kLdsWaves;
+constexpr int kLdsHalo = 3;
+constexpr int kLdsLanesOut = 64 - kLdsHalo;
+constexpr int kLdsSub = 4;
+constexpr int kLdsK = kLdsSub * kLdsLanesOut;  // 244
+constexpr size_t kLdsBudget = 64 * 1024;       // LDS bytes per block (two stage buffers)
+constexpr int kMaxPanelsPerStage = 8;
+
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return the launch status.
@@ -54,7 +67,16 @@ hipError_t launch_tables(int mode, const double *y, const double *dS, const doub
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
                          int32_t *N0, PairRec *rec_op, PairRec *rec_po, hipStream_t stream);
 
-// Source terms + derivatives + natural-spline prefilter -> coefficients [8][P][NS].
+// Per (observer tile t, panel p): lo/hi of n0 over the tile's observers -> tw[t][p];
+// per block of 256 (t, p) entries the largest hi - lo -> wblk[block].
+hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
+                              hipStream_t stream);
+inline int64_t tile_window_blocks(int64_t P, int64_t O) {
+    return ((O + kObsTile - 1) / kObsTile * P + 255) / 256;
+}
+
+// Source terms + derivatives + natural-spline prefilter -> coefficients [P][2][NS][4]
+// (channel c = 4 g + cc at ((p*2 + g)*NS + i)*4 + cc).
 // in_dtype 0 = double, 1 = float; coef_type 0 = double, 1 = float, 2 = bf16; scratch is
 // [8][N][P] of double (coef_type 0) or float (otherwise).
 hipError_t launch_source(int in_dtype, int coef_type, const void *rho, const void *u, const void *pp,
@@ -68,14 +90,22 @@ hipError_t launch_gather_f64(const double *K64, const double *W64, const int32_t
 hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32_t *nt, const void *coef, int64_t P,
                                int64_t O, int64_t NS, int64_t nt_max, int splits, double *partial,
                                hipStream_t stream);
+// LDS-staged gather; NW = staged window length per channel group (multiple of 64, >= max
+// width + kLdsK + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
+hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *tw, const int32_t *nt, const void *coef,
+                             int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
+                             double *partial, hipStream_t stream);
 // out[i] = sum over splits of partial[z][i], fixed order, rounded to float.
 hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream);
 
 hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int32_t *N0, const int32_t *nt,
                                  const double *gbar, int64_t P, int64_t O, int64_t NS, int64_t nt_max, double *cbar,
                                  hipStream_t stream);
-hipError_t launch_adj_gather_tuned(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
-                                   int64_t NS, int64_t nt_max, float *cbar, hipStream_t stream);
+// Transposed gather via a zero-padded copy of gbar (gpad: [O][adj_pad_row(N, NS)] floats).
+inline int64_t adj_pad_lo(int64_t N) { return N + 4; }
+inline int64_t adj_pad_row(int64_t N, int64_t NS) { return ((N + NS + 64 + 8 + 63) / 64) * 64; }
+hipError_t launch_adj_gather_dpp(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
+                                 int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream);
 
 // Adjoint of the source stage: coefficient adjoints [8][P][NS] -> gradients (time-major, in_dtype).
 // real_type 0 = double (cbar and scratch double), 1 = float.

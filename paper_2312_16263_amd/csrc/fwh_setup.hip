@@ -137,7 +137,44 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
     }
 }
 
+// Window of the fractional-delay index over an observer tile, per panel.
+__global__ __launch_bounds__(256) void tile_window_kernel(const PairRec *__restrict__ rec_op, int64_t P, int64_t O,
+                                                          int64_t n_tiles, int2 *__restrict__ tw,
+                                                          int32_t *__restrict__ wblk) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int width = 0;
+    if (i < n_tiles * P) {
+        const int64_t t = i / P, p = i - t * P;
+        const int64_t o0 = t * kObsTile;
+        const int64_t o1 = o0 + kObsTile < O ? o0 + kObsTile : O;
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int64_t o = o0; o < o1; ++o) {
+            const int n0 = rec_op[o * P + p].n0;
+            lo = n0 < lo ? n0 : lo;
+            hi = n0 > hi ? n0 : hi;
+        }
+        tw[i] = make_int2(lo, hi);
+        width = hi - lo;
+    }
+    __shared__ int sw[256];
+    sw[threadIdx.x] = width;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sw[threadIdx.x] = sw[threadIdx.x] > sw[threadIdx.x + s] ? sw[threadIdx.x] : sw[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wblk[blockIdx.x] = sw[0];
+}
+
 }  // namespace
+
+hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
+                              hipStream_t stream) {
+    const int64_t n_tiles = (O + kObsTile - 1) / kObsTile;
+    tile_window_kernel<<<dim3((unsigned)tile_window_blocks(P, O)), dim3(256), 0, stream>>>(rec_op, P, O, n_tiles, tw,
+                                                                                         wblk);
+    return hipGetLastError();
+}
 
 hipError_t launch_delay(const double *y, const double *x_obs, int64_t P, int64_t O, Flow f, double *D,
                         hipStream_t stream) {

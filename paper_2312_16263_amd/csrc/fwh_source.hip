@@ -13,11 +13,13 @@
 // cp[r] = 1/(4 - cp[r-1])).
 //
 // Layout: one thread per (panel, channel), a wave = 64 consecutive panels of one
-// channel, so every time step is one coalesced load per input variable.  The
-// forward elimination streams the inputs in time order and writes the reduced
-// right-hand sides to a time-major scratch [8][N][P]; back substitution runs in
-// reverse time order and the coefficients go out panel-major [8][P][NS]
-// (time-contiguous rows) through a per-wave LDS transpose.  All arithmetic FP64.
+// channel and a block = the 4 channels of one channel group, so every time step
+// is one coalesced load per input variable.  The forward elimination streams
+// the inputs in time order and writes the reduced right-hand sides to a
+// time-major scratch [8][N][P]; back substitution runs in reverse time order and
+// the coefficients go out panel-major with the 4 channels of a group
+// interleaved, coef[P][2][NS][4] (one 4-channel quad per time index), through a
+// block-wide LDS transpose.  All arithmetic FP64.
 #include "fwh_internal.h"
 
 namespace fwh {
@@ -84,9 +86,10 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__
                                                          const double *__restrict__ normal, int64_t P, int64_t N,
                                                          int64_t NS, Flow f, const double *__restrict__ cp,
                                                          TScr *__restrict__ scr, TOut *__restrict__ coef) {
-    constexpr int CH = 128 / (int)sizeof(TOut);  // coefficients per flushed row segment (128 bytes)
+    constexpr int CH = 128 / (int)sizeof(TOut);  // time indices per flush (128-byte row segments per channel)
     constexpr int PF = 8;                        // time steps loaded ahead
-    __shared__ TOut stage[4][64][CH + 1];
+    constexpr int RS = CH * 4 + 1;               // padded LDS row: [CH][4 channels] + 1
+    __shared__ TOut stage[64 * RS];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int ch = blockIdx.y * 4 + wv;
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__
     // i = 0: c_{-1}; i = n+1: c_n (n = 0..N-1); i = N+1: c_N; i >= N+2: 0.
     const double xN2 = dprev;  // x_{N-2} = d'_{N-2}
     double x = xN2;            // x_{n+1} of the recurrence
-    TOut *coef_ch = coef + (int64_t)ch * P * NS;
+    const int cc = ch & 3;  // channel within the group
     constexpr int SB = CH < 16 ? CH : 16;  // back-substitution steps loaded ahead
     for (int64_t b = NS / CH - 1; b >= 0; --b) {
         const int64_t i0 = b * CH;
@@ -173,14 +176,22 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__
                     v = x;
                 } else if (i == 1) v = f0;
                 else v = 2.0 * f0 - x;
-                stage[wv][lane][sb + q] = Store<TOut>::put(v);
+                stage[lane * RS + (sb + q) * 4 + cc] = Store<TOut>::put(v);
             }
         }
         __syncthreads();
-        for (int t = lane; t < 64 * CH; t += 64) {
+        // block-wide flush: for each of the 64 panels, CH quads of 4 channels, contiguous in memory
+        for (int t = threadIdx.x; t < 64 * CH; t += 256) {
             const int r = t / CH, col = t - r * CH;
             const int64_t prow = pbase + r;
-            if (prow < P) coef_ch[prow * NS + i0 + col] = stage[wv][r][col];
+            if (prow < P) {
+                TOut *dst = coef + (((prow * 2 + blockIdx.y) * NS) + i0 + col) * 4;
+                const TOut *src = stage + r * RS + col * 4;
+                dst[0] = src[0];
+                dst[1] = src[1];
+                dst[2] = src[2];
+                dst[3] = src[3];
+            }
         }
         __syncthreads();
     }

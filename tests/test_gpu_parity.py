@@ -137,3 +137,20 @@ def test_window_error_is_reported():
     with pytest.raises(fwh.FwhError) as ei:
         fwh.Plan(s.y, s.normal, s.dS, np.array([[100.0, 0, 0]]), 0.5, 0.0, 0.01, 0.0, 16, mode="f32")
     assert ei.value.code == fwh.FWH_EWINDOW
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_direct_load_gather_matches(mode, monkeypatch):
+    """The direct-load gather (used when a panel window does not fit in LDS)
+    against the oracle, forced through its test hook."""
+    import torch
+    monkeypatch.setenv("FWH_FORCE_DIRECT_GATHER", "1")
+    c = CASES["dip_ragged"]
+    rho, u, pp, p_ref, _, nt_ref = _data("dip_ragged")
+    plan = make_plan(c, mode)
+    out = plan.forward(*to_device((rho, u, pp)))
+    torch.cuda.synchronize()
+    p = out.double().cpu().numpy()
+    err = rel_l2(p, p_ref, valid_mask(nt_ref, p.shape[1]))
+    print(f"    direct gather {mode}: rel L2 vs oracle = {err:.3e}", flush=True)
+    assert err <= TOL_FWD[mode], err
