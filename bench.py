@@ -61,6 +61,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for rocprofv3: 1 warmup + `--steps` FP32 steps, then a 1 GiB device copy "
+                         "(the reference kernel for HBM byte counters); prints no JSON")
+    ap.add_argument("--mode", default="f32", choices=["f32", "bf16"], help="mode of the profile run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -85,6 +89,16 @@ def main():
     log(f"[bench] inputs generated and resident in HBM ({time.time() - t0:.1f} s)")
 
     sync = torch.cuda.synchronize
+    if args.profile_run:
+        plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
+                        c.n_tau, mode=args.mode)
+        run_steps(plan, d, 1 + args.steps, sync)
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        log(f"[bench] profile run done: {1 + args.steps} steps ({args.mode}), then a 1 GiB copy")
+        return
     plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
                     c.n_tau, mode="f32")
     nt = plan.window.n_t
