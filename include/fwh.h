@@ -149,6 +149,48 @@ int fwh_adjoint(fwh_plan *plan, int32_t in_dtype, const void *rho, const void *u
 int fwh_profile_enable(fwh_plan *plan, int enable);
 int fwh_profile_read(fwh_plan *plan, int32_t stage, double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------- batches
+ * Many cases (surfaces, observer sets, record lengths, flows) of uneven size run
+ * as one batch: forward and adjoint of all cases are each a fixed sequence of
+ * batched launches (source stage of all cases, a persistent forward gather that
+ * pulls longest-first work items of all cases from a queue, the split sums; then
+ * the transposed gather and source-stage transpose of all cases), so a whole
+ * forward + adjoint can be captured once in a HIP graph and replayed.  No call
+ * below allocates, synchronises or copies from the host except fwh_batch_bind.
+ * Not in the paper: its cases run one at a time (Sec. III B); the longest-first
+ * ordering follows the paper's greedy Face partition (Sec. III A).
+ *
+ * Every case names a set-up plan (FWH_MODE_F32 or FWH_MODE_BF16, the same for
+ * all cases) and its device buffers, with the layouts of fwh_forward/fwh_adjoint
+ * (p_out and grad_p are float).  The plans and buffers must outlive the batch. */
+typedef struct fwh_batch fwh_batch;
+typedef struct {
+    fwh_plan *plan;
+    const void *rho, *u, *p_prime;   /* device surface data, in_dtype */
+    void *p_out;                     /* device [O][n_t_max] float */
+    const void *grad_p;              /* device [O][n_t_max] float (adjoint input) */
+    void *g_rho, *g_u, *g_p;         /* device gradients, in_dtype */
+} fwh_batch_case;
+
+/* Host only: validate the cases and report the size of the batch's own device
+ * workspace (descriptors, work list, queue counter). */
+int fwh_batch_create(const fwh_batch_case *cases, int32_t n_cases, int32_t in_dtype, fwh_batch **out,
+                     size_t *workspace_bytes);
+/* Host only: tile granularity for the next fwh_batch_bind: target work per item
+ * (panel-observer-samples; <= 0 keeps the default) and resident blocks per
+ * compute unit of the persistent gather (1..4). */
+int fwh_batch_tune(fwh_batch *batch, double item_units, int32_t blocks_per_cu);
+/* Build the work list and upload descriptors and list into the workspace
+ * (>= workspace_bytes, 256-byte aligned) on `stream`; synchronises `stream`. */
+int fwh_batch_bind(fwh_batch *batch, void *workspace, size_t workspace_bytes, void *stream);
+/* Enqueue the batched forward (all p_out) / adjoint (all gradients) on `stream`. */
+int fwh_batch_forward(fwh_batch *batch, void *stream);
+int fwh_batch_adjoint(fwh_batch *batch, void *stream);
+/* Number of work items of the persistent gather, total panel-observer-samples
+ * and resident blocks of the persistent grid (any pointer may be NULL). */
+int fwh_batch_info(const fwh_batch *batch, int64_t *n_items, int64_t *units, int64_t *grid);
+void fwh_batch_destroy(fwh_batch *batch);
+
 /* Release the plan (host memory only; the workspace stays the caller's). */
 void fwh_destroy(fwh_plan *plan);
 

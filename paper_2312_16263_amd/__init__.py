@@ -27,7 +27,9 @@ ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW
 
 # names declared in include/fwh.h
 EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_profile_enable",
-            "fwh_profile_read", "fwh_destroy", "fwh_last_error", "fwh_version"]
+            "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_bind", "fwh_batch_forward",
+            "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_last_error",
+            "fwh_version"]
 STAGES = {"setup": 0, "source": 1, "gather": 2, "reduce": 3, "adj_gather": 4, "source_adj": 5}
 
 
@@ -43,6 +45,12 @@ class SetupArgs(ctypes.Structure):
                 ("dS", ctypes.POINTER(ctypes.c_double)), ("x_obs", ctypes.POINTER(ctypes.c_double)),
                 ("mach", ctypes.c_double), ("aoa_deg", ctypes.c_double), ("dtau", ctypes.c_double),
                 ("tau0", ctypes.c_double), ("mode", ctypes.c_int32)]
+
+
+class BatchCaseC(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("p_prime", ctypes.c_void_p), ("p_out", ctypes.c_void_p), ("grad_p", ctypes.c_void_p),
+                ("g_rho", ctypes.c_void_p), ("g_u", ctypes.c_void_p), ("g_p", ctypes.c_void_p)]
 
 
 _lib = None
@@ -71,6 +79,20 @@ def lib():
         L.fwh_profile_enable.restype = ctypes.c_int
         L.fwh_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.fwh_profile_read.restype = ctypes.c_int
+        L.fwh_batch_create.argtypes = [ctypes.POINTER(BatchCaseC), i32, i32, ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.fwh_batch_create.restype = ctypes.c_int
+        L.fwh_batch_tune.argtypes = [vp, ctypes.c_double, i32]
+        L.fwh_batch_tune.restype = ctypes.c_int
+        L.fwh_batch_bind.argtypes = [vp, vp, sz, vp]
+        L.fwh_batch_bind.restype = ctypes.c_int
+        L.fwh_batch_forward.argtypes = [vp, vp]
+        L.fwh_batch_forward.restype = ctypes.c_int
+        L.fwh_batch_adjoint.argtypes = [vp, vp]
+        L.fwh_batch_adjoint.restype = ctypes.c_int
+        L.fwh_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fwh_batch_info.restype = ctypes.c_int
+        L.fwh_batch_destroy.argtypes = [vp]
+        L.fwh_batch_destroy.restype = None
         L.fwh_destroy.argtypes = [vp]
         L.fwh_destroy.restype = None
         L.fwh_last_error.argtypes = []
@@ -205,6 +227,140 @@ class Plan:
                                      ctypes.c_void_p(g_u.data_ptr()), ctypes.c_void_p(g_p.data_ptr()),
                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
         return g_r, g_u, g_p
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Batch:
+    """Many set-up plans (FP32 or BF16 mode) run as one batch: forward and
+    adjoint of every case are each a fixed sequence of batched launches (the
+    forward gather persistent over a longest-first work list), so
+    `capture()` records a whole step (forward, dJ/dp' = 2 p', adjoint) in one
+    HIP graph.  `inputs` holds (rho, u, p) device tensors per plan, one dtype."""
+
+    def __init__(self, plans, inputs, item_units=None, blocks_per_cu=2):
+        import torch
+        L = lib()
+        self.plans = list(plans)
+        self.inputs = [tuple(t) for t in inputs]
+        dt = self.inputs[0][0].dtype
+        self.in_dtype = FWH_F64 if dt == torch.float64 else FWH_F32
+        self.p_out, self.grad_p, self.grads = [], [], []
+        arr = (BatchCaseC * len(self.plans))()
+        for i, (pl, (rho, u, pp)) in enumerate(zip(self.plans, self.inputs)):
+            pl._check_inputs(rho, u, pp)
+            if rho.dtype != dt:
+                raise TypeError("all cases of a batch need one input dtype")
+            po = torch.zeros((pl.O, pl.window.n_t_max), dtype=torch.float32, device=pl.device)
+            gp = torch.zeros_like(po)
+            g = (torch.empty_like(rho), torch.empty_like(u), torch.empty_like(pp))
+            self.p_out.append(po)
+            self.grad_p.append(gp)
+            self.grads.append(g)
+            arr[i] = BatchCaseC(pl._h.value, rho.data_ptr(), u.data_ptr(), pp.data_ptr(), po.data_ptr(),
+                                gp.data_ptr(), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr())
+        h = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
+        _check(L.fwh_batch_create(arr, len(self.plans), self.in_dtype, ctypes.byref(h), ctypes.byref(nb)))
+        self._h = h
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.plans[0].device)
+        self.tune(item_units, blocks_per_cu)
+
+    def tune(self, item_units=None, blocks_per_cu=2):
+        L = lib()
+        _check(L.fwh_batch_tune(self._h, float(item_units or 0.0), int(blocks_per_cu)))
+        _check(L.fwh_batch_bind(self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                _stream()))
+        self.item_units, self.blocks_per_cu = item_units, blocks_per_cu
+
+    def info(self):
+        n_items, units, grid = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fwh_batch_info(self._h, ctypes.byref(n_items), ctypes.byref(units), ctypes.byref(grid)))
+        return {"items": int(n_items.value), "units": int(units.value), "grid": int(grid.value)}
+
+    def forward(self):
+        _check(lib().fwh_batch_forward(self._h, _stream()))
+        return self.p_out
+
+    def adjoint(self):
+        _check(lib().fwh_batch_adjoint(self._h, _stream()))
+        return self.grads
+
+    def step(self):
+        """forward, dJ/dp' = 2 p' for J = sum p'^2 (elementwise, no memset), adjoint."""
+        import torch
+        self.forward()
+        for po, gp in zip(self.p_out, self.grad_p):
+            torch.mul(po, 2.0, out=gp)
+        self.adjoint()
+
+    def capture(self):
+        """Record one step in a HIP graph (torch.cuda.CUDAGraph) and return it."""
+        import torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        return g
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fwh_batch_destroy(h)
+            self._h = None
+
+
+DEFAULT_TUNING_CANDIDATES = [(1e6, 2), (2e6, 2), (4e6, 2), (8e6, 2), (16e6, 2), (4e6, 1), (4e6, 3)]
+
+
+def batch_signature(batch: "Batch") -> str:
+    parts = [f"m{batch.plans[0].mode}", f"d{batch.in_dtype}"]
+    parts += [f"{p.P}x{p.O}x{p.N}" for p in batch.plans]
+    return "|".join(parts)
+
+
+def autotune(batch: "Batch", candidates=None, reps=3, cache_path=None):
+    """Pick the work granularity (target panel-observer-samples per work item)
+    and the resident blocks per CU of the persistent forward gather by timing
+    each candidate with HIP events; cache the choice per batch signature in
+    `cache_path` (JSON) when given.  Returns (item_units, blocks_per_cu, table)."""
+    import json
+    import os
+    import torch
+    key = batch_signature(batch)
+    if cache_path and os.path.exists(cache_path):
+        cache = json.load(open(cache_path))
+        if key in cache:
+            iu, bpc = cache[key]["choice"]
+            batch.tune(iu, bpc)
+            return iu, bpc, cache[key]["table"]
+    table = []
+    for iu, bpc in (candidates or DEFAULT_TUNING_CANDIDATES):
+        batch.tune(iu, bpc)
+        batch.forward()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            batch.forward()
+        b.record()
+        b.synchronize()
+        table.append((iu, bpc, a.elapsed_time(b) / reps))
+    iu, bpc, _ = min(table, key=lambda r: r[2])
+    batch.tune(iu, bpc)
+    if cache_path:
+        cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
+        cache[key] = {"choice": [iu, bpc], "table": table}
+        json.dump(cache, open(cache_path, "w"))
+    return iu, bpc, table
 
 
 def _autograd_function():

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -51,7 +52,7 @@ struct fwh_plan {
     bool ready = false;
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
-    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_rec_po = 0, off_tw = 0, off_wblk = 0;
+    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_tw = 0, off_wblk = 0;
     size_t off_coef = 0, off_scr = 0, off_part = 0, off_gpad = 0, ws_bytes = 0;
     char *ws = nullptr;
     // optional per-stage event timing
@@ -89,7 +90,6 @@ int layout(fwh_plan *pl) {
         pl->off_N0 = take(O * P * sizeof(int32_t));
     } else {
         pl->off_rec_op = take(O * P * sizeof(fwh::PairRec));
-        pl->off_rec_po = take(O * P * sizeof(fwh::PairRec));
         pl->off_tw = take((O + fwh::kObsTile - 1) / fwh::kObsTile * P * sizeof(int2));
         pl->off_wblk = take((size_t)fwh::tile_window_blocks(pl->P, pl->O) * sizeof(int32_t));
     }
@@ -255,8 +255,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
                                 pl->at<double>(pl->off_x), pl->at<double>(pl->off_ts), pl->at<int32_t>(pl->off_nt), P,
                                 O, N, pl->flow, f64 ? pl->at<double>(pl->off_K64) : nullptr,
                                 f64 ? pl->at<double>(pl->off_W64) : nullptr, f64 ? pl->at<int32_t>(pl->off_N0) : nullptr,
-                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op),
-                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_po), st)))
+                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op), st)))
         return hip_fail("fwh_setup: table kernel", e);
     if (!f64) {
         // per (observer tile, panel) windows of n0 and their largest width -> LDS staging geometry
@@ -374,7 +373,7 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
                                        static_cast<const double *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
                                        pl->at<double>(pl->off_coef), st);
     else
-        e = fwh::launch_adj_gather_dpp(pl->at<fwh::PairRec>(pl->off_rec_po), pl->at<int32_t>(pl->off_nt),
+        e = fwh::launch_adj_gather_dpp(pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
                                        static_cast<const float *>(grad_p), pl->P, pl->O, pl->N, pl->NS, pl->n_t_max,
                                        pl->at<float>(pl->off_gpad), pl->at<float>(pl->off_coef), st);
     }
@@ -419,6 +418,218 @@ int fwh_profile_read(fwh_plan *pl, int32_t stage, double *total_ms, int64_t *lau
     if (launches) *launches = n;
     return status;
 }
+
+}  // extern "C"
+
+struct fwh_batch {
+    std::vector<fwh_batch_case> cases;
+    int in_dtype = 0, mode = 0, n = 0;
+    double item_units = 4.0e6;
+    int blocks_per_cu = 2;
+    int64_t max_items = 0, n_items = 0, units = 0, grid = 0;
+    int64_t blocks_src = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_pre = 0, blocks_chain = 0;
+    size_t shmem = 0;
+    size_t off_cases = 0, off_idx = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
+    char *ws = nullptr;
+    bool bound = false;
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+extern "C" {
+
+int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, fwh_batch **out,
+                     size_t *workspace_bytes) {
+    g_last_error.clear();
+    if (out) *out = nullptr;
+    if (!cases || !out || n < 1) return fail(FWH_EINVAL, "fwh_batch_create: need cases, out and n_cases >= 1");
+    if (in_dtype != FWH_F64 && in_dtype != FWH_F32) return fail(FWH_EINVAL, "fwh_batch_create: bad in_dtype");
+    int mode = -1;
+    int64_t max_items = 0;
+    for (int c = 0; c < n; ++c) {
+        const fwh_batch_case &k = cases[c];
+        if (!k.plan || !k.rho || !k.u || !k.p_prime || !k.p_out || !k.grad_p || !k.g_rho || !k.g_u || !k.g_p)
+            return fail(FWH_EINVAL, "fwh_batch_create: case %d has a null pointer", c);
+        if (!k.plan->ready) return fail(FWH_ESTATE, "fwh_batch_create: plan of case %d is not set up", c);
+        if (k.plan->mode == FWH_MODE_F64)
+            return fail(FWH_EINVAL, "fwh_batch_create: case %d uses the plain FP64 mode (batches run FP32/BF16)", c);
+        if (mode < 0) mode = k.plan->mode;
+        if (k.plan->mode != mode) return fail(FWH_EINVAL, "fwh_batch_create: cases mix FP32 and BF16 modes");
+        if (k.plan->lds_pt <= 0)
+            return fail(FWH_EINVAL, "fwh_batch_create: case %d has delay windows too wide for the LDS gather", c);
+        const int64_t tiles = ceil_div(k.plan->O, fwh::kObsTile), kbs = ceil_div(k.plan->n_t_max, fwh::kLdsK);
+        max_items += tiles * kbs * fwh::kMaxPanelSplits;
+    }
+    if (max_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many work items");
+    fwh_batch *b = new (std::nothrow) fwh_batch();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_create: out of host memory");
+    b->cases.assign(cases, cases + n);
+    b->n = n;
+    b->in_dtype = in_dtype;
+    b->mode = mode;
+    b->max_items = max_items;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    b->off_cases = take((size_t)n * sizeof(fwh::BatchCase));
+    b->off_idx = take((size_t)6 * (n + 1) * sizeof(int64_t));
+    b->off_items = take((size_t)max_items * sizeof(int4));
+    b->off_counter = take(sizeof(int));
+    b->ws_bytes = off;
+    *out = b;
+    if (workspace_bytes) *workspace_bytes = off;
+    return FWH_OK;
+}
+
+int fwh_batch_tune(fwh_batch *b, double item_units, int32_t blocks_per_cu) {
+    g_last_error.clear();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_tune: null batch");
+    if (blocks_per_cu < 1 || blocks_per_cu > 4) return fail(FWH_EINVAL, "fwh_batch_tune: blocks_per_cu in 1..4");
+    if (item_units > 0.0) b->item_units = item_units;
+    b->blocks_per_cu = blocks_per_cu;
+    b->bound = false;
+    return FWH_OK;
+}
+
+int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *stream_) {
+    g_last_error.clear();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_bind: null batch");
+    if (!workspace || workspace_bytes < b->ws_bytes || reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(FWH_EWORKSPACE, "fwh_batch_bind: need a %zu-byte, 256-byte aligned workspace", b->ws_bytes);
+    hipStream_t st = as_stream(stream_);
+    const int n = b->n;
+    const int coef_type = b->mode == FWH_MODE_F32 ? 1 : 2;
+    std::vector<fwh::BatchCase> desc((size_t)n);
+    std::vector<int64_t> idx((size_t)6 * (n + 1), 0);
+    int64_t *s_src = idx.data(), *s_red = s_src + (n + 1), *s_pad = s_red + (n + 1), *s_adj = s_pad + (n + 1),
+            *s_pre = s_adj + (n + 1), *s_chain = s_pre + (n + 1);
+    struct Item {
+        double cost;
+        int4 w;
+    };
+    std::vector<Item> items;
+    b->units = 0;
+    b->shmem = 0;
+    for (int c = 0; c < n; ++c) {
+        const fwh_batch_case &k = b->cases[c];
+        fwh_plan *pl = k.plan;
+        const int64_t P = pl->P, O = pl->O, N = pl->N, NS = pl->NS, ntm = pl->n_t_max;
+        const int64_t tiles = ceil_div(O, fwh::kObsTile), kbs = ceil_div(ntm, fwh::kLdsK);
+        // panel splits: work per item close to item_units
+        const double tile_units = (double)P * std::min<int64_t>(O, fwh::kObsTile) * std::min<int64_t>(ntm, fwh::kLdsK);
+        int64_t S = (int64_t)std::ceil(tile_units / b->item_units);
+        S = std::max<int64_t>(1, std::min<int64_t>({S, (int64_t)fwh::kMaxPanelSplits, ceil_div(P, 64)}));
+        const int64_t p_chunk = ceil_div(P, S);
+        const int64_t LR = fwh::adj_pad_row(N, NS), padlo = fwh::adj_pad_lo(N);
+        const int64_t nib = ceil_div(NS, fwh::kLdsLanesOut);
+        fwh::BatchCase &d = desc[c];
+        d.src = fwh::SrcFwdArgs{k.rho, k.u, k.p_prime, pl->at<double>(pl->off_n), P, N, NS, pl->flow,
+                                pl->at<double>(pl->off_cp), pl->ws + pl->off_scr, pl->ws + pl->off_coef};
+        d.gat = fwh::GatherArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int2>(pl->off_tw),
+                                pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, P, O, NS, ntm, p_chunk,
+                                pl->lds_nw, pl->lds_pt, (int)S, pl->at<double>(pl->off_part)};
+        d.red = fwh::ReduceArgs{pl->at<double>(pl->off_part), (int)S, O * ntm, static_cast<float *>(k.p_out)};
+        d.pad = fwh::PadArgs{static_cast<const float *>(k.grad_p), pl->at<int32_t>(pl->off_nt), O, ntm, LR, padlo,
+                             pl->at<float>(pl->off_gpad)};
+        d.adj = fwh::AdjArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<float>(pl->off_gpad), P, O, NS, LR, padlo,
+                             nib, pl->at<float>(pl->off_coef)};
+        d.pre = fwh::PreAdjArgs{pl->ws + pl->off_coef, P, N, NS, pl->at<double>(pl->off_cp), pl->ws + pl->off_scr};
+        d.chain = fwh::ChainArgs{pl->ws + pl->off_scr, k.rho, k.u, pl->at<double>(pl->off_n), P, N, pl->flow,
+                                 k.g_rho, k.g_u, k.g_p};
+        s_src[c + 1] = s_src[c] + ceil_div(P, 64) * 2;
+        s_red[c + 1] = s_red[c] + ceil_div(O * ntm, 256);
+        s_pad[c + 1] = s_pad[c] + ceil_div(O * LR, 256);
+        s_adj[c + 1] = s_adj[c] + P * nib;
+        s_pre[c + 1] = s_pre[c] + ceil_div(P, 64) * 2;
+        s_chain[c + 1] = s_chain[c] + ceil_div(P, 256) * N;
+        b->shmem = std::max(b->shmem, fwh::gather_lds_shmem(coef_type, pl->lds_nw, pl->lds_pt));
+        for (int64_t t = 0; t < tiles; ++t)
+            for (int64_t kb = 0; kb < kbs; ++kb)
+                for (int64_t z = 0; z < S; ++z) {
+                    const int64_t np = std::max<int64_t>(0, std::min(P, (z + 1) * p_chunk) - z * p_chunk);
+                    const int64_t no = std::min<int64_t>(fwh::kObsTile, O - t * fwh::kObsTile);
+                    const int64_t nk = std::min<int64_t>(fwh::kLdsK, ntm - kb * fwh::kLdsK);
+                    items.push_back({(double)np * no * nk, make_int4(c, (int)t, (int)kb, (int)z)});
+                }
+        int64_t sum_nt = 0;
+        for (int64_t o = 0; o < O; ++o) sum_nt += pl->n_t[o];
+        b->units += P * sum_nt;
+    }
+    // longest first (the paper's greedy partition by size), ties in case order
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    std::vector<int4> wl(items.size());
+    for (size_t i = 0; i < items.size(); ++i) wl[i] = items[i].w;
+    b->n_items = (int64_t)wl.size();
+    b->blocks_src = s_src[n];
+    b->blocks_red = s_red[n];
+    b->blocks_pad = s_pad[n];
+    b->waves_adj = s_adj[n];
+    b->blocks_pre = s_pre[n];
+    b->blocks_chain = s_chain[n];
+    int dev = 0, cus = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
+        return hip_fail("fwh_batch_bind: device query", e);
+    b->grid = (int64_t)cus * b->blocks_per_cu;
+    b->ws = static_cast<char *>(workspace);
+    if ((e = hipMemcpyAsync(b->at<fwh::BatchCase>(b->off_cases), desc.data(), desc.size() * sizeof(fwh::BatchCase),
+                            hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(b->at<int64_t>(b->off_idx), idx.data(), idx.size() * sizeof(int64_t),
+                            hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(b->at<int4>(b->off_items), wl.data(), wl.size() * sizeof(int4), hipMemcpyHostToDevice,
+                            st)) ||
+        (e = hipStreamSynchronize(st)))
+        return hip_fail("fwh_batch_bind: upload", e);
+    b->bound = true;
+    return FWH_OK;
+}
+
+static fwh::BatchIndex batch_index(const fwh_batch *b) {
+    const int64_t *base = b->at<int64_t>(b->off_idx);
+    const int64_t m = b->n + 1;
+    return fwh::BatchIndex{base, base + m, base + 2 * m, base + 3 * m, base + 4 * m, base + 5 * m, b->n};
+}
+
+int fwh_batch_forward(fwh_batch *b, void *stream_) {
+    g_last_error.clear();
+    if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_forward: batch is not bound");
+    hipError_t e = fwh::launch_batch_forward(b->in_dtype == FWH_F64 ? 0 : 1, b->mode == FWH_MODE_F32 ? 1 : 2,
+                                             b->at<fwh::BatchCase>(b->off_cases), batch_index(b),
+                                             b->at<int4>(b->off_items), (int)b->n_items, b->at<int>(b->off_counter),
+                                             (int)b->grid, b->shmem, b->blocks_src, b->blocks_red, as_stream(stream_));
+    if (e) return hip_fail("fwh_batch_forward", e);
+    return FWH_OK;
+}
+
+int fwh_batch_adjoint(fwh_batch *b, void *stream_) {
+    g_last_error.clear();
+    if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_adjoint: batch is not bound");
+    hipError_t e = fwh::launch_batch_adjoint(b->in_dtype == FWH_F64 ? 0 : 1, b->at<fwh::BatchCase>(b->off_cases),
+                                             batch_index(b), b->blocks_pad, b->waves_adj, b->blocks_pre,
+                                             b->blocks_chain, as_stream(stream_));
+    if (e) return hip_fail("fwh_batch_adjoint", e);
+    return FWH_OK;
+}
+
+int fwh_batch_info(const fwh_batch *b, int64_t *n_items, int64_t *units, int64_t *grid) {
+    g_last_error.clear();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_info: null batch");
+    if (n_items) *n_items = b->n_items;
+    if (units) *units = b->units;
+    if (grid) *grid = b->grid;
+    return FWH_OK;
+}
+
+void fwh_batch_destroy(fwh_batch *b) { delete b; }
 
 void fwh_destroy(fwh_plan *pl) {
     if (!pl) return;

@@ -243,23 +243,22 @@ __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t la
 // combined values of lanes l+1..l+3 by three wavefront shifts and applies the
 // four taps.
 template <typename TS>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(const PairRec *__restrict__ rec,
-                                                                    const int2 *__restrict__ tw,
-                                                                    const int32_t *__restrict__ nt,
-                                                                    const TS *__restrict__ coef, int64_t P,
-                                                                    int64_t O, int64_t NS, int64_t nt_max,
-                                                                    int64_t p_chunk, int NW, int PT,
-                                                                    double *__restrict__ partial) {
+__device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, int64_t kb, int64_t z,
+                                                unsigned char *smem_raw) {
+    const PairRec *__restrict__ rec = a.rec;
+    const int2 *__restrict__ tw = a.tw;
+    const int32_t *__restrict__ nt = a.nt;
+    const TS *__restrict__ coef = static_cast<const TS *>(a.coef);
+    const int64_t P = a.P, O = a.O, NS = a.NS, nt_max = a.nt_max, p_chunk = a.p_chunk;
+    const int NW = a.NW, PT = a.PT;
+    double *__restrict__ partial = a.partial;
     using QT = typename Quad<TS>::T;
     constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels)
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const size_t win_bytes = (size_t)2 * NW * EB;                    // one panel, both groups
     const size_t buf_bytes = (size_t)PT * (win_bytes + kObsTile * sizeof(PairRec));
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t = blockIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.y * kLdsK;
-    const int64_t z = blockIdx.z;
+    const int64_t k0 = kb * kLdsK;
     const int64_t pb = z * p_chunk;
     const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
     const int64_t obase = t * kObsTile + (int64_t)wv * kObsPerWave;
@@ -379,15 +378,52 @@ __global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(const PairRe
     }
 }
 
+template <typename TS>
+__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    gather_lds_body<TS>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+}
+
+// Persistent batched gather: blocks pull work items (case, tile, k-block, split)
+// in list order (longest first) through an atomic counter until the list is
+// exhausted; every block ends when it draws an index past the list.
+template <typename TS>
+__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_persistent(const BatchCase *__restrict__ cases,
+                                                                        const int4 *__restrict__ items,
+                                                                        int n_items, int *__restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int cur;
+    for (;;) {
+        __syncthreads();  // the previous item is finished with LDS
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(cur);
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const int c = __builtin_amdgcn_readfirstlane(w.x);
+        gather_lds_body<TS>(cases[c].gat, __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
+                            __builtin_amdgcn_readfirstlane(w.w), smem_raw);
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
+
 // Zero-padded copy of dJ/dp': gpad[o][k + padlo] = gbar[o][k] for 0 <= k < N_t(o), 0 elsewhere.
-__global__ __launch_bounds__(256) void pad_grad_kernel(const float *__restrict__ gbar, const int32_t *__restrict__ nt,
-                                                       int64_t O, int64_t nt_max, int64_t LR, int64_t padlo,
-                                                       float *__restrict__ gpad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= O * LR) return;
-    const int64_t o = i / LR;
-    const int64_t k = i - o * LR - padlo;
-    gpad[i] = (k >= 0 && k < nt[o]) ? gbar[o * nt_max + k] : 0.f;
+__device__ __forceinline__ void pad_grad_body(const PadArgs &a, int64_t i) {
+    if (i >= a.O * a.LR) return;
+    const int64_t o = i / a.LR;
+    const int64_t k = i - o * a.LR - a.padlo;
+    a.gpad[i] = (k >= 0 && k < a.nt[o]) ? a.gbar[o * a.nt_max + k] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void pad_grad_kernel(PadArgs a) {
+    pad_grad_body(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void pad_grad_batched(const BatchCase *__restrict__ cases,
+                                                        const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    pad_grad_body(cases[c].pad, ((int64_t)blockIdx.x - start[c]) * 256 + threadIdx.x);
 }
 
 // Value of lane l-1 (wavefront shift by one lane; lane 0 receives 0).
@@ -400,18 +436,17 @@ __device__ __forceinline__ float from_prev_lane(float x) {
 // observer, lane l loads gpad at i - n0 (one coalesced load), receives the
 // values at i - n0 - 1 .. i - n0 - 3 from lanes l-1..l-3 by wavefront shifts,
 // applies the four taps and accumulates the 8 channel weights.
-__global__ __launch_bounds__(256) void adj_gather_dpp_kernel(const PairRec *__restrict__ rec_po,
-                                                             const float *__restrict__ gpad, int64_t P, int64_t O,
-                                                             int64_t NS, int64_t LR, int64_t padlo, int64_t nib,
-                                                             float *__restrict__ cbar) {
+__device__ __forceinline__ void adj_gather_dpp_body(const AdjArgs &a, int64_t wave_id) {
+    const PairRec *__restrict__ rec = a.rec;
+    const float *__restrict__ gpad = a.gpad;
+    const int64_t P = a.P, O = a.O, NS = a.NS, LR = a.LR, padlo = a.padlo, nib = a.nib;
+    float *__restrict__ cbar = a.cbar;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t wave_id = (int64_t)blockIdx.x * 4 + wv;
     if (wave_id >= P * nib) return;
     const int64_t p = wave_id / nib;
     const int64_t b = wave_id - p * nib;
     const int64_t i = b * kLdsLanesOut + lane - kLdsHalo;
-    const PairRec *rr = rec_po + p * O;
+    const PairRec *rr = rec + p;  // record of (o, p) at rr[o * P]
     const float *g = gpad + i + padlo;
     float acc[8];
     double accd[8];
@@ -442,7 +477,7 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(const PairRec *__re
     const int64_t O4 = O & ~(int64_t)3;
     int cnt = 0;
     for (int64_t o = 0; o < O4; o += 4) {
-        const PairRec r0 = rr[o], r1 = rr[o + 1], r2 = rr[o + 2], r3 = rr[o + 3];
+        const PairRec r0 = rr[o * P], r1 = rr[(o + 1) * P], r2 = rr[(o + 2) * P], r3 = rr[(o + 3) * P];
         const float v0 = g[o * LR - r0.n0];
         const float v1 = g[(o + 1) * LR - r1.n0];
         const float v2 = g[(o + 2) * LR - r2.n0];
@@ -458,7 +493,7 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(const PairRec *__re
         }
     }
     for (int64_t o = O4; o < O; ++o) {
-        const PairRec r = rr[o];
+        const PairRec r = rr[o * P];
         step(r, g[o * LR - r.n0]);
     }
     flush();
@@ -468,7 +503,31 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(const PairRec *__re
     }
 }
 
+__global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
+    adj_gather_dpp_body(a, (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+}
+
+__global__ __launch_bounds__(256) void adj_gather_dpp_batched(const BatchCase *__restrict__ cases,
+                                                              const int64_t *__restrict__ start, int n) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = find_case(start, n, w);
+    adj_gather_dpp_body(cases[c].adj, w - start[c]);
+}
+
 // out[o][k] = sum_z partial[z][o][k] in fixed order.
+__device__ __forceinline__ void reduce_body(const ReduceArgs &a, int64_t i) {
+    if (i >= a.total) return;
+    double s = 0.0;
+    for (int z = 0; z < a.splits; ++z) s += a.partial[(int64_t)z * a.total + i];
+    a.out[i] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void reduce_batched(const BatchCase *__restrict__ cases,
+                                                      const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    reduce_body(cases[c].red, ((int64_t)blockIdx.x - start[c]) * 256 + threadIdx.x);
+}
+
 __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__restrict__ partial, int splits,
                                                             int64_t total, float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -508,15 +567,13 @@ hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *t
                              int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
                              double *partial, hipStream_t stream) {
     const int64_t p_chunk = (P + splits - 1) / splits;
+    const GatherArgs a{rec_op, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
     dim3 grid((unsigned)((O + kObsTile - 1) / kObsTile), (unsigned)((nt_max + kLdsK - 1) / kLdsK), (unsigned)splits);
-    const size_t esz = coef_type == 1 ? sizeof(float) : sizeof(uint16_t);
-    const size_t shmem = 2 * (size_t)PT * ((size_t)8 * NW * esz + (size_t)kObsTile * sizeof(PairRec));
+    const size_t shmem = gather_lds_shmem(coef_type, NW, PT);
     if (coef_type == 1)
-        gather_lds_kernel<float><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(
-            rec_op, tw, nt, (const float *)coef, P, O, NS, nt_max, p_chunk, NW, PT, partial);
+        gather_lds_kernel<float><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(a);
     else
-        gather_lds_kernel<uint16_t><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(
-            rec_op, tw, nt, (const uint16_t *)coef, P, O, NS, nt_max, p_chunk, NW, PT, partial);
+        gather_lds_kernel<uint16_t><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(a);
     return hipGetLastError();
 }
 
@@ -534,18 +591,45 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
     return hipGetLastError();
 }
 
-hipError_t launch_adj_gather_dpp(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
+hipError_t launch_adj_gather_dpp(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
                                  int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream) {
     const int64_t LR = adj_pad_row(N, NS), padlo = adj_pad_lo(N);
-    pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(gbar, nt, O, nt_max, LR, padlo,
-                                                                                     gpad);
+    const PadArgs pa{gbar, nt, O, nt_max, LR, padlo, gpad};
+    pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nib = (NS + kLdsLanesOut - 1) / kLdsLanesOut;
-    const int64_t waves = P * nib;
-    adj_gather_dpp_kernel<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream>>>(rec_po, gpad, P, O, NS, LR,
-                                                                                     padlo, nib, cbar);
+    const AdjArgs aa{rec_op, gpad, P, O, NS, LR, padlo, nib, cbar};
+    adj_gather_dpp_kernel<<<dim3((unsigned)((P * nib + 3) / 4)), dim3(256), 0, stream>>>(aa);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
+                                const int4 *items, int n_items, int *counter, int grid, size_t shmem,
+                                int64_t blocks_src, int64_t blocks_red, hipStream_t stream) {
+    hipError_t e = launch_batch_source(in_dtype, coef_type, cases, idx.src, idx.n, blocks_src, stream);
+    if (e != hipSuccess) return e;
+    reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (coef_type == 1)
+        gather_lds_persistent<float><<<dim3((unsigned)grid), dim3(kLdsWaves * 64), shmem, stream>>>(cases, items,
+                                                                                                   n_items, counter);
+    else
+        gather_lds_persistent<uint16_t><<<dim3((unsigned)grid), dim3(kLdsWaves * 64), shmem, stream>>>(
+            cases, items, n_items, counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    reduce_batched<<<dim3((unsigned)blocks_red), dim3(256), 0, stream>>>(cases, idx.red, idx.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
+                                int64_t waves_adj, int64_t blocks_pre, int64_t blocks_chain, hipStream_t stream) {
+    pad_grad_batched<<<dim3((unsigned)blocks_pad), dim3(256), 0, stream>>>(cases, idx.pad, idx.n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    adj_gather_dpp_batched<<<dim3((unsigned)((waves_adj + 3) / 4)), dim3(256), 0, stream>>>(cases, idx.adj, idx.n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_batch_source_adjoint(in_dtype, cases, idx.pre, idx.chain, idx.n, blocks_pre, blocks_chain, stream);
 }
 
 }  // namespace fwh

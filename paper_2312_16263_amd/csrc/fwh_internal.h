@@ -56,16 +56,105 @@ constexpr size_t kLdsBudget = 64 * 1024;       // LDS bytes per block (two stage
 constexpr int kMaxPanelsPerStage = 8;
 
 
+// ------------------------------------------------------- per-stage arguments
+// Every stage kernel is a body taking one of these; the single-case kernels
+// pass them by value, the batched kernels pick them from a per-case array.
+
+struct SrcFwdArgs {
+    const void *rho, *u, *pp;  // time-major inputs
+    const double *normal;
+    int64_t P, N, NS;
+    Flow f;
+    const double *cp;
+    void *scr;   // [8][N][P]
+    void *coef;  // [P][2][NS][4]
+};
+
+struct GatherArgs {
+    const PairRec *rec;
+    const int2 *tw;
+    const int32_t *nt;
+    const void *coef;
+    int64_t P, O, NS, nt_max, p_chunk;
+    int NW, PT, splits;
+    double *partial;
+};
+
+struct ReduceArgs {
+    const double *partial;
+    int splits;
+    int64_t total;
+    float *out;
+};
+
+struct PadArgs {
+    const float *gbar;
+    const int32_t *nt;
+    int64_t O, nt_max, LR, padlo;
+    float *gpad;
+};
+
+struct AdjArgs {
+    const PairRec *rec;  // [O][P]
+    const float *gpad;
+    int64_t P, O, NS, LR, padlo, nib;
+    float *cbar;
+};
+
+struct PreAdjArgs {
+    const void *cbar;
+    int64_t P, N, NS;
+    const double *cp;
+    void *scr;
+};
+
+struct ChainArgs {
+    const void *scr;
+    const void *rho, *u;
+    const double *normal;
+    int64_t P, N;
+    Flow f;
+    void *g_rho, *g_u, *g_p;
+};
+
+// One case of a batch (device-resident array) and the block counts of its stages.
+struct BatchCase {
+    SrcFwdArgs src;
+    GatherArgs gat;
+    ReduceArgs red;
+    PadArgs pad;
+    AdjArgs adj;
+    PreAdjArgs pre;
+    ChainArgs chain;
+};
+
+// Case of flattened block b: start[c] <= b < start[c+1] (start has n + 1 entries).
+__device__ __forceinline__ int find_case(const int64_t *start, int n, int64_t b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Block/wave offsets of each case in the flattened batched grids: start[c] .. start[c+1].
+struct BatchIndex {
+    const int64_t *src, *red, *pad, *adj, *pre, *chain;
+    int n;
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return the launch status.
 
 hipError_t launch_delay(const double *y, const double *x_obs, int64_t P, int64_t O, Flow f, double *D,
                         hipStream_t stream);
 hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hipStream_t stream);
-// mode 0: FP64 tables (K64 [O][P][8], W64 [O][P][4], N0 [O][P]); mode 1/2: PairRec [O][P] and [P][O].
+// mode 0: FP64 tables (K64 [O][P][8], W64 [O][P][4], N0 [O][P]); mode 1/2: PairRec [O][P].
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, PairRec *rec_po, hipStream_t stream);
+                         int32_t *N0, PairRec *rec_op, hipStream_t stream);
 
 // Per (observer tile t, panel p): lo/hi of n0 over the tile's observers -> tw[t][p];
 // per block of 256 (t, p) entries the largest hi - lo -> wblk[block].
@@ -92,6 +181,10 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
                                hipStream_t stream);
 // LDS-staged gather; NW = staged window length per channel group (multiple of 64, >= max
 // width + kLdsK + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
+inline size_t gather_lds_shmem(int coef_type, int NW, int PT) {
+    const size_t esz = coef_type == 1 ? 4 : 2;
+    return 2 * (size_t)PT * ((size_t)8 * NW * esz + (size_t)kObsTile * sizeof(PairRec));
+}
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *tw, const int32_t *nt, const void *coef,
                              int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
                              double *partial, hipStream_t stream);
@@ -104,7 +197,7 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
 // Transposed gather via a zero-padded copy of gbar (gpad: [O][adj_pad_row(N, NS)] floats).
 inline int64_t adj_pad_lo(int64_t N) { return N + 4; }
 inline int64_t adj_pad_row(int64_t N, int64_t NS) { return ((N + NS + 64 + 8 + 63) / 64) * 64; }
-hipError_t launch_adj_gather_dpp(const PairRec *rec_po, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
+hipError_t launch_adj_gather_dpp(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
                                  int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream);
 
 // Adjoint of the source stage: coefficient adjoints [8][P][NS] -> gradients (time-major, in_dtype).
@@ -112,5 +205,20 @@ hipError_t launch_adj_gather_dpp(const PairRec *rec_po, const int32_t *nt, const
 hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, const void *rho, const void *u,
                                  const double *normal, int64_t P, int64_t N, int64_t NS, Flow f, const double *cp,
                                  void *scratch, void *g_rho, void *g_u, void *g_p, hipStream_t stream);
+
+// Batched launches over n cases (device arrays `cases`, prefix tables in `idx`).
+// coef_type 1 = float, 2 = bf16; in_dtype 0 = double, 1 = float.  The forward gather
+// is persistent: `grid` blocks pull work items (case, tile, k-block, split) from
+// items[0..n_items) through counter[0], which the launch resets first.
+hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start, int n,
+                               int64_t blocks, hipStream_t stream);
+hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_pre,
+                                       const int64_t *start_chain, int n, int64_t blocks_pre, int64_t blocks_chain,
+                                       hipStream_t stream);
+hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
+                                const int4 *items, int n_items, int *counter, int grid, size_t shmem,
+                                int64_t blocks_src, int64_t blocks_red, hipStream_t stream);
+hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
+                                int64_t waves_adj, int64_t blocks_pre, int64_t blocks_chain, hipStream_t stream);
 
 }  // namespace fwh

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
                                                      const int32_t *__restrict__ nt, int64_t P, int64_t O,
                                                      int64_t N, Flow f, double *__restrict__ K64,
                                                      double *__restrict__ W64, int32_t *__restrict__ N0,
-                                                     PairRec *__restrict__ rec_op, PairRec *__restrict__ rec_po) {
+                                                     PairRec *__restrict__ rec_op) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P * O) return;
     const int64_t o = i / P, p = i - o * P;
@@ -133,7 +133,6 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
         r.n0 = n0;
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
         rec_op[i] = r;
-        rec_po[p * O + o] = r;
     }
 }
 
@@ -190,10 +189,10 @@ hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hip
 
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, PairRec *rec_po, hipStream_t stream) {
+                         int32_t *N0, PairRec *rec_op, hipStream_t stream) {
     const int64_t n = P * O;
     tables_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(mode, y, dS, x_obs, t_start, nt, P, O, N,
-                                                                            f, K64, W64, N0, rec_op, rec_po);
+                                                                            f, K64, W64, N0, rec_op);
     return hipGetLastError();
 }
 

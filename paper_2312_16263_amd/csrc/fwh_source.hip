@@ -81,21 +81,26 @@ __device__ __forceinline__ double source_term(int base, const TIn *__restrict__ 
 }
 
 template <typename TIn, typename TScr, typename TOut>
-__global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__ rho, const TIn *__restrict__ u,
-                                                         const TIn *__restrict__ pp,
-                                                         const double *__restrict__ normal, int64_t P, int64_t N,
-                                                         int64_t NS, Flow f, const double *__restrict__ cp,
-                                                         TScr *__restrict__ scr, TOut *__restrict__ coef) {
+__device__ __forceinline__ void source_fwd_body(const SrcFwdArgs &a, int64_t bx, int by) {
+    const TIn *__restrict__ rho = static_cast<const TIn *>(a.rho);
+    const TIn *__restrict__ u = static_cast<const TIn *>(a.u);
+    const TIn *__restrict__ pp = static_cast<const TIn *>(a.pp);
+    const double *__restrict__ normal = a.normal;
+    const int64_t P = a.P, N = a.N, NS = a.NS;
+    const Flow f = a.f;
+    const double *__restrict__ cp = a.cp;
+    TScr *__restrict__ scr = static_cast<TScr *>(a.scr);
+    TOut *__restrict__ coef = static_cast<TOut *>(a.coef);
     constexpr int CH = 128 / (int)sizeof(TOut);  // time indices per flush (128-byte row segments per channel)
     constexpr int PF = 8;                        // time steps loaded ahead
     constexpr int RS = CH * 4 + 1;               // padded LDS row: [CH][4 channels] + 1
     __shared__ TOut stage[64 * RS];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int ch = blockIdx.y * 4 + wv;
+    const int ch = by * 4 + wv;
     const int base = channel_base(ch);
     const bool deriv = channel_deriv(ch);
-    const int64_t pbase = (int64_t)blockIdx.x * 64;
+    const int64_t pbase = bx * 64;
     const int64_t p = pbase + lane;
     const bool active = p < P;
     const int64_t pc = active ? p : P - 1;
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__
             const int r = t / CH, col = t - r * CH;
             const int64_t prow = pbase + r;
             if (prow < P) {
-                TOut *dst = coef + (((prow * 2 + blockIdx.y) * NS) + i0 + col) * 4;
+                TOut *dst = coef + (((prow * 2 + by) * NS) + i0 + col) * 4;
                 const TOut *src = stage + r * RS + col * 4;
                 dst[0] = src[0];
                 dst[1] = src[1];
@@ -206,16 +211,18 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(const TIn *__restrict__
 //   fbar_r = 6 z_r (r = 1..N-2), fbar_0 = a_0 - z_1, fbar_{N-1} = a_{N-1} - z_{N-2}.
 // Result written time-major into scr [8][N][P].
 template <typename TR>
-__global__ __launch_bounds__(256) void prefilter_adj_kernel(const TR *__restrict__ cbar, int64_t P, int64_t N,
-                                                            int64_t NS, const double *__restrict__ cp,
-                                                            TR *__restrict__ scr) {
+__device__ __forceinline__ void prefilter_adj_body(const PreAdjArgs &a, int64_t bx, int by) {
+    const TR *__restrict__ cbar = static_cast<const TR *>(a.cbar);
+    const int64_t P = a.P, N = a.N, NS = a.NS;
+    const double *__restrict__ cp = a.cp;
+    TR *__restrict__ scr = static_cast<TR *>(a.scr);
     constexpr int CH = 128 / (int)sizeof(TR);
     constexpr int PF = 8;
     __shared__ TR stage[4][64][CH + 1];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int ch = blockIdx.y * 4 + wv;
-    const int64_t pbase = (int64_t)blockIdx.x * 64;
+    const int ch = by * 4 + wv;
+    const int64_t pbase = bx * 64;
     const int64_t p = pbase + lane;
     const bool active = p < P;
     const int64_t pc = active ? p : P - 1;
@@ -286,14 +293,17 @@ __global__ __launch_bounds__(256) void prefilter_adj_kernel(const TR *__restrict
 //   drho = u.n (Qbar + Lbar.w),  du = rho n (Qbar + Lbar.w) + rho u.n Lbar,
 //   dp' = Lbar.n,  with w = u - U0.
 template <typename TR, typename TIn>
-__global__ __launch_bounds__(256) void source_adj_chain_kernel(const TR *__restrict__ scr,
-                                                               const TIn *__restrict__ rho,
-                                                               const TIn *__restrict__ u,
-                                                               const double *__restrict__ normal, int64_t P,
-                                                               int64_t N, Flow f, TIn *__restrict__ g_rho,
-                                                               TIn *__restrict__ g_u, TIn *__restrict__ g_p) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = blockIdx.y;
+__device__ __forceinline__ void source_adj_chain_body(const ChainArgs &a, int64_t bx, int64_t n) {
+    const TR *__restrict__ scr = static_cast<const TR *>(a.scr);
+    const TIn *__restrict__ rho = static_cast<const TIn *>(a.rho);
+    const TIn *__restrict__ u = static_cast<const TIn *>(a.u);
+    const double *__restrict__ normal = a.normal;
+    const int64_t P = a.P, N = a.N;
+    const Flow f = a.f;
+    TIn *__restrict__ g_rho = static_cast<TIn *>(a.g_rho);
+    TIn *__restrict__ g_u = static_cast<TIn *>(a.g_u);
+    TIn *__restrict__ g_p = static_cast<TIn *>(a.g_p);
+    const int64_t p = bx * 256 + threadIdx.x;
     if (p >= P) return;
     const int64_t NP = N * P;
     const double i2h = 1.0 / (2.0 * f.dtau);
@@ -324,26 +334,62 @@ __global__ __launch_bounds__(256) void source_adj_chain_kernel(const TR *__restr
 }
 
 template <typename TIn, typename TScr, typename TOut>
-hipError_t source_launch_t(const void *rho, const void *u, const void *pp, const double *normal, int64_t P, int64_t N,
-                           int64_t NS, Flow f, const double *cp, void *scratch, void *coef, hipStream_t stream) {
-    dim3 grid((unsigned)((P + 63) / 64), 2);
-    source_fwd_kernel<TIn, TScr, TOut><<<grid, dim3(256), 0, stream>>>(
-        (const TIn *)rho, (const TIn *)u, (const TIn *)pp, normal, P, N, NS, f, cp, (TScr *)scratch, (TOut *)coef);
+__global__ __launch_bounds__(256) void source_fwd_kernel(SrcFwdArgs a) {
+    source_fwd_body<TIn, TScr, TOut>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename TIn, typename TScr, typename TOut>
+__global__ __launch_bounds__(256) void source_fwd_batched(const BatchCase *__restrict__ cases,
+                                                          const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    source_fwd_body<TIn, TScr, TOut>(cases[c].src, local >> 1, (int)(local & 1));
+}
+
+template <typename TR>
+__global__ __launch_bounds__(256) void prefilter_adj_kernel(PreAdjArgs a) {
+    prefilter_adj_body<TR>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename TR>
+__global__ __launch_bounds__(256) void prefilter_adj_batched(const BatchCase *__restrict__ cases,
+                                                             const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    prefilter_adj_body<TR>(cases[c].pre, local >> 1, (int)(local & 1));
+}
+
+template <typename TR, typename TIn>
+__global__ __launch_bounds__(256) void source_adj_chain_kernel(ChainArgs a) {
+    source_adj_chain_body<TR, TIn>(a, blockIdx.x, blockIdx.y);
+}
+
+// flattened: block -> (case, frame n, panel block)
+template <typename TR, typename TIn>
+__global__ __launch_bounds__(256) void source_adj_chain_batched(const BatchCase *__restrict__ cases,
+                                                                const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    const int64_t pblocks = (cases[c].chain.P + 255) / 256;
+    const int64_t fr = local / pblocks;
+    source_adj_chain_body<TR, TIn>(cases[c].chain, local - fr * pblocks, fr);
+}
+
+template <typename TIn, typename TScr, typename TOut>
+hipError_t source_launch_t(const SrcFwdArgs &a, hipStream_t stream) {
+    dim3 grid((unsigned)((a.P + 63) / 64), 2);
+    source_fwd_kernel<TIn, TScr, TOut><<<grid, dim3(256), 0, stream>>>(a);
     return hipGetLastError();
 }
 
 template <typename TR, typename TIn>
-hipError_t source_adj_launch_t(const void *cbar, const void *rho, const void *u, const double *normal, int64_t P,
-                               int64_t N, int64_t NS, Flow f, const double *cp, void *scratch, void *g_rho, void *g_u,
-                               void *g_p, hipStream_t stream) {
-    dim3 grid1((unsigned)((P + 63) / 64), 2);
-    prefilter_adj_kernel<TR><<<grid1, dim3(256), 0, stream>>>((const TR *)cbar, P, N, NS, cp, (TR *)scratch);
+hipError_t source_adj_launch_t(const PreAdjArgs &pa, const ChainArgs &ca, hipStream_t stream) {
+    dim3 grid1((unsigned)((pa.P + 63) / 64), 2);
+    prefilter_adj_kernel<TR><<<grid1, dim3(256), 0, stream>>>(pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid2((unsigned)((P + 255) / 256), (unsigned)N);
-    source_adj_chain_kernel<TR, TIn><<<grid2, dim3(256), 0, stream>>>((const TR *)scratch, (const TIn *)rho,
-                                                                      (const TIn *)u, normal, P, N, f, (TIn *)g_rho,
-                                                                      (TIn *)g_u, (TIn *)g_p);
+    dim3 grid2((unsigned)((ca.P + 255) / 256), (unsigned)ca.N);
+    source_adj_chain_kernel<TR, TIn><<<grid2, dim3(256), 0, stream>>>(ca);
     return hipGetLastError();
 }
 
@@ -352,27 +398,57 @@ hipError_t source_adj_launch_t(const void *cbar, const void *rho, const void *u,
 hipError_t launch_source(int in_dtype, int coef_type, const void *rho, const void *u, const void *pp,
                          const double *normal, int64_t P, int64_t N, int64_t NS, Flow f, const double *cp,
                          void *scratch, void *coef, hipStream_t stream) {
+    const SrcFwdArgs a{rho, u, pp, normal, P, N, NS, f, cp, scratch, coef};
     if (in_dtype == 0) {
-        if (coef_type == 0) return source_launch_t<double, double, double>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
-        if (coef_type == 1) return source_launch_t<double, float, float>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
-        return source_launch_t<double, float, bf16s>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+        if (coef_type == 0) return source_launch_t<double, double, double>(a, stream);
+        if (coef_type == 1) return source_launch_t<double, float, float>(a, stream);
+        return source_launch_t<double, float, bf16s>(a, stream);
     }
-    if (coef_type == 0) return source_launch_t<float, double, double>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
-    if (coef_type == 1) return source_launch_t<float, float, float>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
-    return source_launch_t<float, float, bf16s>(rho, u, pp, normal, P, N, NS, f, cp, scratch, coef, stream);
+    if (coef_type == 0) return source_launch_t<float, double, double>(a, stream);
+    if (coef_type == 1) return source_launch_t<float, float, float>(a, stream);
+    return source_launch_t<float, float, bf16s>(a, stream);
 }
 
 hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, const void *rho, const void *u,
                                  const double *normal, int64_t P, int64_t N, int64_t NS, Flow f, const double *cp,
                                  void *scratch, void *g_rho, void *g_u, void *g_p, hipStream_t stream) {
+    const PreAdjArgs pa{cbar, P, N, NS, cp, scratch};
+    const ChainArgs ca{scratch, rho, u, normal, P, N, f, g_rho, g_u, g_p};
     if (real_type == 0) {
-        if (in_dtype == 0)
-            return source_adj_launch_t<double, double>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
-        return source_adj_launch_t<double, float>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+        if (in_dtype == 0) return source_adj_launch_t<double, double>(pa, ca, stream);
+        return source_adj_launch_t<double, float>(pa, ca, stream);
     }
+    if (in_dtype == 0) return source_adj_launch_t<float, double>(pa, ca, stream);
+    return source_adj_launch_t<float, float>(pa, ca, stream);
+}
+
+// Batched source stages (FP32/BF16 modes: float scratch).
+hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start, int n,
+                               int64_t blocks, hipStream_t stream) {
+    const dim3 g((unsigned)blocks), b(256);
+    if (in_dtype == 0) {
+        if (coef_type == 1) source_fwd_batched<double, float, float><<<g, b, 0, stream>>>(cases, start, n);
+        else source_fwd_batched<double, float, bf16s><<<g, b, 0, stream>>>(cases, start, n);
+    } else {
+        if (coef_type == 1) source_fwd_batched<float, float, float><<<g, b, 0, stream>>>(cases, start, n);
+        else source_fwd_batched<float, float, bf16s><<<g, b, 0, stream>>>(cases, start, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_pre,
+                                       const int64_t *start_chain, int n, int64_t blocks_pre, int64_t blocks_chain,
+                                       hipStream_t stream) {
+    prefilter_adj_batched<float><<<dim3((unsigned)blocks_pre), dim3(256), 0, stream>>>(cases, start_pre, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (in_dtype == 0)
-        return source_adj_launch_t<float, double>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
-    return source_adj_launch_t<float, float>(cbar, rho, u, normal, P, N, NS, f, cp, scratch, g_rho, g_u, g_p, stream);
+        source_adj_chain_batched<float, double><<<dim3((unsigned)blocks_chain), dim3(256), 0, stream>>>(cases,
+                                                                                                      start_chain, n);
+    else
+        source_adj_chain_batched<float, float><<<dim3((unsigned)blocks_chain), dim3(256), 0, stream>>>(cases,
+                                                                                                     start_chain, n);
+    return hipGetLastError();
 }
 
 }  // namespace fwh

@@ -1,0 +1,131 @@
+"""The batched launch (many uneven cases; persistent forward gather over a
+longest-first work list; forward + dJ/dp' + adjoint captured in one HIP graph)
+against the FP64 oracle, against single-case launches, and graph replays
+against the eager result."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import make_plan, rel_l2, to_device, valid_mask
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-3}
+
+
+def _small_cases():
+    return configs.batched_cases(n_cases=6, seed=11, p_range=(200, 3000), n_range=(160, 600), o_range=(3, 70),
+                                 dtau=1.0 / 64.0)
+
+
+_data = {}
+
+
+def _case_data(cases):
+    key = id(cases)
+    if key not in _data:
+        out = []
+        for c in cases:
+            rho, u, pp = c.data()
+            p_ref, ts, nt = oracle.forward(c.surface, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0, rho, u, pp)
+            out.append((rho, u, pp, p_ref, nt))
+        _data[key] = out
+    return _data[key]
+
+
+CASES = _small_cases()
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_batch_forward_adjoint_vs_oracle_and_single(mode):
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    data = _case_data(CASES)
+    print(f"[batch] mode={mode} cases=" + ", ".join(f"{c.n_panels}x{c.n_obs}x{c.n_tau}" for c in CASES), flush=True)
+    plans = [make_plan(c, mode) for c in CASES]
+    inputs = [to_device(d[:3]) for d in data]
+    batch = fwh.Batch(plans, inputs, item_units=2e5)
+    info = batch.info()
+    print(f"    items={info['items']} grid={info['grid']} units={info['units']:.3e}", flush=True)
+    p_b = [t.clone() for t in batch.forward()]
+    for i, (c, d) in enumerate(zip(CASES, data)):
+        p_ref, nt = d[3], d[4]
+        m = valid_mask(nt, p_ref.shape[1])
+        err = rel_l2(p_b[i].double().cpu().numpy(), p_ref, m)
+        single = plans[i].forward(*inputs[i])
+        err_s = rel_l2(p_b[i].double().cpu().numpy(), single.double().cpu().numpy(), m)
+        print(f"    case {i} {c.name}: rel L2 vs oracle {err:.3e}, vs single-case launch {err_s:.3e}", flush=True)
+        assert err <= TOL[mode], err
+        assert err_s <= 1e-6, err_s
+        assert np.all(p_b[i].cpu().numpy()[m == 0] == 0.0)
+    # adjoint: identical kernels per case, so bitwise equal to single-case launches
+    for po, gp in zip(batch.p_out, batch.grad_p):
+        torch.mul(po, 2.0, out=gp)
+    g_b = [tuple(x.clone() for x in g) for g in batch.adjoint()]
+    torch.cuda.synchronize()
+    for i in range(len(CASES)):
+        g_s = plans[i].adjoint(*inputs[i], batch.grad_p[i])
+        for a, b in zip(g_b[i], g_s):
+            assert torch.equal(a, b)
+    # and the gradient against the oracle's
+    for i, (c, d) in enumerate(zip(CASES, data)):
+        gbar = batch.grad_p[i].double().cpu().numpy()
+        g_ref = oracle.adjoint(c.surface, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0, *[a.astype(np.float64) for a in d[:3]],
+                               gbar)
+        for gv, gr in zip(g_b[i], g_ref):
+            err = rel_l2(gv.double().cpu().numpy(), gr)
+            assert err <= 1e-5, (i, err)
+
+
+def test_batch_graph_replays_match_eager():
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    data = _case_data(CASES)
+    plans = [make_plan(c, "bf16") for c in CASES]
+    inputs = [to_device(d[:3]) for d in data]
+    batch = fwh.Batch(plans, inputs, item_units=2e5)
+    batch.step()
+    torch.cuda.synchronize()
+    ref_p = [t.clone() for t in batch.p_out]
+    ref_g = [tuple(x.clone() for x in g) for g in batch.grads]
+    graph = batch.capture()
+    for rep in range(3):
+        # the program's own eager work between replays
+        for t in batch.p_out:
+            t.fill_(float("nan"))
+        for g in batch.grads:
+            for x in g:
+                x.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(batch.p_out, ref_p):
+            assert torch.equal(a, b), f"replay {rep}: forward differs"
+        for g, r in zip(batch.grads, ref_g):
+            for a, b in zip(g, r):
+                assert torch.equal(a, b), f"replay {rep}: gradient differs"
+        print(f"    replay {rep} matches the eager step", flush=True)
+
+
+def test_batch_autotune_keeps_results(tmp_path):
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    data = _case_data(CASES)
+    plans = [make_plan(c, "f32") for c in CASES]
+    inputs = [to_device(d[:3]) for d in data]
+    batch = fwh.Batch(plans, inputs)
+    iu, bpc, table = fwh.autotune(batch, candidates=[(1e5, 2), (1e6, 1), (1e7, 2)], reps=2,
+                                  cache_path=str(tmp_path / "tune.json"))
+    print(f"    autotune table {table} -> {iu:.0e} units/item, {bpc} blocks/CU", flush=True)
+    p = [t.clone() for t in batch.forward()]
+    torch.cuda.synchronize()
+    for i, d in enumerate(data):
+        m = valid_mask(d[4], d[3].shape[1])
+        assert rel_l2(p[i].double().cpu().numpy(), d[3], m) <= TOL["f32"]
+    # cached choice is reused
+    iu2, bpc2, _ = fwh.autotune(batch, cache_path=str(tmp_path / "tune.json"))
+    assert (iu2, bpc2) == (iu, bpc)

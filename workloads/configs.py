@@ -92,3 +92,35 @@ def airfoil_broadband(n_points=1200, n_stations=200, n_tau=4096, n_obs=72, seed=
 def by_name(name: str) -> Case:
     return {"monopole_small": monopole_small, "dipole_sphere": dipole_sphere,
             "airfoil_broadband": airfoil_broadband}[name]()
+
+
+def batched_cases(n_cases=64, seed=4, p_range=(2048, 65536), n_range=(512, 4096), o_range=(8, 360),
+                  mach_range=(0.1, 0.5), aoa_range=(0.0, 10.0), dtau=1.0 / 128.0):
+    """Seeded uneven cases for the batched launch: surface kind (analytic sphere
+    with a monopole or dipole, or an extruded Joukowski contour with broadband
+    data), panel count log-uniform in p_range, record length uniform in
+    n_range, observer count uniform in o_range, Mach number and AoA uniform.
+    Spheres have n_phi = 2 n_theta; contours use about 6 points per station.
+    Observers sit on a circle of radius 10 to 100 (spheres) or 10 chords
+    (contours).  FP32 surface data."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(n_cases):
+        P_target = float(np.exp(rng.uniform(np.log(p_range[0]), np.log(p_range[1]))))
+        N = int(rng.integers(n_range[0], n_range[1] + 1))
+        O = int(rng.integers(o_range[0], o_range[1] + 1))
+        mach = float(rng.uniform(*mach_range))
+        aoa = float(rng.uniform(*aoa_range))
+        kind = ["monopole", "dipole", "broadband"][int(rng.integers(0, 3))]
+        if kind == "broadband":
+            stations = max(4, int(round(np.sqrt(P_target / 6.0))))
+            points = max(16, int(round(P_target / stations)))
+            surf = surfaces.extruded_contour(surfaces.joukowski_contour(points), stations, 1.0 / 9.0)
+            x = surfaces.observer_circle(O, 10.0, center=(0.5, 0.0, 0.0), start_deg=float(rng.uniform(0, 360)))
+        else:
+            nth = max(4, int(round(np.sqrt(P_target / 2.0))))
+            surf = surfaces.sphere(1.0, nth, 2 * nth)
+            x = surfaces.observer_circle(O, float(rng.uniform(10.0, 100.0)), start_deg=float(rng.uniform(0, 360)))
+        cases.append(Case(f"batch{i:02d}_{kind}", surf, x, mach, aoa, dtau, N, kind=kind,
+                          seed=int(seed * 1000 + i), data_dtype=np.float32))
+    return cases
