@@ -52,6 +52,109 @@ def run_steps(plan, d, steps, sync):
     sync()
 
 
+def bench_airfoil(steps, sync):
+    """Airfoil-like extruded Joukowski surface with broadband data (240000
+    panels, 4096 samples, 72 observers), FP32 and BF16 coefficient storage:
+    step time and error against the FP64 oracle on two sampled observers."""
+    import torch
+
+    import oracle
+    import paper_2312_16263_amd as fwh
+    from workloads import configs
+    c = configs.airfoil_broadband()
+    log(f"[bench] airfoil: P={c.n_panels} O={c.n_obs} N={c.n_tau}")
+    d = c.data_device("cuda")
+    sync()
+    host = [t.cpu().numpy() for t in d]
+    sample = np.array([0, 36])
+    p_ref, _, nt_ref = oracle.forward(c.surface, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0, *host, obs_idx=sample)
+    del host
+    out = {"workload": "Joukowski contour (1200 points, chord 1) x 200 stations = 240000 panels, N=4096, 72 "
+                       "observers at R=10, M0=0.17, AoA=5.5 deg; seeded broadband FP32 data (k^-5/3, RMS 1%)"}
+    for mode in ("f32", "bf16"):
+        plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
+                        c.n_tau, mode=mode)
+        U = int(c.n_panels * int(plan.window.n_t.sum()))
+        run_steps(plan, d, 1, sync)
+        plan.profile(True)
+        t0 = time.perf_counter()
+        run_steps(plan, d, steps, sync)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = plan.profile_read()
+        p = plan.forward(*d).double().cpu().numpy()[sample]
+        m = (np.arange(p_ref.shape[1])[None, :] < nt_ref[sample][:, None]).astype(float)
+        err = rel_l2(p, p_ref, m)
+        out[mode] = {"value": U / (ms * 1e-3), "ms_per_step": ms, "err_vs_oracle": err,
+                     "stage_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in st.items()}}
+        log(f"[bench] airfoil {mode}: {ms:.2f} ms/step, {U / (ms * 1e-3):.3e} units/s, err {err:.3e}")
+        out["units_per_step"] = U
+        del plan
+        torch.cuda.empty_cache()
+    del d
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(replays, sync):
+    """64 seeded uneven cases (spheres with analytic sources, extruded contours
+    with broadband data; P 2048-32768, N 512-2048, O 8-360, M0 0.1-0.5, AoA
+    0-10 deg), BF16 storage, one step (forward, dJ/dp', adjoint) of all cases
+    as one HIP-graph replay, against 64 separate plain FP64 steps."""
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    from workloads import configs
+    cases = configs.batched_cases(p_range=(2048, 32768), n_range=(512, 2048))
+    t0 = time.time()
+    inputs = [c.data_device("cuda") for c in cases]
+    sync()
+    log(f"[bench] batch: {len(cases)} cases generated ({time.time() - t0:.1f} s)")
+    plans = [fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
+                      c.n_tau, mode="bf16") for c in cases]
+    batch = fwh.Batch(plans, inputs)
+    iu, bpc, table = fwh.autotune(batch, candidates=[(1e6, 2), (4e6, 2), (16e6, 2), (4e6, 1)], reps=2)
+    info = batch.info()
+    graph = batch.capture()
+    graph.replay()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        graph.replay()
+    sync()
+    ms = (time.perf_counter() - t0) * 1e3 / replays
+    p_b = [t.double().cpu().numpy() for t in batch.p_out]
+    del graph, batch
+    del plans
+    torch.cuda.empty_cache()
+    # 64 separate plain FP64 steps (setup + forward + adjoint per case)
+    t_plain = 0.0
+    errs = []
+    for c, d, pb in zip(cases, inputs, p_b):
+        plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
+                        c.n_tau, mode="f64")
+        sync()
+        t1 = time.perf_counter()
+        run_steps(plan, d, 1, sync)
+        t_plain += time.perf_counter() - t1
+        p64 = plan.forward(*d).cpu().numpy()
+        m = (np.arange(p64.shape[1])[None, :] < plan.window.n_t[:, None]).astype(float)
+        errs.append(rel_l2(pb, p64, m))
+        del plan
+        torch.cuda.empty_cache()
+    U = info["units"]
+    out = {"workload": "64 seeded uneven cases (sphere monopole/dipole and extruded-contour broadband; P 2048-32768, "
+                       "N 512-2048, O 8-360, M0 0.1-0.5, AoA 0-10 deg), BF16 storage, FP32 inputs",
+           "units_per_step": U, "ms_per_step": ms, "value": U / (ms * 1e-3),
+           "plain_f64_64_launches": {"ms_per_step": t_plain * 1e3, "value": U / t_plain},
+           "speedup_vs_plain_f64": t_plain * 1e3 / ms, "max_rel_l2_vs_plain_f64": max(errs),
+           "work_items": info["items"], "grid": info["grid"], "autotune": {"choice": [iu, bpc], "table": table}}
+    log(f"[bench] batch: {ms:.2f} ms/step ({U / (ms * 1e-3):.3e} units/s) vs 64 plain FP64 steps "
+        f"{t_plain * 1e3:.1f} ms; max rel L2 vs FP64 {max(errs):.3e}")
+    del inputs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,10 +164,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the airfoil and batched workloads")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: 1 warmup + `--steps` FP32 steps, then a 1 GiB device copy "
                          "(the reference kernel for HBM byte counters); prints no JSON")
     ap.add_argument("--mode", default="f32", choices=["f32", "bf16"], help="mode of the profile run")
+    ap.add_argument("--workload", default="dipole_sphere", choices=["dipole_sphere", "airfoil_broadband"],
+                    help="workload of the profile run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -80,16 +186,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    c = configs.dipole_sphere()
-    log(f"[bench] {fwh.version()}; workload {c.name}: P={c.n_panels} O={c.n_obs} N={c.n_tau}")
-    t0 = time.time()
-    rho, u, pp = c.data()
-    d = [torch.from_numpy(a).to(dev) for a in (rho, u, pp)]
-    torch.cuda.synchronize()
-    log(f"[bench] inputs generated and resident in HBM ({time.time() - t0:.1f} s)")
-
     sync = torch.cuda.synchronize
     if args.profile_run:
+        c = configs.by_name(args.workload)
+        log(f"[bench] profile run: workload {c.name}: P={c.n_panels} O={c.n_obs} N={c.n_tau}")
+        d = list(c.data_device(dev))
         plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
                         c.n_tau, mode=args.mode)
         run_steps(plan, d, 1 + args.steps, sync)
@@ -99,6 +200,14 @@ def main():
         sync()
         log(f"[bench] profile run done: {1 + args.steps} steps ({args.mode}), then a 1 GiB copy")
         return
+    c = configs.dipole_sphere()
+    log(f"[bench] {fwh.version()}; workload {c.name}: P={c.n_panels} O={c.n_obs} N={c.n_tau}")
+    t0 = time.time()
+    rho, u, pp = c.data()
+    d = [torch.from_numpy(a).to(dev) for a in (rho, u, pp)]
+    torch.cuda.synchronize()
+    log(f"[bench] inputs generated and resident in HBM ({time.time() - t0:.1f} s)")
+
     plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
                     c.n_tau, mode="f32")
     nt = plan.window.n_t
@@ -192,6 +301,13 @@ def main():
                          f"excludes input generation", "seconds": t_cpu}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} units/s on {cpu['cores']} threads")
 
+    extra = {}
+    if not args.no_extra:
+        del plan
+        torch.cuda.empty_cache()
+        extra["airfoil_broadband"] = bench_airfoil(3, sync)
+        extra["batched"] = bench_batch(5, sync)
+
     out = {
         "metric": "FW-H panel-obs-samples/s (fwd, adjoint) vs FP64 plain at stated err; % HBM peak",
         "value": value, "unit": "panel-obs-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -213,6 +329,7 @@ def main():
         "speedup_vs_plain_f64": (value / plain["value"]) if plain else None,
         "oracle_sampled_forward_s": t_o,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

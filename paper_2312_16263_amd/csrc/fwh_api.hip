@@ -427,7 +427,7 @@ struct fwh_batch {
     double item_units = 4.0e6;
     int blocks_per_cu = 2;
     int64_t max_items = 0, n_items = 0, units = 0, grid = 0;
-    int64_t blocks_src = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_pre = 0, blocks_chain = 0;
+    int64_t blocks_src = 0, blocks_srcg = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_pre = 0, blocks_chain = 0;
     size_t shmem = 0;
     size_t off_cases = 0, off_idx = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
     char *ws = nullptr;
@@ -481,7 +481,7 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
         return o;
     };
     b->off_cases = take((size_t)n * sizeof(fwh::BatchCase));
-    b->off_idx = take((size_t)6 * (n + 1) * sizeof(int64_t));
+    b->off_idx = take((size_t)7 * (n + 1) * sizeof(int64_t));
     b->off_items = take((size_t)max_items * sizeof(int4));
     b->off_counter = take(sizeof(int));
     b->ws_bytes = off;
@@ -509,9 +509,9 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     const int n = b->n;
     const int coef_type = b->mode == FWH_MODE_F32 ? 1 : 2;
     std::vector<fwh::BatchCase> desc((size_t)n);
-    std::vector<int64_t> idx((size_t)6 * (n + 1), 0);
+    std::vector<int64_t> idx((size_t)7 * (n + 1), 0);
     int64_t *s_src = idx.data(), *s_red = s_src + (n + 1), *s_pad = s_red + (n + 1), *s_adj = s_pad + (n + 1),
-            *s_pre = s_adj + (n + 1), *s_chain = s_pre + (n + 1);
+            *s_pre = s_adj + (n + 1), *s_chain = s_pre + (n + 1), *s_srcg = s_chain + (n + 1);
     struct Item {
         double cost;
         int4 w;
@@ -545,7 +545,9 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         d.pre = fwh::PreAdjArgs{pl->ws + pl->off_coef, P, N, NS, pl->at<double>(pl->off_cp), pl->ws + pl->off_scr};
         d.chain = fwh::ChainArgs{pl->ws + pl->off_scr, k.rho, k.u, pl->at<double>(pl->off_n), P, N, pl->flow,
                                  k.g_rho, k.g_u, k.g_p};
-        s_src[c + 1] = s_src[c] + ceil_div(P, 64) * 2;
+        const int64_t src_int = fwh::src_interior_chunks(N);
+        s_src[c + 1] = s_src[c] + ceil_div(P, fwh::kSrcPanels) * src_int;
+        s_srcg[c + 1] = s_srcg[c] + ceil_div(P, fwh::kSrcPanels) * (NS / fwh::kSrcTC - src_int);
         s_red[c + 1] = s_red[c] + ceil_div(O * ntm, 256);
         s_pad[c + 1] = s_pad[c] + ceil_div(O * LR, 256);
         s_adj[c + 1] = s_adj[c] + P * nib;
@@ -570,6 +572,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     for (size_t i = 0; i < items.size(); ++i) wl[i] = items[i].w;
     b->n_items = (int64_t)wl.size();
     b->blocks_src = s_src[n];
+    b->blocks_srcg = s_srcg[n];
     b->blocks_red = s_red[n];
     b->blocks_pad = s_pad[n];
     b->waves_adj = s_adj[n];
@@ -596,7 +599,8 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
 static fwh::BatchIndex batch_index(const fwh_batch *b) {
     const int64_t *base = b->at<int64_t>(b->off_idx);
     const int64_t m = b->n + 1;
-    return fwh::BatchIndex{base, base + m, base + 2 * m, base + 3 * m, base + 4 * m, base + 5 * m, b->n};
+    return fwh::BatchIndex{base,         base + m,     base + 2 * m, base + 3 * m,
+                           base + 4 * m, base + 5 * m, base + 6 * m, b->n};
 }
 
 int fwh_batch_forward(fwh_batch *b, void *stream_) {
@@ -605,7 +609,8 @@ int fwh_batch_forward(fwh_batch *b, void *stream_) {
     hipError_t e = fwh::launch_batch_forward(b->in_dtype == FWH_F64 ? 0 : 1, b->mode == FWH_MODE_F32 ? 1 : 2,
                                              b->at<fwh::BatchCase>(b->off_cases), batch_index(b),
                                              b->at<int4>(b->off_items), (int)b->n_items, b->at<int>(b->off_counter),
-                                             (int)b->grid, b->shmem, b->blocks_src, b->blocks_red, as_stream(stream_));
+                                             (int)b->grid, b->shmem, b->blocks_src, b->blocks_srcg, b->blocks_red,
+                                             as_stream(stream_));
     if (e) return hip_fail("fwh_batch_forward", e);
     return FWH_OK;
 }

@@ -606,8 +606,9 @@ hipError_t launch_adj_gather_dpp(const PairRec *rec_op, const int32_t *nt, const
 
 hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
-                                int64_t blocks_src, int64_t blocks_red, hipStream_t stream) {
-    hipError_t e = launch_batch_source(in_dtype, coef_type, cases, idx.src, idx.n, blocks_src, stream);
+                                int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream) {
+    hipError_t e =
+        launch_batch_source(in_dtype, coef_type, cases, idx.src, idx.srcg, idx.n, blocks_src, blocks_srcg, stream);
     if (e != hipSuccess) return e;
     reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -141,7 +141,7 @@ __device__ __forceinline__ int find_case(const int64_t *start, int n, int64_t b)
 
 // Block/wave offsets of each case in the flattened batched grids: start[c] .. start[c+1].
 struct BatchIndex {
-    const int64_t *src, *red, *pad, *adj, *pre, *chain;
+    const int64_t *src, *red, *pad, *adj, *pre, *chain, *srcg;  // block starts per case
     int n;
 };
 
@@ -162,6 +162,29 @@ hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 
                               hipStream_t stream);
 inline int64_t tile_window_blocks(int64_t P, int64_t O) {
     return ((O + kObsTile - 1) / kObsTile * P + 255) / 256;
+}
+
+// Chunked source stage (FP32/BF16 modes).  A block owns kSrcPanels panels and
+// the kSrcTC coefficient indices [i0, i0 + kSrcTC) (NS is a multiple of 64); its
+// recurrences run over the rows [i0 - 1 - kSrcH, i0 + kSrcTC - 1 + kSrcH].
+// Interior chunks (every row, and every source term read, away from the record
+// ends and past the first kSrcPivotRows rows) take a branch-free unrolled
+// kernel; the others (the first chunk, the last one or two, all of them for
+// short records) a general kernel.
+constexpr int kSrcPanels = 32;
+constexpr int kSrcTC = 64;
+constexpr int kSrcH = 16;
+constexpr int kSrcW = kSrcTC + 2 * kSrcH + 1;
+constexpr int kSrcPivotRows = 16;
+// interior chunks are k = 1 .. src_interior_chunks(N): i0 >= kSrcPivotRows + kSrcH + 1
+// and i0 - 1 - kSrcH + kSrcW + 2 <= N - 1
+__host__ __device__ inline int64_t src_interior_chunks(int64_t N) {
+    const int64_t top = N - 1 - (kSrcW + 2) + 1 + kSrcH;  // largest admissible i0
+    return top >= kSrcTC ? top / kSrcTC : 0;
+}
+// general chunk g -> chunk index: the first chunk, then those above the interior ones
+__host__ __device__ inline int64_t src_general_chunk(int64_t g, int64_t n_interior) {
+    return g == 0 ? 0 : n_interior + g;
 }
 
 // Source terms + derivatives + natural-spline prefilter -> coefficients [P][2][NS][4]
@@ -210,14 +233,16 @@ hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, 
 // coef_type 1 = float, 2 = bf16; in_dtype 0 = double, 1 = float.  The forward gather
 // is persistent: `grid` blocks pull work items (case, tile, k-block, split) from
 // items[0..n_items) through counter[0], which the launch resets first.
-hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start, int n,
-                               int64_t blocks, hipStream_t stream);
+// interior-chunk blocks then general-chunk blocks of the chunked source stage
+hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start_int,
+                               const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
+                               hipStream_t stream);
 hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_pre,
                                        const int64_t *start_chain, int n, int64_t blocks_pre, int64_t blocks_chain,
                                        hipStream_t stream);
 hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
-                                int64_t blocks_src, int64_t blocks_red, hipStream_t stream);
+                                int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream);
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
                                 int64_t waves_adj, int64_t blocks_pre, int64_t blocks_chain, hipStream_t stream);
 

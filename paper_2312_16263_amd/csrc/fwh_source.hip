@@ -202,6 +202,250 @@ __device__ __forceinline__ void source_fwd_body(const SrcFwdArgs &a, int64_t bx,
     }
 }
 
+// ------------------------------------------------------- chunked source stage
+// FP32 and BF16 coefficient modes (the plain FP64 form keeps the exact
+// sequential kernel above).  Geometry in fwh_internal.h: a block owns 32 panels
+// and 64 coefficient indices; wave w handles base quantity w (Q, L_1, L_2, L_3)
+// with lanes 0-31 on its derivative channel and lanes 32-63 on the channel
+// itself, so the source terms are wave-uniform.  Each thread runs the forward
+// elimination over the rows [R0, R0 + kSrcW) (pivots from the exact table, so a
+// window that reaches row 1 is exact) and back-substitutes from the top of the
+// window (exact when it reaches row N-2).  Starting elsewhere from zero moves
+// the chunk's coefficients by about (2 - sqrt 3)^kSrcH = 7e-10 of their local
+// scale, below the FP32/BF16 storage rounding.  No scratch: the coefficients
+// leave through an LDS tile [kSrcTC][257] as 16-byte (8-byte for BF16) quads
+// of the interleaved layout.
+constexpr int kSrcRS = 257;  // LDS row: 8 channels x 32 panels + 1
+constexpr int kSrcPF = 8;    // source-term rows loaded ahead
+
+// Per-thread source-term form X = a p' + rho (b.u - g) u.n - d, which covers
+// Q (a = 0, b = 0, g = -1, d = U0.n) and L_i (a = n_i, b = e_i, g = U0_i, d = 0).
+template <typename TIn>
+struct SrcLane {
+    const TIn *rho, *u, *pp;
+    int64_t NP;
+    double nx, ny, nz, al, b1, b2, b3, gm, dl;
+    double s_der, s_val;  // f = s_der (X+ - X-) + s_val X
+    int ch;               // channel index (0..7)
+    __device__ __forceinline__ SrcLane(const SrcFwdArgs &a, int64_t pc) {
+        rho = static_cast<const TIn *>(a.rho) + pc;
+        u = static_cast<const TIn *>(a.u) + pc;
+        pp = static_cast<const TIn *>(a.pp) + pc;
+        NP = a.N * a.P;
+        const int w = threadIdx.x >> 6;
+        const bool der = (threadIdx.x & 32) == 0;
+        ch = w == 0 ? (der ? 0 : 1) : (der ? 1 + w : 4 + w);
+        nx = a.normal[3 * pc];
+        ny = a.normal[3 * pc + 1];
+        nz = a.normal[3 * pc + 2];
+        const double Ux = a.f.ca, Uy = a.f.sa;
+        al = w == 1 ? nx : (w == 2 ? ny : (w == 3 ? nz : 0.0));
+        b1 = w == 1 ? 1.0 : 0.0;
+        b2 = w == 2 ? 1.0 : 0.0;
+        b3 = w == 3 ? 1.0 : 0.0;
+        gm = w == 0 ? -1.0 : (w == 1 ? Ux : (w == 2 ? Uy : 0.0));
+        dl = w == 0 ? Ux * nx + Uy * ny : 0.0;
+        s_der = der ? 1.0 / (2.0 * a.f.dtau) : 0.0;
+        s_val = der ? 0.0 : 1.0;
+    }
+    // source term at time row m (offset m * P from this panel)
+    __device__ __forceinline__ double X(int64_t off) const {
+        const double r = (double)rho[off];
+        const double u1 = (double)u[off], u2 = (double)u[NP + off], u3 = (double)u[2 * NP + off];
+        const double pv = (double)pp[off];
+        const double un = u1 * nx + u2 * ny + u3 * nz;
+        const double bu = b1 * u1 + b2 * u2 + b3 * u3 - gm;
+        return al * pv + r * bu * un - dl;
+    }
+};
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void store_quad(float *dst, const float *v) {
+    *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store_quad(bf16s *dst, const float *v) {
+    uint2 w;
+    w.x = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+    w.y = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+    *reinterpret_cast<uint2 *>(dst) = w;
+}
+
+// tile[q * kSrcRS + c * 32 + pl] (q < kSrcTC) -> coef quads; a wave writes 64
+// consecutive indices of one panel and channel group.
+template <typename TOut>
+__device__ __forceinline__ void src_flush(const float *tile, TOut *coef, int64_t pbase, int64_t P, int64_t NS,
+                                          int64_t i0) {
+    for (int e = threadIdx.x; e < kSrcPanels * 2 * kSrcTC; e += 256) {
+        const int pl = e / (2 * kSrcTC);
+        const int g = (e / kSrcTC) & 1;
+        const int q = e & (kSrcTC - 1);
+        const int64_t p = pbase + pl;
+        if (p < P) {
+            float v[4];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) v[cc] = tile[q * kSrcRS + (4 * g + cc) * 32 + pl];
+            store_quad(coef + ((p * 2 + g) * NS + i0 + q) * 4, v);
+        }
+    }
+}
+
+// Interior chunk: rows [R0, R0 + kSrcW) all in [kSrcPivotRows, N - 3], source
+// terms read from rows [R0 - 3, R0 + kSrcW + 2] inside the record, central
+// differences throughout, constant pivot: no branches; the reduced right-hand
+// sides stay in registers.
+template <typename TIn, typename TOut>
+__device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t pbk, int64_t i0, float *tile) {
+    const int64_t P = a.P;
+    const int pl = threadIdx.x & 31;
+    const int64_t pbase = pbk * kSrcPanels;
+    const int64_t pc = min(pbase + pl, P - 1);
+    const SrcLane<TIn> L(a, pc);
+    const double cpi = 2.0 - sqrt(3.0);
+    const int64_t R0 = i0 - 1 - kSrcH;
+    int64_t off = (R0 - 3) * P;
+    double Xa = L.X(off), Xb = L.X(off + P), Xc = L.X(off + 2 * P), Xd = L.X(off + 3 * P), Xe = L.X(off + 4 * P);
+    off += 5 * P;  // next row to load: R0 + 2
+    float dv[kSrcW];
+    double fprev = 0.0, dprev = 0.0;
+    constexpr int ITER = kSrcW + 2;  // n = R0 - 1 .. R0 + kSrcW
+#pragma unroll
+    for (int g0 = 0; g0 < ITER; g0 += kSrcPF) {
+        double Xf[kSrcPF];
+#pragma unroll
+        for (int q = 0; q < kSrcPF; ++q)  // rows up to R0 + kSrcW + 2 (the last iteration needs no new row)
+            Xf[q] = (g0 + q < ITER - 1) ? L.X(off + q * P) : 0.0;
+        off += kSrcPF * P;
+#pragma unroll
+        for (int q = 0; q < kSrcPF; ++q) {
+            const int it = g0 + q;
+            if (it < ITER) {
+                const double fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
+                if (it >= 2) {
+                    const double d = (6.0 * fprev - dprev) * cpi;
+                    dprev = d;
+                    dv[it - 2] = (float)d;
+                }
+                fprev = fn;
+                Xa = Xb;
+                Xb = Xc;
+                Xc = Xd;
+                Xd = Xe;
+                Xe = Xf[q];
+            }
+        }
+    }
+    (void)Xa;
+    double x = 0.0;
+#pragma unroll
+    for (int s = kSrcW - 1; s >= 0; --s) {
+        x = (double)dv[s] - cpi * x;
+        if (s >= kSrcH && s < kSrcH + kSrcTC) tile[(s - kSrcH) * kSrcRS + L.ch * 32 + pl] = (float)x;
+    }
+}
+
+// General chunk (either record end in reach): one-sided differences at the
+// first and last frame, zero source terms outside the record, the end rows'
+// right-hand-side corrections, exact pivots, end coefficients c_{-1}, c_0,
+// c_{N-1}, c_N and zero padding.  Reduced right-hand sides go to the LDS tile
+// [kSrcW][kSrcRS]; the output values overwrite them in place.
+template <typename TIn>
+__device__ __forceinline__ void src_chunk_general(const SrcFwdArgs &a, int64_t pbk, int64_t i0, float *tile) {
+    const int64_t P = a.P, N = a.N;
+    const int pl = threadIdx.x & 31;
+    const int64_t pbase = pbk * kSrcPanels;
+    const int64_t pc = min(pbase + pl, P - 1);
+    const SrcLane<TIn> L(a, pc);
+    const double *__restrict__ cp = a.cp;
+    const double cpi = 2.0 - sqrt(3.0);
+    const double sfd = L.s_der;  // 1/(2 dtau) on derivative lanes
+    const int col = L.ch * 32 + pl;
+    const int64_t R0 = i0 - 1 - kSrcH;
+    auto X = [&](int64_t m) -> double { return (m >= 0 && m < N) ? L.X(m * P) : 0.0; };
+    double Xa = X(R0 - 3), Xb = X(R0 - 2), Xc = X(R0 - 1), Xd = X(R0), Xe = X(R0 + 1);
+    double fprev = 0.0, f0 = 0.0, fN1 = 0.0, dprev = 0.0, dN2 = 0.0;
+    constexpr int ITER = kSrcW + 2;
+    for (int g0 = 0; g0 < ITER; g0 += kSrcPF) {
+        double Xf[kSrcPF];
+#pragma unroll
+        for (int q = 0; q < kSrcPF; ++q) Xf[q] = X(R0 + 2 + g0 + q);
+#pragma unroll
+        for (int q = 0; q < kSrcPF; ++q) {
+            const int it = g0 + q;
+            if (it < ITER) {
+                const int64_t n = R0 - 1 + it;  // Xa..Xe = X(n-2) .. X(n+2)
+                double fn = 0.0;
+                if (n >= 0 && n < N) {
+                    double dx;
+                    if (n == 0) dx = -3.0 * Xc + 4.0 * Xd - Xe;
+                    else if (n == N - 1) dx = 3.0 * Xc - 4.0 * Xb + Xa;
+                    else dx = Xd - Xb;
+                    fn = sfd * dx + L.s_val * Xc;
+                }
+                if (n == 0) f0 = fn;
+                if (n == N - 1) fN1 = fn;
+                if (it >= 2) {
+                    const int64_t r = n - 1;
+                    float dvs = 0.f;
+                    if (r >= 1 && r <= N - 2) {
+                        double rhs = 6.0 * fprev;
+                        if (r == 1) rhs -= f0;
+                        if (r == N - 2) rhs -= fn;
+                        const double d = (rhs - dprev) * (r < 64 ? cp[r] : cpi);
+                        dprev = d;
+                        dvs = (float)d;
+                        if (r == N - 2) dN2 = d;
+                    }
+                    tile[(it - 2) * kSrcRS + col] = dvs;
+                }
+                fprev = fn;
+                Xa = Xb;
+                Xb = Xc;
+                Xc = Xd;
+                Xd = Xe;
+                Xe = Xf[q];
+            }
+        }
+    }
+    // back substitution from the top of the window; coefficient index i = r + 1
+    double x = 0.0;
+    for (int s = kSrcW - 1; s >= 0; --s) {
+        const int64_t r = R0 + s;
+        if (r >= 1 && r <= N - 2) x = (double)tile[s * kSrcRS + col] - (r < 64 ? cp[r] : cpi) * x;
+        if (s >= kSrcH && s < kSrcH + kSrcTC) {
+            const int64_t i = r + 1;
+            double v;
+            if (i == 0) v = 2.0 * f0 - x;
+            else if (i == 1) v = f0;
+            else if (i < N) v = x;
+            else if (i == N) v = fN1;
+            else if (i == N + 1) v = 2.0 * fN1 - dN2;
+            else v = 0.0;
+            tile[s * kSrcRS + col] = (float)v;
+        }
+    }
+}
+
+template <typename TIn, typename TOut>
+__device__ __forceinline__ void src_interior_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
+    __shared__ float tile[kSrcTC * kSrcRS];
+    src_chunk_interior<TIn, TOut>(a, pbk, k * kSrcTC, tile);
+    __syncthreads();
+    src_flush(tile, static_cast<TOut *>(a.coef), pbk * kSrcPanels, a.P, a.NS, k * kSrcTC);
+}
+
+template <typename TIn, typename TOut>
+__device__ __forceinline__ void src_general_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
+    __shared__ float tile[kSrcW * kSrcRS];
+    src_chunk_general<TIn>(a, pbk, k * kSrcTC, tile);
+    __syncthreads();
+    src_flush(tile + kSrcH * kSrcRS, static_cast<TOut *>(a.coef), pbk * kSrcPanels, a.P, a.NS, k * kSrcTC);
+}
+
 // ------------------------------------------------------------------ adjoint
 
 // Transpose of the prefilter for one (panel, channel): coefficient adjoints
@@ -338,12 +582,35 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(SrcFwdArgs a) {
     source_fwd_body<TIn, TScr, TOut>(a, blockIdx.x, blockIdx.y);
 }
 
-template <typename TIn, typename TScr, typename TOut>
-__global__ __launch_bounds__(256) void source_fwd_batched(const BatchCase *__restrict__ cases,
-                                                          const int64_t *__restrict__ start, int n) {
+// grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void src_interior_kernel(SrcFwdArgs a) {
+    src_interior_block<TIn, TOut>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
+}
+// grid (panel blocks, general chunks)
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void src_general_kernel(SrcFwdArgs a) {
+    src_general_block<TIn, TOut>(a, blockIdx.x, src_general_chunk(blockIdx.y, src_interior_chunks(a.N)));
+}
+// batched: blocks of case c are [start[c], start[c+1]), panel block major
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void src_interior_batched(const BatchCase *__restrict__ cases,
+                                                            const int64_t *__restrict__ start, int n) {
     const int c = find_case(start, n, blockIdx.x);
     const int64_t local = (int64_t)blockIdx.x - start[c];
-    source_fwd_body<TIn, TScr, TOut>(cases[c].src, local >> 1, (int)(local & 1));
+    const int64_t nk = src_interior_chunks(cases[c].src.N);
+    const int64_t pbk = local / nk;
+    src_interior_block<TIn, TOut>(cases[c].src, pbk, 1 + local - pbk * nk);
+}
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void src_general_batched(const BatchCase *__restrict__ cases,
+                                                           const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    const int64_t nint = src_interior_chunks(cases[c].src.N);
+    const int64_t ng = cases[c].src.NS / kSrcTC - nint;
+    const int64_t pbk = local / ng;
+    src_general_block<TIn, TOut>(cases[c].src, pbk, src_general_chunk(local - pbk * ng, nint));
 }
 
 template <typename TR>
@@ -375,6 +642,20 @@ __global__ __launch_bounds__(256) void source_adj_chain_batched(const BatchCase 
     source_adj_chain_body<TR, TIn>(cases[c].chain, local - fr * pblocks, fr);
 }
 
+template <typename TIn, typename TOut>
+hipError_t source_chunk_launch_t(const SrcFwdArgs &a, hipStream_t stream) {
+    const unsigned pb = (unsigned)((a.P + kSrcPanels - 1) / kSrcPanels);
+    const int64_t nint = src_interior_chunks(a.N);
+    const int64_t ngen = a.NS / kSrcTC - nint;
+    if (nint > 0) {
+        src_interior_kernel<TIn, TOut><<<dim3(pb, (unsigned)nint), dim3(256), 0, stream>>>(a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    src_general_kernel<TIn, TOut><<<dim3(pb, (unsigned)ngen), dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+
 template <typename TIn, typename TScr, typename TOut>
 hipError_t source_launch_t(const SrcFwdArgs &a, hipStream_t stream) {
     dim3 grid((unsigned)((a.P + 63) / 64), 2);
@@ -401,12 +682,12 @@ hipError_t launch_source(int in_dtype, int coef_type, const void *rho, const voi
     const SrcFwdArgs a{rho, u, pp, normal, P, N, NS, f, cp, scratch, coef};
     if (in_dtype == 0) {
         if (coef_type == 0) return source_launch_t<double, double, double>(a, stream);
-        if (coef_type == 1) return source_launch_t<double, float, float>(a, stream);
-        return source_launch_t<double, float, bf16s>(a, stream);
+        if (coef_type == 1) return source_chunk_launch_t<double, float>(a, stream);
+        return source_chunk_launch_t<double, bf16s>(a, stream);
     }
     if (coef_type == 0) return source_launch_t<float, double, double>(a, stream);
-    if (coef_type == 1) return source_launch_t<float, float, float>(a, stream);
-    return source_launch_t<float, float, bf16s>(a, stream);
+    if (coef_type == 1) return source_chunk_launch_t<float, float>(a, stream);
+    return source_chunk_launch_t<float, bf16s>(a, stream);
 }
 
 hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, const void *rho, const void *u,
@@ -423,15 +704,29 @@ hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, 
 }
 
 // Batched source stages (FP32/BF16 modes: float scratch).
-hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start, int n,
-                               int64_t blocks, hipStream_t stream) {
-    const dim3 g((unsigned)blocks), b(256);
+hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start_int,
+                               const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
+                               hipStream_t stream) {
+    const dim3 b(256);
+    if (blocks_int > 0) {
+        const dim3 g((unsigned)blocks_int);
+        if (in_dtype == 0) {
+            if (coef_type == 1) src_interior_batched<double, float><<<g, b, 0, stream>>>(cases, start_int, n);
+            else src_interior_batched<double, bf16s><<<g, b, 0, stream>>>(cases, start_int, n);
+        } else {
+            if (coef_type == 1) src_interior_batched<float, float><<<g, b, 0, stream>>>(cases, start_int, n);
+            else src_interior_batched<float, bf16s><<<g, b, 0, stream>>>(cases, start_int, n);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 g((unsigned)blocks_gen);
     if (in_dtype == 0) {
-        if (coef_type == 1) source_fwd_batched<double, float, float><<<g, b, 0, stream>>>(cases, start, n);
-        else source_fwd_batched<double, float, bf16s><<<g, b, 0, stream>>>(cases, start, n);
+        if (coef_type == 1) src_general_batched<double, float><<<g, b, 0, stream>>>(cases, start_gen, n);
+        else src_general_batched<double, bf16s><<<g, b, 0, stream>>>(cases, start_gen, n);
     } else {
-        if (coef_type == 1) source_fwd_batched<float, float, float><<<g, b, 0, stream>>>(cases, start, n);
-        else source_fwd_batched<float, float, bf16s><<<g, b, 0, stream>>>(cases, start, n);
+        if (coef_type == 1) src_general_batched<float, float><<<g, b, 0, stream>>>(cases, start_gen, n);
+        else src_general_batched<float, bf16s><<<g, b, 0, stream>>>(cases, start_gen, n);
     }
     return hipGetLastError();
 }

@@ -46,3 +46,36 @@ def surface_data(P: int, n_tau: int, aoa_deg: float, seed: int, rms: float = 0.0
             u[i, :, b0:b1] = (U[i] + x[1 + i]).T
         pp[:, b0:b1] = x[4].T
     return rho, u, pp
+
+
+def surface_data_torch(P: int, n_tau: int, aoa_deg: float, seed: int, rms: float = 0.01, device="cuda",
+                       block: int = 8192):
+    """Device-side version of `surface_data` (same spectrum, RMS and layout;
+    torch's generator, so a different realisation): FP32 tensors rho [N,P],
+    u [3,N,P], p' [N,P].  Blocks of panels are seeded from (seed, block)."""
+    import torch
+    a = math.radians(aoa_deg)
+    U = (math.cos(a), math.sin(a), 0.0)
+    rho = torch.empty((n_tau, P), dtype=torch.float32, device=device)
+    u = torch.empty((3, n_tau, P), dtype=torch.float32, device=device)
+    pp = torch.empty((n_tau, P), dtype=torch.float32, device=device)
+    nf = n_tau // 2 + 1
+    f = torch.arange(nf, dtype=torch.float64, device=device)
+    amp = torch.zeros(nf, dtype=torch.float64, device=device)
+    amp[1:] = f[1:] ** (-5.0 / 6.0)
+    g = torch.Generator(device=device)
+    for b0 in range(0, P, block):
+        b1 = min(P, b0 + block)
+        g.manual_seed(int(seed) * 1000003 + b0 // block)
+        m = 5 * (b1 - b0)
+        re = torch.randn((m, nf), generator=g, dtype=torch.float64, device=device)
+        im = torch.randn((m, nf), generator=g, dtype=torch.float64, device=device)
+        x = torch.fft.irfft(torch.complex(re, im) * amp, n=n_tau, dim=1)
+        x -= x.mean(dim=1, keepdim=True)
+        x *= rms / torch.sqrt(torch.mean(x * x, dim=1, keepdim=True))
+        x = x.reshape(5, b1 - b0, n_tau)
+        rho[:, b0:b1] = (1.0 + x[0]).T.float()
+        for i in range(3):
+            u[i, :, b0:b1] = (U[i] + x[1 + i]).T.float()
+        pp[:, b0:b1] = x[4].T.float()
+    return rho, u, pp

@@ -61,6 +61,14 @@ class Case:
                                        self.amplitude, self.omega, self.n_tau, self.dtau, self.tau0,
                                        dtype=self.data_dtype)
 
+    def data_device(self, device="cuda"):
+        """Surface data as device tensors; broadband data are generated on the
+        device (torch generator), analytic data on the host then copied."""
+        import torch
+        if self.kind == "broadband":
+            return broadband.surface_data_torch(self.n_panels, self.n_tau, self.aoa_deg, self.seed, device=device)
+        return tuple(torch.from_numpy(a).to(device) for a in self.data())
+
     def exact(self, t):
         """Closed-form p'(x_o, t) of the analytic source ([O, K] times)."""
         return analytic.far_field_pressure(self.kind, self.x_obs, analytic.Flow(self.mach, self.aoa_deg),
