@@ -53,7 +53,7 @@ struct fwh_plan {
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
     size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_tw = 0, off_wblk = 0;
-    size_t off_coef = 0, off_scr = 0, off_part = 0, off_gpad = 0, ws_bytes = 0;
+    size_t off_coef = 0, off_scr = SIZE_MAX, off_part = 0, off_gpad = 0, ws_bytes = 0;
     char *ws = nullptr;
     // optional per-stage event timing
     bool profiling = false;
@@ -61,6 +61,7 @@ struct fwh_plan {
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    void *scratch() const { return off_scr == SIZE_MAX ? nullptr : ws + off_scr; }
 };
 
 namespace {
@@ -96,8 +97,9 @@ int layout(fwh_plan *pl) {
     // coefficient channels (forward) and coefficient adjoints (adjoint) share one region
     const size_t real_sz = pl->mode == FWH_MODE_F64 ? sizeof(double) : sizeof(float);
     pl->off_coef = take(8 * P * NS * real_sz);
-    // time-major scratch of the source stage, forward and adjoint
-    pl->off_scr = take(8 * N * P * real_sz);
+    // time-major scratch of the sequential FP64 source stage, forward and adjoint
+    // (the chunked FP32/BF16 stages need none)
+    if (pl->mode == FWH_MODE_F64) pl->off_scr = take(8 * N * P * real_sz);
     if (pl->mode != FWH_MODE_F64) {
         pl->off_part = take((size_t)fwh::kMaxPanelSplits * O * N * sizeof(double));
         pl->off_gpad = take((size_t)O * fwh::adj_pad_row(pl->N, pl->NS) * sizeof(float));
@@ -321,7 +323,7 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
     {
         StageScope sc(pl, FWH_STAGE_SOURCE, st);
         e = fwh::launch_source(in_dtype == FWH_F64 ? 0 : 1, coef_type, rho, u, pp, pl->at<double>(pl->off_n), pl->P,
-                               pl->N, pl->NS, pl->flow, pl->at<double>(pl->off_cp), pl->ws + pl->off_scr,
+                               pl->N, pl->NS, pl->flow, pl->at<double>(pl->off_cp), pl->scratch(),
                                pl->ws + pl->off_coef, st);
     }
     if (e) return hip_fail("fwh_forward: source kernel", e);
@@ -382,7 +384,7 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
         StageScope sc(pl, FWH_STAGE_SOURCE_ADJ, st);
         e = fwh::launch_source_adjoint(f64 ? 0 : 1, in_dtype == FWH_F64 ? 0 : 1, pl->ws + pl->off_coef, rho, u,
                                        pl->at<double>(pl->off_n), pl->P, pl->N, pl->NS, pl->flow,
-                                       pl->at<double>(pl->off_cp), pl->ws + pl->off_scr, g_rho, g_u, g_p, st);
+                                       pl->at<double>(pl->off_cp), pl->scratch(), g_rho, g_u, g_p, st);
     }
     if (e) return hip_fail("fwh_adjoint: source adjoint", e);
     (void)pp;
@@ -427,7 +429,8 @@ struct fwh_batch {
     double item_units = 4.0e6;
     int blocks_per_cu = 2;
     int64_t max_items = 0, n_items = 0, units = 0, grid = 0;
-    int64_t blocks_src = 0, blocks_srcg = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_pre = 0, blocks_chain = 0;
+    int64_t blocks_src = 0, blocks_srcg = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_sadj = 0,
+            blocks_sadjg = 0;
     size_t shmem = 0;
     size_t off_cases = 0, off_idx = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
     char *ws = nullptr;
@@ -510,8 +513,8 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     const int coef_type = b->mode == FWH_MODE_F32 ? 1 : 2;
     std::vector<fwh::BatchCase> desc((size_t)n);
     std::vector<int64_t> idx((size_t)7 * (n + 1), 0);
-    int64_t *s_src = idx.data(), *s_red = s_src + (n + 1), *s_pad = s_red + (n + 1), *s_adj = s_pad + (n + 1),
-            *s_pre = s_adj + (n + 1), *s_chain = s_pre + (n + 1), *s_srcg = s_chain + (n + 1);
+    int64_t *s_src = idx.data(), *s_srcg = s_src + (n + 1), *s_red = s_srcg + (n + 1), *s_pad = s_red + (n + 1),
+            *s_adj = s_pad + (n + 1), *s_sadj = s_adj + (n + 1), *s_sadjg = s_sadj + (n + 1);
     struct Item {
         double cost;
         int4 w;
@@ -533,7 +536,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         const int64_t nib = ceil_div(NS, fwh::kLdsLanesOut);
         fwh::BatchCase &d = desc[c];
         d.src = fwh::SrcFwdArgs{k.rho, k.u, k.p_prime, pl->at<double>(pl->off_n), P, N, NS, pl->flow,
-                                pl->at<double>(pl->off_cp), pl->ws + pl->off_scr, pl->ws + pl->off_coef};
+                                pl->at<double>(pl->off_cp), pl->scratch(), pl->ws + pl->off_coef};
         d.gat = fwh::GatherArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int2>(pl->off_tw),
                                 pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, P, O, NS, ntm, p_chunk,
                                 pl->lds_nw, pl->lds_pt, (int)S, pl->at<double>(pl->off_part)};
@@ -542,17 +545,17 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
                              pl->at<float>(pl->off_gpad)};
         d.adj = fwh::AdjArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<float>(pl->off_gpad), P, O, NS, LR, padlo,
                              nib, pl->at<float>(pl->off_coef)};
-        d.pre = fwh::PreAdjArgs{pl->ws + pl->off_coef, P, N, NS, pl->at<double>(pl->off_cp), pl->ws + pl->off_scr};
-        d.chain = fwh::ChainArgs{pl->ws + pl->off_scr, k.rho, k.u, pl->at<double>(pl->off_n), P, N, pl->flow,
-                                 k.g_rho, k.g_u, k.g_p};
+        d.sadj = fwh::SrcAdjArgs{pl->at<float>(pl->off_coef), k.rho, k.u, pl->at<double>(pl->off_n), P, N, NS,
+                                 pl->flow, pl->at<double>(pl->off_cp), k.g_rho, k.g_u, k.g_p};
         const int64_t src_int = fwh::src_interior_chunks(N);
         s_src[c + 1] = s_src[c] + ceil_div(P, fwh::kSrcPanels) * src_int;
         s_srcg[c + 1] = s_srcg[c] + ceil_div(P, fwh::kSrcPanels) * (NS / fwh::kSrcTC - src_int);
         s_red[c + 1] = s_red[c] + ceil_div(O * ntm, 256);
         s_pad[c + 1] = s_pad[c] + ceil_div(O * LR, 256);
         s_adj[c + 1] = s_adj[c] + P * nib;
-        s_pre[c + 1] = s_pre[c] + ceil_div(P, 64) * 2;
-        s_chain[c + 1] = s_chain[c] + ceil_div(P, 256) * N;
+        const int64_t adj_int = fwh::adj_interior_chunks(N);
+        s_sadj[c + 1] = s_sadj[c] + ceil_div(P, fwh::kSrcPanels) * adj_int;
+        s_sadjg[c + 1] = s_sadjg[c] + ceil_div(P, fwh::kSrcPanels) * (fwh::adj_chunks(N) - adj_int);
         b->shmem = std::max(b->shmem, fwh::gather_lds_shmem(coef_type, pl->lds_nw, pl->lds_pt));
         for (int64_t t = 0; t < tiles; ++t)
             for (int64_t kb = 0; kb < kbs; ++kb)
@@ -576,8 +579,8 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     b->blocks_red = s_red[n];
     b->blocks_pad = s_pad[n];
     b->waves_adj = s_adj[n];
-    b->blocks_pre = s_pre[n];
-    b->blocks_chain = s_chain[n];
+    b->blocks_sadj = s_sadj[n];
+    b->blocks_sadjg = s_sadjg[n];
     int dev = 0, cus = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
@@ -619,8 +622,8 @@ int fwh_batch_adjoint(fwh_batch *b, void *stream_) {
     g_last_error.clear();
     if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_adjoint: batch is not bound");
     hipError_t e = fwh::launch_batch_adjoint(b->in_dtype == FWH_F64 ? 0 : 1, b->at<fwh::BatchCase>(b->off_cases),
-                                             batch_index(b), b->blocks_pad, b->waves_adj, b->blocks_pre,
-                                             b->blocks_chain, as_stream(stream_));
+                                             batch_index(b), b->blocks_pad, b->waves_adj, b->blocks_sadj,
+                                             b->blocks_sadjg, as_stream(stream_));
     if (e) return hip_fail("fwh_batch_adjoint", e);
     return FWH_OK;
 }

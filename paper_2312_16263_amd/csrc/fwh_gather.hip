@@ -624,13 +624,13 @@ hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *ca
 }
 
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                int64_t waves_adj, int64_t blocks_pre, int64_t blocks_chain, hipStream_t stream) {
+                                int64_t waves_adj, int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream) {
     pad_grad_batched<<<dim3((unsigned)blocks_pad), dim3(256), 0, stream>>>(cases, idx.pad, idx.n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     adj_gather_dpp_batched<<<dim3((unsigned)((waves_adj + 3) / 4)), dim3(256), 0, stream>>>(cases, idx.adj, idx.n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_batch_source_adjoint(in_dtype, cases, idx.pre, idx.chain, idx.n, blocks_pre, blocks_chain, stream);
+    return launch_batch_source_adjoint(in_dtype, cases, idx.sadj, idx.sadjg, idx.n, blocks_sadj, blocks_sadjg, stream);
 }
 
 }  // namespace fwh

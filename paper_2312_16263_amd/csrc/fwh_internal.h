@@ -118,14 +118,24 @@ struct ChainArgs {
 };
 
 // One case of a batch (device-resident array) and the block counts of its stages.
+// Chunked source adjoint (FP32/BF16 modes): cbar [8][P][NS] float -> gradients.
+struct SrcAdjArgs {
+    const float *cbar;
+    const void *rho, *u;
+    const double *normal;
+    int64_t P, N, NS;
+    Flow f;
+    const double *cp;
+    void *g_rho, *g_u, *g_p;
+};
+
 struct BatchCase {
     SrcFwdArgs src;
     GatherArgs gat;
     ReduceArgs red;
     PadArgs pad;
     AdjArgs adj;
-    PreAdjArgs pre;
-    ChainArgs chain;
+    SrcAdjArgs sadj;
 };
 
 // Case of flattened block b: start[c] <= b < start[c+1] (start has n + 1 entries).
@@ -141,7 +151,7 @@ __device__ __forceinline__ int find_case(const int64_t *start, int n, int64_t b)
 
 // Block/wave offsets of each case in the flattened batched grids: start[c] .. start[c+1].
 struct BatchIndex {
-    const int64_t *src, *red, *pad, *adj, *pre, *chain, *srcg;  // block starts per case
+    const int64_t *src, *srcg, *red, *pad, *adj, *sadj, *sadjg;  // block starts per case
     int n;
 };
 
@@ -186,6 +196,19 @@ __host__ __device__ inline int64_t src_interior_chunks(int64_t N) {
 __host__ __device__ inline int64_t src_general_chunk(int64_t g, int64_t n_interior) {
     return g == 0 ? 0 : n_interior + g;
 }
+
+// Chunked source adjoint: a block owns kSrcPanels panels and the frames
+// [m0, m0 + kSrcTC); its recurrences run over the rows [m0 - kAdjLo, m0 - kAdjLo + kAdjW),
+// whose coefficient adjoints are the 16-byte aligned storage indices
+// [m0 - kAdjLo + 1, m0 - kAdjLo + 1 + kAdjW).  Interior chunks: rows inside
+// [kSrcPivotRows, N - 3].
+constexpr int kAdjLo = 17;
+constexpr int kAdjW = 96;
+__host__ __device__ inline int64_t adj_interior_chunks(int64_t N) {
+    const int64_t top = N - 3 - (kAdjW - kAdjLo - 1);  // largest admissible m0
+    return top >= kSrcTC ? top / kSrcTC : 0;
+}
+__host__ __device__ inline int64_t adj_chunks(int64_t N) { return (N + kSrcTC - 1) / kSrcTC; }
 
 // Source terms + derivatives + natural-spline prefilter -> coefficients [P][2][NS][4]
 // (channel c = 4 g + cc at ((p*2 + g)*NS + i)*4 + cc).
@@ -237,13 +260,13 @@ hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, 
 hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cases, const int64_t *start_int,
                                const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
                                hipStream_t stream);
-hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_pre,
-                                       const int64_t *start_chain, int n, int64_t blocks_pre, int64_t blocks_chain,
+hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_int,
+                                       const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
                                        hipStream_t stream);
 hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
                                 int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream);
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                int64_t waves_adj, int64_t blocks_pre, int64_t blocks_chain, hipStream_t stream);
+                                int64_t waves_adj, int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream);
 
 }  // namespace fwh

@@ -446,6 +446,273 @@ __device__ __forceinline__ void src_general_block(const SrcFwdArgs &a, int64_t p
     src_flush(tile + kSrcH * kSrcRS, static_cast<TOut *>(a.coef), pbk * kSrcPanels, a.P, a.NS, k * kSrcTC);
 }
 
+// ------------------------------------------------ chunked source adjoint stage
+// FP32/BF16 modes: the exact transpose of the chunked source stage, fused with
+// the derivative transpose and the chain rule (geometry in fwh_internal.h).
+// With a_k the adjoint of coefficient c_k (storage index k + 1):
+//   chat_r = a_r - [r = 1] a_{-1} - [r = N-2] a_N   (r = 1 .. N-2),  z = A^{-1} chat,
+//   fbar_j = 6 z_j (1 <= j <= N-2),  fbar_0 = a_0 + 2 a_{-1} - z_1,
+//   fbar_{N-1} = a_{N-1} + 2 a_N - z_{N-2}
+// (A = tridiag(1, 4, 1) is symmetric, so its transpose solve is the same Thomas
+// sweep); then Xbar = fbar (value channels) or D^T fbar (derivative channels)
+// and the chain rule through the source terms at every frame of the chunk.
+// Wave w, lanes 0-31 / 32-63: base w, derivative / value channel (as forward).
+
+// Xbar of 8 channels at (frame m, panel) from tile[(m - m0) * kSrcRS + c * 32 + pl];
+// chain rule; gradients out time-major (32 consecutive panels per frame).
+template <typename TIn>
+__device__ __forceinline__ void src_adj_chain_out(const float *tile, const SrcAdjArgs &a, int64_t pbase, int64_t m0) {
+    const int64_t P = a.P, N = a.N, NP = N * P;
+    const TIn *__restrict__ rho = static_cast<const TIn *>(a.rho);
+    const TIn *__restrict__ u = static_cast<const TIn *>(a.u);
+    TIn *__restrict__ g_rho = static_cast<TIn *>(a.g_rho);
+    TIn *__restrict__ g_u = static_cast<TIn *>(a.g_u);
+    TIn *__restrict__ g_p = static_cast<TIn *>(a.g_p);
+    const int pl = threadIdx.x & 31;
+    const int64_t p = pbase + pl;
+    if (p >= P) return;
+    const double nx = a.normal[3 * p], ny = a.normal[3 * p + 1], nz = a.normal[3 * p + 2];
+    const double Ux = a.f.ca, Uy = a.f.sa;
+    for (int ml = threadIdx.x >> 5; ml < kSrcTC; ml += 8) {
+        const int64_t m = m0 + ml;
+        if (m >= N) break;
+        const float *t = tile + ml * kSrcRS + pl;
+        const double Qb = (double)t[0] + (double)t[32];
+        const double L1 = (double)t[2 * 32] + (double)t[5 * 32];
+        const double L2 = (double)t[3 * 32] + (double)t[6 * 32];
+        const double L3 = (double)t[4 * 32] + (double)t[7 * 32];
+        const int64_t idx = m * P + p;
+        const double r = (double)rho[idx];
+        const double u1 = (double)u[idx], u2 = (double)u[NP + idx], u3 = (double)u[2 * NP + idx];
+        const double un = u1 * nx + u2 * ny + u3 * nz;
+        const double w1 = u1 - Ux, w2 = u2 - Uy, w3 = u3;
+        const double S = Qb + L1 * w1 + L2 * w2 + L3 * w3;
+        g_rho[idx] = (TIn)(un * S);
+        g_u[idx] = (TIn)(r * nx * S + r * un * L1);
+        g_u[NP + idx] = (TIn)(r * ny * S + r * un * L2);
+        g_u[2 * NP + idx] = (TIn)(r * nz * S + r * un * L3);
+        g_p[idx] = (TIn)(L1 * nx + L2 * ny + L3 * nz);
+    }
+}
+
+struct AdjLane {
+    double s_der, s_val;
+    int ch;
+    __device__ __forceinline__ explicit AdjLane(double dtau) {
+        const int w = threadIdx.x >> 6;
+        const bool der = (threadIdx.x & 32) == 0;
+        ch = w == 0 ? (der ? 0 : 1) : (der ? 1 + w : 4 + w);
+        s_der = der ? 1.0 / (2.0 * dtau) : 0.0;
+        s_val = der ? 0.0 : 1.0;
+    }
+};
+
+constexpr int kAdjSlab = 32;            // storage indices per staged slab
+constexpr int kAdjSlabRS = kAdjSlab + 1;
+
+// Interior chunk: rows [m0 - kAdjLo, m0 - kAdjLo + kAdjW) inside [kSrcPivotRows, N - 3];
+// the coefficient adjoints come in through LDS slabs of 32 indices x 256 rows
+// (8 lanes per 128-byte row segment), the reduced right-hand sides stay in registers.
+template <typename TIn>
+__device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pbk, int64_t k, float *lds) {
+    const int64_t P = a.P, NS = a.NS;
+    const int pl = threadIdx.x & 31;
+    const int64_t pbase = pbk * kSrcPanels;
+    const AdjLane L(a.f.dtau);
+    const double cpi = 2.0 - sqrt(3.0);
+    const int64_t m0 = k * kSrcTC;
+    const int64_t i_lo = m0 - kAdjLo + 1;  // storage index of window row 0
+    // cooperative slab loads: float4 e = tid + 256 j -> row e / 8 (channel-major rows c*32 + pl), quad e % 8
+    auto slab_load = [&](int t, float4 *v) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            const int row = e >> 3, qd = e & 7;
+            const int64_t pr = min(pbase + (row & 31), P - 1);
+            const float *src = a.cbar + ((int64_t)(row >> 5) * P + pr) * NS + i_lo + t * kAdjSlab + 4 * qd;
+            v[j] = *reinterpret_cast<const float4 *>(src);
+        }
+    };
+    auto slab_store = [&](const float4 *v) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            float *dst = lds + (e >> 3) * kAdjSlabRS + 4 * (e & 7);
+            dst[0] = v[j].x;
+            dst[1] = v[j].y;
+            dst[2] = v[j].z;
+            dst[3] = v[j].w;
+        }
+    };
+    const int myrow = L.ch * 32 + pl;
+    float dv[kAdjW];
+    double dprev = 0.0;
+    float4 cur[8], nxt[8];
+    slab_load(0, cur);
+#pragma unroll
+    for (int t = 0; t < kAdjW / kAdjSlab; ++t) {
+        if (t + 1 < kAdjW / kAdjSlab) slab_load(t + 1, nxt);
+        __syncthreads();
+        slab_store(cur);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kAdjSlab; ++q) {
+            const double d = ((double)lds[myrow * kAdjSlabRS + q] - dprev) * cpi;
+            dprev = d;
+            dv[t * kAdjSlab + q] = (float)d;
+        }
+        if (t + 1 < kAdjW / kAdjSlab) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cur[j] = nxt[j];
+        }
+    }
+    __syncthreads();  // slabs done: the LDS becomes the Xbar tile
+    // back substitution; Xbar_m once fbar_{m-1} is known (window row s = m - m0 + kAdjLo - 1)
+    double z = 0.0, fp1 = 0.0, fc = 0.0;
+#pragma unroll
+    for (int s = kAdjW - 1; s >= 0; --s) {
+        z = (double)dv[s] - cpi * z;
+        const double fm1 = 6.0 * z;
+        const int ml = s - kAdjLo + 1;  // frame m = m0 + ml has fbar_{m-1} = fm1
+        if (ml >= 0 && ml < kSrcTC)
+            lds[ml * kSrcRS + myrow] = (float)(L.s_val * fc + L.s_der * (fm1 - fp1));
+        fp1 = fc;
+        fc = fm1;
+    }
+}
+
+// General chunk (either record end in reach, or short records): exact end rows
+// and pivots; reduced right-hand sides and then z in the LDS window
+// [kAdjW][kSrcRS]; Xbar_m overwrites the row of fbar_{m-1}, so the Xbar tile
+// starts at window row kAdjLo - 1.
+template <typename TIn>
+__device__ __forceinline__ void src_adj_general(const SrcAdjArgs &a, int64_t pbk, int64_t k, float *lds) {
+    const int64_t P = a.P, N = a.N, NS = a.NS;
+    const int pl = threadIdx.x & 31;
+    const int64_t pbase = pbk * kSrcPanels;
+    const int64_t pc = min(pbase + pl, P - 1);
+    const AdjLane L(a.f.dtau);
+    const double *__restrict__ cp = a.cp;
+    const double cpi = 2.0 - sqrt(3.0);
+    const int myrow = L.ch * 32 + pl;
+    const float *row = a.cbar + ((int64_t)L.ch * P + pc) * NS;
+    const int64_t m0 = k * kSrcTC;
+    const int64_t R0 = m0 - kAdjLo;
+    const double am1 = row[0], a0 = row[1], aN1 = row[N], aN = row[N + 1];
+    double dprev = 0.0;
+    for (int s = 0; s < kAdjW; ++s) {
+        const int64_t r = R0 + s;
+        float v = 0.f;
+        if (r >= 1 && r <= N - 2) {
+            double c = (double)row[r + 1];
+            if (r == 1) c -= am1;
+            if (r == N - 2) c -= aN;
+            const double d = (c - dprev) * (r < 64 ? cp[r] : cpi);
+            dprev = d;
+            v = (float)d;
+        }
+        lds[s * kSrcRS + myrow] = v;
+    }
+    double z = 0.0, z1 = 0.0, zN2 = 0.0;
+    for (int s = kAdjW - 1; s >= 0; --s) {
+        const int64_t r = R0 + s;
+        if (r >= 1 && r <= N - 2) {
+            z = (double)lds[s * kSrcRS + myrow] - (r < 64 ? cp[r] : cpi) * z;
+            lds[s * kSrcRS + myrow] = (float)z;
+            if (r == 1) z1 = z;
+            if (r == N - 2) zN2 = z;
+        }
+    }
+    const double fb0 = a0 + 2.0 * am1 - z1, fbN1 = aN1 + 2.0 * aN - zN2;
+    auto fbar = [&](int64_t j) -> double {  // j within the window rows
+        if (j == 0) return fb0;
+        if (j == N - 1) return fbN1;
+        if (j >= 1 && j <= N - 2) return 6.0 * (double)lds[(j - R0) * kSrcRS + myrow];
+        return 0.0;
+    };
+    const double sd = L.s_der;
+    for (int ml = 0; ml < kSrcTC; ++ml) {
+        const int64_t m = m0 + ml;
+        double xb = 0.0;
+        if (m < N) {
+            const double fm = fbar(m);
+            double dx = 0.0;
+            if (m - 1 >= 1 && m - 1 <= N - 2) dx += fbar(m - 1);
+            if (m + 1 >= 1 && m + 1 <= N - 2) dx -= fbar(m + 1);
+            if (m == 0) dx -= 3.0 * fb0;
+            if (m == 1) dx += 4.0 * fb0;
+            if (m == 2) dx -= fb0;
+            if (m == N - 1) dx += 3.0 * fbN1;
+            if (m == N - 2) dx -= 4.0 * fbN1;
+            if (m == N - 3) dx += fbN1;
+            xb = L.s_val * fm + sd * dx;
+        }
+        // row of fbar_{m-1} is no longer needed by frames >= m
+        lds[(ml + kAdjLo - 1) * kSrcRS + myrow] = (float)xb;
+    }
+}
+
+template <typename TIn>
+__device__ __forceinline__ void src_adj_interior_block(const SrcAdjArgs &a, int64_t pbk, int64_t k) {
+    __shared__ float lds[kSrcTC * kSrcRS];
+    src_adj_interior<TIn>(a, pbk, k, lds);
+    __syncthreads();
+    src_adj_chain_out<TIn>(lds, a, pbk * kSrcPanels, k * kSrcTC);
+}
+
+template <typename TIn>
+__device__ __forceinline__ void src_adj_general_block(const SrcAdjArgs &a, int64_t pbk, int64_t k) {
+    __shared__ float lds[kAdjW * kSrcRS];
+    src_adj_general<TIn>(a, pbk, k, lds);
+    __syncthreads();
+    src_adj_chain_out<TIn>(lds + (kAdjLo - 1) * kSrcRS, a, pbk * kSrcPanels, k * kSrcTC);
+}
+
+// grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
+template <typename TIn>
+__global__ __launch_bounds__(256) void src_adj_interior_kernel(SrcAdjArgs a) {
+    src_adj_interior_block<TIn>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
+}
+// grid (panel blocks, general chunks)
+template <typename TIn>
+__global__ __launch_bounds__(256) void src_adj_general_kernel(SrcAdjArgs a) {
+    src_adj_general_block<TIn>(a, blockIdx.x, src_general_chunk(blockIdx.y, adj_interior_chunks(a.N)));
+}
+template <typename TIn>
+__global__ __launch_bounds__(256) void src_adj_interior_batched(const BatchCase *__restrict__ cases,
+                                                                const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    const int64_t nk = adj_interior_chunks(cases[c].sadj.N);
+    const int64_t pbk = local / nk;
+    src_adj_interior_block<TIn>(cases[c].sadj, pbk, 1 + local - pbk * nk);
+}
+template <typename TIn>
+__global__ __launch_bounds__(256) void src_adj_general_batched(const BatchCase *__restrict__ cases,
+                                                               const int64_t *__restrict__ start, int n) {
+    const int c = find_case(start, n, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - start[c];
+    const int64_t N = cases[c].sadj.N;
+    const int64_t nint = adj_interior_chunks(N);
+    const int64_t ng = adj_chunks(N) - nint;
+    const int64_t pbk = local / ng;
+    src_adj_general_block<TIn>(cases[c].sadj, pbk, src_general_chunk(local - pbk * ng, nint));
+}
+
+template <typename TIn>
+hipError_t src_adj_chunk_launch_t(const SrcAdjArgs &a, hipStream_t stream) {
+    const unsigned pb = (unsigned)((a.P + kSrcPanels - 1) / kSrcPanels);
+    const int64_t nint = adj_interior_chunks(a.N);
+    const int64_t ngen = adj_chunks(a.N) - nint;
+    if (nint > 0) {
+        src_adj_interior_kernel<TIn><<<dim3(pb, (unsigned)nint), dim3(256), 0, stream>>>(a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    src_adj_general_kernel<TIn><<<dim3(pb, (unsigned)ngen), dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ adjoint
 
 // Transpose of the prefilter for one (panel, channel): coefficient adjoints
@@ -618,28 +885,9 @@ __global__ __launch_bounds__(256) void prefilter_adj_kernel(PreAdjArgs a) {
     prefilter_adj_body<TR>(a, blockIdx.x, blockIdx.y);
 }
 
-template <typename TR>
-__global__ __launch_bounds__(256) void prefilter_adj_batched(const BatchCase *__restrict__ cases,
-                                                             const int64_t *__restrict__ start, int n) {
-    const int c = find_case(start, n, blockIdx.x);
-    const int64_t local = (int64_t)blockIdx.x - start[c];
-    prefilter_adj_body<TR>(cases[c].pre, local >> 1, (int)(local & 1));
-}
-
 template <typename TR, typename TIn>
 __global__ __launch_bounds__(256) void source_adj_chain_kernel(ChainArgs a) {
     source_adj_chain_body<TR, TIn>(a, blockIdx.x, blockIdx.y);
-}
-
-// flattened: block -> (case, frame n, panel block)
-template <typename TR, typename TIn>
-__global__ __launch_bounds__(256) void source_adj_chain_batched(const BatchCase *__restrict__ cases,
-                                                                const int64_t *__restrict__ start, int n) {
-    const int c = find_case(start, n, blockIdx.x);
-    const int64_t local = (int64_t)blockIdx.x - start[c];
-    const int64_t pblocks = (cases[c].chain.P + 255) / 256;
-    const int64_t fr = local / pblocks;
-    source_adj_chain_body<TR, TIn>(cases[c].chain, local - fr * pblocks, fr);
 }
 
 template <typename TIn, typename TOut>
@@ -699,8 +947,9 @@ hipError_t launch_source_adjoint(int real_type, int in_dtype, const void *cbar, 
         if (in_dtype == 0) return source_adj_launch_t<double, double>(pa, ca, stream);
         return source_adj_launch_t<double, float>(pa, ca, stream);
     }
-    if (in_dtype == 0) return source_adj_launch_t<float, double>(pa, ca, stream);
-    return source_adj_launch_t<float, float>(pa, ca, stream);
+    const SrcAdjArgs sa{static_cast<const float *>(cbar), rho, u, normal, P, N, NS, f, cp, g_rho, g_u, g_p};
+    if (in_dtype == 0) return src_adj_chunk_launch_t<double>(sa, stream);
+    return src_adj_chunk_launch_t<float>(sa, stream);
 }
 
 // Batched source stages (FP32/BF16 modes: float scratch).
@@ -731,18 +980,18 @@ hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cas
     return hipGetLastError();
 }
 
-hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_pre,
-                                       const int64_t *start_chain, int n, int64_t blocks_pre, int64_t blocks_chain,
+hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_int,
+                                       const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
                                        hipStream_t stream) {
-    prefilter_adj_batched<float><<<dim3((unsigned)blocks_pre), dim3(256), 0, stream>>>(cases, start_pre, n);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (in_dtype == 0)
-        source_adj_chain_batched<float, double><<<dim3((unsigned)blocks_chain), dim3(256), 0, stream>>>(cases,
-                                                                                                      start_chain, n);
-    else
-        source_adj_chain_batched<float, float><<<dim3((unsigned)blocks_chain), dim3(256), 0, stream>>>(cases,
-                                                                                                     start_chain, n);
+    const dim3 b(256);
+    if (blocks_int > 0) {
+        if (in_dtype == 0) src_adj_interior_batched<double><<<dim3((unsigned)blocks_int), b, 0, stream>>>(cases, start_int, n);
+        else src_adj_interior_batched<float><<<dim3((unsigned)blocks_int), b, 0, stream>>>(cases, start_int, n);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (in_dtype == 0) src_adj_general_batched<double><<<dim3((unsigned)blocks_gen), b, 0, stream>>>(cases, start_gen, n);
+    else src_adj_general_batched<float><<<dim3((unsigned)blocks_gen), b, 0, stream>>>(cases, start_gen, n);
     return hipGetLastError();
 }
 
