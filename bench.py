@@ -270,15 +270,15 @@ def main():
     dom = "gather" if avg["gather"] >= avg["adj_gather"] else "adj_gather"
     t_dom = avg[dom] * 1e-3
     achieved = FLOP_PER_UNIT * U / t_dom / 1e12
-    roofline = {"bound": "alu", "kernel": "gather_tuned_kernel<float>" if dom == "gather" else
-                "adj_gather_tuned_kernel", "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+    roofline = {"bound": "alu", "kernel": "gather_lds_kernel<float>" if dom == "gather" else
+                "adj_gather_dpp_kernel", "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": None,
                 "frac_of_packed_fp32_peak": achieved * 1e12 / FP32_PACKED_PEAK,
                 "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom]}
     # source stage: HBM-bound streaming (inputs read once, coefficients written once)
     NS = ((c.n_tau + 12 + 63) // 64) * 64
     src_bytes = 5 * 8 * c.n_panels * c.n_tau + 8 * 4 * c.n_panels * NS
-    src = {"bound": "hbm", "kernel": "source_fwd_kernel", "achieved": src_bytes / (avg["source"] * 1e-3) / 1e9,
+    src = {"bound": "hbm", "kernel": "src_interior_kernel + src_general_kernel", "achieved": src_bytes / (avg["source"] * 1e-3) / 1e9,
            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "algorithmic_bytes": src_bytes, "avg_launch_ms": avg["source"]}
     src["frac"] = src["achieved"] * 1e9 / HBM_PEAK
 

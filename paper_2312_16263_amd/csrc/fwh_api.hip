@@ -375,7 +375,7 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
                                        static_cast<const double *>(grad_p), pl->P, pl->O, pl->NS, pl->n_t_max,
                                        pl->at<double>(pl->off_coef), st);
     else
-        e = fwh::launch_adj_gather_dpp(pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
+        e = fwh::launch_adj_gather(pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
                                        static_cast<const float *>(grad_p), pl->P, pl->O, pl->N, pl->NS, pl->n_t_max,
                                        pl->at<float>(pl->off_gpad), pl->at<float>(pl->off_coef), st);
     }

@@ -305,21 +305,36 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         }
     int cnt = 0;
     int b = 0;
-    if (pb < pe) fill(pb, 0);
+    // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
+    auto load_lo = [&](int64_t ps) {
+        const int64_t q = ps + lane < pe ? ps + lane : pe - 1;
+        return twt[q].x;
+    };
+    int lo_cur = 0;
+    if (pb < pe) {
+        fill(pb, 0);
+        lo_cur = load_lo(pb);
+    }
     for (int64_t ps = pb; ps < pe; ps += PT, b ^= 1) {
         const int np = (int)(pe - ps < PT ? pe - ps : PT);
         __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
         __syncthreads();                // ... and every wave's; the other buffer is free
-        if (ps + PT < pe) fill(ps + PT, b ^ 1);
+        const int lo_stage = lo_cur;
+        if (ps + PT < pe) {
+            fill(ps + PT, b ^ 1);
+            lo_cur = load_lo(ps + PT);
+        }
         const unsigned char *base = smem_raw + (size_t)b * buf_bytes;
         const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
         for (int q = 0; q < np; ++q) {
-            const int lo = twt[ps + q].x;
+            const int lo = __builtin_amdgcn_readlane(lo_stage, q);
             const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
             const QT *L1 = L0 + NW;
+            // every record slot of the tile holds a valid record (slots past the last
+            // observer repeat it), so a wave with any observer runs all kObsPerWave
+            if (obase < O) {
 #pragma unroll
-            for (int j = 0; j < kObsPerWave; ++j) {
-                if (obase + j < O) {
+                for (int j = 0; j < kObsPerWave; ++j) {
                     const float4 *R = lrec + (q * kObsTile + wv * kObsPerWave + j) * 4;
                     const float4 Ka = R[0], Kb = R[1], W = R[2];
                     const int off = __float_as_int(R[3].x) - lo;
@@ -591,7 +606,7 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
     return hipGetLastError();
 }
 
-hipError_t launch_adj_gather_dpp(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
+hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
                                  int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream) {
     const int64_t LR = adj_pad_row(N, NS), padlo = adj_pad_lo(N);
     const PadArgs pa{gbar, nt, O, nt_max, LR, padlo, gpad};
