@@ -533,7 +533,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         S = std::max<int64_t>(1, std::min<int64_t>({S, (int64_t)fwh::kMaxPanelSplits, ceil_div(P, 64)}));
         const int64_t p_chunk = ceil_div(P, S);
         const int64_t LR = fwh::adj_pad_row(N, NS), padlo = fwh::adj_pad_lo(N);
-        const int64_t nib = ceil_div(NS, fwh::kLdsLanesOut);
+        const int64_t nib = ceil_div(NS, fwh::kAdjSub * fwh::kLdsLanesOut);
         fwh::BatchCase &d = desc[c];
         d.src = fwh::SrcFwdArgs{k.rho, k.u, k.p_prime, pl->at<double>(pl->off_n), P, N, NS, pl->flow,
                                 pl->at<double>(pl->off_cp), pl->scratch(), pl->ws + pl->off_coef};

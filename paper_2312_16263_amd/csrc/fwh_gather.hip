@@ -460,43 +460,56 @@ __device__ __forceinline__ void adj_gather_dpp_body(const AdjArgs &a, int64_t wa
     if (wave_id >= P * nib) return;
     const int64_t p = wave_id / nib;
     const int64_t b = wave_id - p * nib;
-    const int64_t i = b * kLdsLanesOut + lane - kLdsHalo;
+    constexpr int S = kAdjSub;  // index blocks per wave: each record load serves S blocks
+    const int64_t i0 = b * S * kLdsLanesOut + lane - kLdsHalo;
     const PairRec *rr = rec + p;  // record of (o, p) at rr[o * P]
-    const float *g = gpad + i + padlo;
-    float acc[8];
-    double accd[8];
+    const float *g = gpad + i0 + padlo;
+    float acc[S][8];
+    double accd[S][8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc[c] = 0.f;
-        accd[c] = 0.0;
-    }
-    // observers in groups of 4: the 4 records and the 4 gpad values are fetched before any is used
-    auto step = [&](const PairRec &r, float v) {
-        const float s1 = from_prev_lane(v);
-        const float s2 = from_prev_lane(s1);
-        const float s3 = from_prev_lane(s2);
-        float h = r.w[0] * v;
-        h = fmaf(r.w[1], s1, h);
-        h = fmaf(r.w[2], s2, h);
-        h = fmaf(r.w[3], s3, h);
+    for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fmaf(r.K[c], h, acc[c]);
+        for (int c = 0; c < 8; ++c) {
+            acc[s][c] = 0.f;
+            accd[s][c] = 0.0;
+        }
+    // observers in groups of 4: the 4 records and the 4 S gpad values are fetched before any is used
+    auto step = [&](const PairRec &r, const float *v) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const float s1 = from_prev_lane(v[s]);
+            const float s2 = from_prev_lane(s1);
+            const float s3 = from_prev_lane(s2);
+            float h = r.w[0] * v[s];
+            h = fmaf(r.w[1], s1, h);
+            h = fmaf(r.w[2], s2, h);
+            h = fmaf(r.w[3], s3, h);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[s][c] = fmaf(r.K[c], h, acc[s][c]);
+        }
+    };
+    auto fetch = [&](int64_t o, int n0, float *v) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s] = g[o * LR - n0 + s * kLdsLanesOut];
     };
     auto flush = [&]() {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            accd[c] += (double)acc[c];
-            acc[c] = 0.f;
-        }
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                accd[s][c] += (double)acc[s][c];
+                acc[s][c] = 0.f;
+            }
     };
     const int64_t O4 = O & ~(int64_t)3;
     int cnt = 0;
     for (int64_t o = 0; o < O4; o += 4) {
         const PairRec r0 = rr[o * P], r1 = rr[(o + 1) * P], r2 = rr[(o + 2) * P], r3 = rr[(o + 3) * P];
-        const float v0 = g[o * LR - r0.n0];
-        const float v1 = g[(o + 1) * LR - r1.n0];
-        const float v2 = g[(o + 2) * LR - r2.n0];
-        const float v3 = g[(o + 3) * LR - r3.n0];
+        float v0[S], v1[S], v2[S], v3[S];
+        fetch(o, r0.n0, v0);
+        fetch(o + 1, r1.n0, v1);
+        fetch(o + 2, r2.n0, v2);
+        fetch(o + 3, r3.n0, v3);
         step(r0, v0);
         step(r1, v1);
         step(r2, v2);
@@ -509,12 +522,20 @@ __device__ __forceinline__ void adj_gather_dpp_body(const AdjArgs &a, int64_t wa
     }
     for (int64_t o = O4; o < O; ++o) {
         const PairRec r = rr[o * P];
-        step(r, g[o * LR - r.n0]);
+        float v[S];
+        fetch(o, r.n0, v);
+        step(r, v);
     }
     flush();
-    if (lane >= kLdsHalo && i < NS) {
+    if (lane >= kLdsHalo) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) cbar[((int64_t)c * P + p) * NS + i] = (float)accd[c];
+        for (int s = 0; s < S; ++s) {
+            const int64_t i = i0 + s * kLdsLanesOut;
+            if (i < NS) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) cbar[((int64_t)c * P + p) * NS + i] = (float)accd[s][c];
+            }
+        }
     }
 }
 
@@ -613,7 +634,7 @@ hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const flo
     pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t nib = (NS + kLdsLanesOut - 1) / kLdsLanesOut;
+    const int64_t nib = (NS + kAdjSub * kLdsLanesOut - 1) / (kAdjSub * kLdsLanesOut);
     const AdjArgs aa{rec_op, gpad, P, O, NS, LR, padlo, nib, cbar};
     adj_gather_dpp_kernel<<<dim3((unsigned)((P * nib + 3) / 4)), dim3(256), 0, stream>>>(aa);
     return hipGetLastError();
