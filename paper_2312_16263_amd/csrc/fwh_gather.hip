@@ -164,16 +164,8 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
 }
 
 
-// LDS-staged gather.  Block = kLdsWaves waves, observer tile t (kObsPerWave
-// observers per wave), samples k0 .. k0 + kLdsK - 1, panels [z*p_chunk, ...).
-// For each stage of up to PT panels the block copies into LDS, per panel, the
-// coefficient window [lo + k0, lo + k0 + (hi - lo) + kLdsK + kLdsHalo) of the 8
-// channels, interleaved as [2][NW][4] (lo/hi bound n0 over the tile's
-// observers), and the stage's pair records.  Then every wave, for each of its
-// observers and each of the kLdsSub sub-blocks, lets lane l combine the 8
-// channels at window position n0 - lo + 61 m + l (two vector LDS reads),
-// fetches the combined values of lanes l+1..l+3 by three wavefront shifts and
-// applies the four taps.
+// A staged element: the 4 channels of one group at one time index (float4 in
+// FP32, four bfloat16 in BF16) and its expansion to FP32.
 template <typename TS>
 struct Quad;
 template <>
