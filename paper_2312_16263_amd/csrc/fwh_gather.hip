@@ -19,6 +19,16 @@
 namespace fwh {
 namespace {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block h to XCD h mod 8),
+// each with its own L2.  xcd_block(h, n) renumbers them so that XCD x runs the
+// consecutive logical blocks [start(x), start(x) + count(x)): neighbouring
+// logical blocks, which read the same panels' data, share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t h, int64_t n) {
+    const int64_t x = h % kXcds, s = h / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // ---------------------------------------------------------- plain FP64 forms
 
 // One thread per (observer, sample): loop over panels, interpolate each channel.
@@ -386,9 +396,12 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
 }
 
 template <typename TS>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a) {
+__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    gather_lds_body<TS>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+    // 1-D grid, block order (tile fastest, k block, split) regrouped per XCD
+    const int64_t L = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t = L % tiles, rest = L / tiles;
+    gather_lds_body<TS>(a, t, rest % kblocks, rest / kblocks, smem_raw);
 }
 
 // Persistent batched gather: blocks pull work items (case, tile, k-block, split)
@@ -532,7 +545,8 @@ __device__ __forceinline__ void adj_gather_dpp_body(const AdjArgs &a, int64_t wa
 }
 
 __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
-    adj_gather_dpp_body(a, (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    // consecutive blocks (the waves of neighbouring panels) regrouped per XCD
+    adj_gather_dpp_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(256) void adj_gather_dpp_batched(const BatchCase *__restrict__ cases,
@@ -596,12 +610,13 @@ hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *t
                              double *partial, hipStream_t stream) {
     const int64_t p_chunk = (P + splits - 1) / splits;
     const GatherArgs a{rec_op, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
-    dim3 grid((unsigned)((O + kObsTile - 1) / kObsTile), (unsigned)((nt_max + kLdsK - 1) / kLdsK), (unsigned)splits);
+    const int64_t tiles = (O + kObsTile - 1) / kObsTile, kblocks = (nt_max + kLdsK - 1) / kLdsK;
+    const dim3 n1((unsigned)(tiles * kblocks * splits));
     const size_t shmem = gather_lds_shmem(coef_type, NW, PT);
     if (coef_type == 1)
-        gather_lds_kernel<float><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(a);
+        gather_lds_kernel<float><<<n1, dim3(kLdsWaves * 64), shmem, stream>>>(a, tiles, kblocks);
     else
-        gather_lds_kernel<uint16_t><<<grid, dim3(kLdsWaves * 64), shmem, stream>>>(a);
+        gather_lds_kernel<uint16_t><<<n1, dim3(kLdsWaves * 64), shmem, stream>>>(a, tiles, kblocks);
     return hipGetLastError();
 }
 
