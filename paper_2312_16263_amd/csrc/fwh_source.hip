@@ -248,15 +248,21 @@ struct SrcLane {
         s_der = der ? 1.0 / (2.0 * a.f.dtau) : 0.0;
         s_val = der ? 0.0 : 1.0;
     }
-    // source term at time row m (offset m * P from this panel)
-    __device__ __forceinline__ double X(int64_t off) const {
-        const double r = (double)rho[off];
-        const double u1 = (double)u[off], u2 = (double)u[NP + off], u3 = (double)u[2 * NP + off];
-        const double pv = (double)pp[off];
+    // the five inputs at time row m (offset m * P from this panel)
+    struct Raw {
+        TIn r, u1, u2, u3, p;
+    };
+    __device__ __forceinline__ Raw load(int64_t off) const {
+        return Raw{rho[off], u[off], u[NP + off], u[2 * NP + off], pp[off]};
+    }
+    __device__ __forceinline__ double X(const Raw &v) const {
+        const double r = (double)v.r;
+        const double u1 = (double)v.u1, u2 = (double)v.u2, u3 = (double)v.u3;
         const double un = u1 * nx + u2 * ny + u3 * nz;
         const double bu = b1 * u1 + b2 * u2 + b3 * u3 - gm;
-        return al * pv + r * bu * un - dl;
+        return al * (double)v.p + r * bu * un - dl;
     }
+    __device__ __forceinline__ double X(int64_t off) const { return X(load(off)); }
 };
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -275,15 +281,15 @@ __device__ __forceinline__ void store_quad(bf16s *dst, const float *v) {
     *reinterpret_cast<uint2 *>(dst) = w;
 }
 
-// tile[q * kSrcRS + c * 32 + pl] (q < kSrcTC) -> coef quads; a wave writes 64
-// consecutive indices of one panel and channel group.
-template <typename TOut>
+// tile[q * kSrcRS + c * 32 + pl] (q < TC) -> coef quads; a wave writes TC
+// consecutive indices of one panel and channel group (64 / TC groups per wave).
+template <typename TOut, int TC = kSrcTC>
 __device__ __forceinline__ void src_flush(const float *tile, TOut *coef, int64_t pbase, int64_t P, int64_t NS,
                                           int64_t i0) {
-    for (int e = threadIdx.x; e < kSrcPanels * 2 * kSrcTC; e += 256) {
-        const int pl = e / (2 * kSrcTC);
-        const int g = (e / kSrcTC) & 1;
-        const int q = e & (kSrcTC - 1);
+    for (int e = threadIdx.x; e < kSrcPanels * 2 * TC; e += 256) {
+        const int pl = e / (2 * TC);
+        const int g = (e / TC) & 1;
+        const int q = e & (TC - 1);
         const int64_t p = pbase + pl;
         if (p < P) {
             float v[4];
@@ -296,8 +302,16 @@ __device__ __forceinline__ void src_flush(const float *tile, TOut *coef, int64_t
 
 // Interior chunk: rows [R0, R0 + kSrcW) all in [kSrcPivotRows, N - 3], source
 // terms read from rows [R0 - 3, R0 + kSrcW + 2] inside the record, central
-// differences throughout, constant pivot: no branches; the reduced right-hand
-// sides stay in registers.
+// differences throughout, constant pivot: no branches.  The inputs are loaded
+// kSrcAhead rows ahead of their use (a register ring); the reduced right-hand
+// sides stay in registers and are overwritten by the coefficients during back
+// substitution.  Output: the upper and then the lower half of the chunk go
+// through a [kSrcTC / 2][kSrcRS] LDS tile.
+template <typename TIn>
+struct SrcAhead {
+    static constexpr int value = sizeof(TIn) == 4 ? 8 : 4;
+};
+
 template <typename TIn, typename TOut>
 __device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t pbk, int64_t i0, float *tile) {
     const int64_t P = a.P;
@@ -305,46 +319,57 @@ __device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t 
     const int64_t pbase = pbk * kSrcPanels;
     const int64_t pc = min(pbase + pl, P - 1);
     const SrcLane<TIn> L(a, pc);
+    using Raw = typename SrcLane<TIn>::Raw;
+    constexpr int D = SrcAhead<TIn>::value;
     const double cpi = 2.0 - sqrt(3.0);
     const int64_t R0 = i0 - 1 - kSrcH;
-    int64_t off = (R0 - 3) * P;
-    double Xa = L.X(off), Xb = L.X(off + P), Xc = L.X(off + 2 * P), Xd = L.X(off + 3 * P), Xe = L.X(off + 4 * P);
-    off += 5 * P;  // next row to load: R0 + 2
+    const int64_t off0 = (R0 - 3) * P;
+    constexpr int NX = kSrcW + 6;  // source-term rows R0 - 3 .. R0 + kSrcW + 2
+    Raw ring[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ring[k] = L.load(off0 + k * P);
+    // X of row R0 - 3 + k; refills the ring slot with row k + D
+    auto Xk = [&](int k) {
+        const double x = L.X(ring[k % D]);
+        if (k + D < NX) ring[k % D] = L.load(off0 + (k + D) * P);
+        return x;
+    };
+    double Xa = Xk(0), Xb = Xk(1), Xc = Xk(2), Xd = Xk(3), Xe = Xk(4);
     float dv[kSrcW];
     double fprev = 0.0, dprev = 0.0;
     constexpr int ITER = kSrcW + 2;  // n = R0 - 1 .. R0 + kSrcW
 #pragma unroll
-    for (int g0 = 0; g0 < ITER; g0 += kSrcPF) {
-        double Xf[kSrcPF];
-#pragma unroll
-        for (int q = 0; q < kSrcPF; ++q)  // rows up to R0 + kSrcW + 2 (the last iteration needs no new row)
-            Xf[q] = (g0 + q < ITER - 1) ? L.X(off + q * P) : 0.0;
-        off += kSrcPF * P;
-#pragma unroll
-        for (int q = 0; q < kSrcPF; ++q) {
-            const int it = g0 + q;
-            if (it < ITER) {
-                const double fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
-                if (it >= 2) {
-                    const double d = (6.0 * fprev - dprev) * cpi;
-                    dprev = d;
-                    dv[it - 2] = (float)d;
-                }
-                fprev = fn;
-                Xa = Xb;
-                Xb = Xc;
-                Xc = Xd;
-                Xd = Xe;
-                Xe = Xf[q];
-            }
+    for (int it = 0; it < ITER; ++it) {
+        const double fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
+        if (it >= 2) {
+            const double d = (6.0 * fprev - dprev) * cpi;
+            dprev = d;
+            dv[it - 2] = (float)d;
         }
+        fprev = fn;
+        Xa = Xb;
+        Xb = Xc;
+        Xc = Xd;
+        Xd = Xe;
+        if (it + 1 < ITER) Xe = Xk(it + 5);  // the last iteration needs no new row
     }
     (void)Xa;
     double x = 0.0;
 #pragma unroll
     for (int s = kSrcW - 1; s >= 0; --s) {
         x = (double)dv[s] - cpi * x;
-        if (s >= kSrcH && s < kSrcH + kSrcTC) tile[(s - kSrcH) * kSrcRS + L.ch * 32 + pl] = (float)x;
+        dv[s] = (float)x;
+    }
+    const int col = L.ch * 32 + pl;
+    TOut *coef = static_cast<TOut *>(a.coef);
+    constexpr int HT = kSrcTC / 2;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();  // the first half's flush has read the tile
+#pragma unroll
+        for (int q = 0; q < HT; ++q) tile[q * kSrcRS + col] = dv[kSrcH + half * HT + q];
+        __syncthreads();
+        src_flush<TOut, HT>(tile, coef, pbase, P, a.NS, i0 + half * HT);
     }
 }
 
@@ -432,10 +457,8 @@ __device__ __forceinline__ void src_chunk_general(const SrcFwdArgs &a, int64_t p
 
 template <typename TIn, typename TOut>
 __device__ __forceinline__ void src_interior_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
-    __shared__ float tile[kSrcTC * kSrcRS];
+    __shared__ float tile[(kSrcTC / 2) * kSrcRS];
     src_chunk_interior<TIn, TOut>(a, pbk, k * kSrcTC, tile);
-    __syncthreads();
-    src_flush(tile, static_cast<TOut *>(a.coef), pbk * kSrcPanels, a.P, a.NS, k * kSrcTC);
 }
 
 template <typename TIn, typename TOut>
@@ -460,7 +483,7 @@ __device__ __forceinline__ void src_general_block(const SrcFwdArgs &a, int64_t p
 
 // Xbar of 8 channels at (frame m, panel) from tile[(m - m0) * kSrcRS + c * 32 + pl];
 // chain rule; gradients out time-major (32 consecutive panels per frame).
-template <typename TIn>
+template <typename TIn, int TC = kSrcTC>
 __device__ __forceinline__ void src_adj_chain_out(const float *tile, const SrcAdjArgs &a, int64_t pbase, int64_t m0) {
     const int64_t P = a.P, N = a.N, NP = N * P;
     const TIn *__restrict__ rho = static_cast<const TIn *>(a.rho);
@@ -473,25 +496,40 @@ __device__ __forceinline__ void src_adj_chain_out(const float *tile, const SrcAd
     if (p >= P) return;
     const double nx = a.normal[3 * p], ny = a.normal[3 * p + 1], nz = a.normal[3 * p + 2];
     const double Ux = a.f.ca, Uy = a.f.sa;
-    for (int ml = threadIdx.x >> 5; ml < kSrcTC; ml += 8) {
+    // all of this thread's frames are loaded before any gradient is stored
+    constexpr int NF = TC / 8;
+    TIn vr[NF], v1[NF], v2[NF], v3[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int64_t m = m0 + (threadIdx.x >> 5) + 8 * f;
+        const int64_t idx = (m < N ? m : N - 1) * P + p;
+        vr[f] = rho[idx];
+        v1[f] = u[idx];
+        v2[f] = u[NP + idx];
+        v3[f] = u[2 * NP + idx];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int ml = (threadIdx.x >> 5) + 8 * f;
         const int64_t m = m0 + ml;
-        if (m >= N) break;
-        const float *t = tile + ml * kSrcRS + pl;
-        const double Qb = (double)t[0] + (double)t[32];
-        const double L1 = (double)t[2 * 32] + (double)t[5 * 32];
-        const double L2 = (double)t[3 * 32] + (double)t[6 * 32];
-        const double L3 = (double)t[4 * 32] + (double)t[7 * 32];
-        const int64_t idx = m * P + p;
-        const double r = (double)rho[idx];
-        const double u1 = (double)u[idx], u2 = (double)u[NP + idx], u3 = (double)u[2 * NP + idx];
-        const double un = u1 * nx + u2 * ny + u3 * nz;
-        const double w1 = u1 - Ux, w2 = u2 - Uy, w3 = u3;
-        const double S = Qb + L1 * w1 + L2 * w2 + L3 * w3;
-        g_rho[idx] = (TIn)(un * S);
-        g_u[idx] = (TIn)(r * nx * S + r * un * L1);
-        g_u[NP + idx] = (TIn)(r * ny * S + r * un * L2);
-        g_u[2 * NP + idx] = (TIn)(r * nz * S + r * un * L3);
-        g_p[idx] = (TIn)(L1 * nx + L2 * ny + L3 * nz);
+        if (m < N) {
+            const float *t = tile + ml * kSrcRS + pl;
+            const double Qb = (double)t[0] + (double)t[32];
+            const double L1 = (double)t[2 * 32] + (double)t[5 * 32];
+            const double L2 = (double)t[3 * 32] + (double)t[6 * 32];
+            const double L3 = (double)t[4 * 32] + (double)t[7 * 32];
+            const int64_t idx = m * P + p;
+            const double r = (double)vr[f];
+            const double u1 = (double)v1[f], u2 = (double)v2[f], u3 = (double)v3[f];
+            const double un = u1 * nx + u2 * ny + u3 * nz;
+            const double w1 = u1 - Ux, w2 = u2 - Uy, w3 = u3;
+            const double S = Qb + L1 * w1 + L2 * w2 + L3 * w3;
+            g_rho[idx] = (TIn)(un * S);
+            g_u[idx] = (TIn)(r * nx * S + r * un * L1);
+            g_u[NP + idx] = (TIn)(r * ny * S + r * un * L2);
+            g_u[2 * NP + idx] = (TIn)(r * nz * S + r * un * L3);
+            g_p[idx] = (TIn)(L1 * nx + L2 * ny + L3 * nz);
+        }
     }
 }
 
@@ -566,18 +604,27 @@ __device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pb
             for (int j = 0; j < 8; ++j) cur[j] = nxt[j];
         }
     }
-    __syncthreads();  // slabs done: the LDS becomes the Xbar tile
-    // back substitution; Xbar_m once fbar_{m-1} is known (window row s = m - m0 + kAdjLo - 1)
+    // back substitution; Xbar_m once fbar_{m-1} is known (window row s = m - m0 + kAdjLo - 1),
+    // kept in place of the consumed right-hand side dv[s]
     double z = 0.0, fp1 = 0.0, fc = 0.0;
 #pragma unroll
     for (int s = kAdjW - 1; s >= 0; --s) {
         z = (double)dv[s] - cpi * z;
         const double fm1 = 6.0 * z;
         const int ml = s - kAdjLo + 1;  // frame m = m0 + ml has fbar_{m-1} = fm1
-        if (ml >= 0 && ml < kSrcTC)
-            lds[ml * kSrcRS + myrow] = (float)(L.s_val * fc + L.s_der * (fm1 - fp1));
+        if (ml >= 0 && ml < kSrcTC) dv[s] = (float)(L.s_val * fc + L.s_der * (fm1 - fp1));
         fp1 = fc;
         fc = fm1;
+    }
+    // chain rule in two halves of kSrcTC / 2 frames through a [kSrcTC / 2][kSrcRS] tile
+    constexpr int HT = kSrcTC / 2;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();  // the slabs (first half) or the previous half's tile have been read
+#pragma unroll
+        for (int q = 0; q < HT; ++q) lds[q * kSrcRS + myrow] = dv[half * HT + q + kAdjLo - 1];
+        __syncthreads();
+        src_adj_chain_out<TIn, HT>(lds, a, pbase, m0 + half * HT);
     }
 }
 
@@ -654,10 +701,10 @@ __device__ __forceinline__ void src_adj_general(const SrcAdjArgs &a, int64_t pbk
 
 template <typename TIn>
 __device__ __forceinline__ void src_adj_interior_block(const SrcAdjArgs &a, int64_t pbk, int64_t k) {
-    __shared__ float lds[kSrcTC * kSrcRS];
+    // slabs [256][kAdjSlabRS], then the Xbar tile [kSrcTC / 2][kSrcRS]
+    constexpr int kWords = 256 * kAdjSlabRS > (kSrcTC / 2) * kSrcRS ? 256 * kAdjSlabRS : (kSrcTC / 2) * kSrcRS;
+    __shared__ float lds[kWords];
     src_adj_interior<TIn>(a, pbk, k, lds);
-    __syncthreads();
-    src_adj_chain_out<TIn>(lds, a, pbk * kSrcPanels, k * kSrcTC);
 }
 
 template <typename TIn>
@@ -851,7 +898,7 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(SrcFwdArgs a) {
 
 // grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
 template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) void src_interior_kernel(SrcFwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_kernel(SrcFwdArgs a) {
     src_interior_block<TIn, TOut>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
 }
 // grid (panel blocks, general chunks)
@@ -861,7 +908,7 @@ __global__ __launch_bounds__(256) void src_general_kernel(SrcFwdArgs a) {
 }
 // batched: blocks of case c are [start[c], start[c+1]), panel block major
 template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) void src_interior_batched(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_batched(const BatchCase *__restrict__ cases,
                                                             const int64_t *__restrict__ start, int n) {
     const int c = find_case(start, n, blockIdx.x);
     const int64_t local = (int64_t)blockIdx.x - start[c];
