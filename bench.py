@@ -31,6 +31,21 @@ HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
 FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: non-packed FP32 FMA (packed FP32 is not used)
 FP32_PACKED_PEAK = 157.3e12       # published FP32 vector peak (needs packed FP32 FMA)
 FLOP_PER_UNIT = 24                # 8 FMA channel combine + 4 FMA taps per (panel, observer, sample)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_dipole32768_f32.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (read + written, copy-calibrated) from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                if len(cells) == 5 and cells[0].strip("`") == kernel:
+                    return (float(cells[3]) + float(cells[4])) * 1e9
+    except (OSError, ValueError):
+        return None
+    return None
 
 
 def log(*a):
@@ -270,9 +285,14 @@ def main():
     dom = "gather" if avg["gather"] >= avg["adj_gather"] else "adj_gather"
     t_dom = avg[dom] * 1e-3
     achieved = FLOP_PER_UNIT * U / t_dom / 1e12
-    roofline = {"bound": "alu", "kernel": "gather_lds_kernel<float>" if dom == "gather" else
-                "adj_gather_dpp_kernel", "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": None,
+    dom_kernel = "gather_lds_kernel<float>" if dom == "gather" else "adj_gather_dpp_kernel"
+    # algorithmic bytes per launch: coefficients (8 channels FP32 over NS) + pair records + output/input signal
+    NSd = ((c.n_tau + 12 + 63) // 64) * 64
+    alg_bytes = 8 * 4 * c.n_panels * NSd + 64 * c.n_obs * c.n_panels + 4 * c.n_obs * int(nt.max())
+    roofline = {"bound": "alu", "kernel": dom_kernel, "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": measured_traffic(dom_kernel),
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes": alg_bytes,
                 "frac_of_packed_fp32_peak": achieved * 1e12 / FP32_PACKED_PEAK,
                 "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom]}
     # source stage: HBM-bound streaming (inputs read once, coefficients written once)
