@@ -72,3 +72,55 @@ def test_fullsize_adjoint_sampled(mode):
         err = rel_l2(gv.double().cpu().numpy(), gr)
         print(f"    d/d{name}: rel L2 vs oracle = {err:.3e}", flush=True)
         assert err <= TOL_ADJ[mode], (name, err)
+
+
+def test_fullsize_adjoint_central_differences():
+    """dJ/d(rho, u_i, p') of J = sum p'^2 at the full size, on 64 seeded entries:
+    central differences of J evaluated with the plain FP64 GPU forward (J is
+    quadratic in p' and quartic in rho, u; h = 1e-4) against the FP64 and the
+    FP32 adjoint through the C ABI."""
+    import torch
+    st = _setup()
+    c = st["case"]
+    rho, u, pp = st["data"]
+    d = to_device((rho, u, pp))
+    plan64 = make_plan(c, "f64")
+    plan32 = make_plan(c, "f32")
+
+    def J():
+        p = plan64.forward(*d)
+        return float((p * p).sum().item())
+
+    p64 = plan64.forward(*d)
+    g64 = plan64.adjoint(*d, 2.0 * p64)
+    g32 = plan32.adjoint(*d, (2.0 * p64).float())
+    rng = np.random.default_rng(2312)
+    h = 1e-4
+    fd, a64, a32 = [], [], []
+    for e in range(64):
+        v = int(rng.integers(0, 5))           # 0 rho, 1..3 u_i, 2 + ... p'
+        n = int(rng.integers(0, c.n_tau))
+        pnl = int(rng.integers(0, c.n_panels))
+        if v == 0:
+            x, idx, gi = d[0], (n, pnl), 0
+        elif v <= 3:
+            x, idx, gi = d[1], (v - 1, n, pnl), 1
+        else:
+            x, idx, gi = d[2], (n, pnl), 2
+        x0 = x[idx].item()
+        x[idx] = x0 + h
+        jp = J()
+        x[idx] = x0 - h
+        jm = J()
+        x[idx] = x0
+        fd.append((jp - jm) / (2 * h))
+        a64.append(g64[gi][idx].item())
+        a32.append(g32[gi][idx].item())
+    torch.cuda.synchronize()
+    fd, a64, a32 = np.array(fd), np.array(a64), np.array(a32)
+    e64 = np.linalg.norm(a64 - fd) / np.linalg.norm(fd)
+    e32 = np.linalg.norm(a32 - fd) / np.linalg.norm(fd)
+    print(f"    64 entries, |dJ| rms {np.sqrt(np.mean(fd * fd)):.3e}: rel L2 FP64 adjoint vs FD {e64:.3e}, "
+          f"FP32 adjoint vs FD {e32:.3e}", flush=True)
+    assert e64 <= 1e-6, e64
+    assert e32 <= 1e-4, e32
