@@ -14,6 +14,8 @@
 // applies the 4 taps (4 FMA per output): 12 FMA per (panel, observer, sample).
 // No matrix cores: the contraction over channels has length 8 and each pair
 // has its own shift, so the work is a shifted gather, not a dense GEMM.
+#include <type_traits>
+
 #include "fwh_internal.h"
 
 namespace fwh {
@@ -305,6 +307,47 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             acc[j][m] = 0.f;
             accd[j][m] = 0.0;
         }
+    // sub-rows of 61 samples below the largest window of this wave's observers (0: nothing to do)
+    int nt_wave = 0;
+#pragma unroll
+    for (int j = 0; j < kObsPerWave; ++j)
+        if (obase + j < O) nt_wave = nt[obase + j] > nt_wave ? nt[obase + j] : nt_wave;
+    int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
+    nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > kLdsSub ? kLdsSub : nsub));
+    // one panel of the stage for this wave's observers, NSUB sub-rows
+    auto panel_work = [&](auto nsub_c, const float4 *lrec, const QT *L0, const QT *L1, int lo, int q) {
+        constexpr int NSUB = decltype(nsub_c)::value;
+#pragma unroll
+        for (int j = 0; j < kObsPerWave; ++j) {
+            const float4 *R = lrec + (q * kObsTile + wv * kObsPerWave + j) * 4;
+            const float4 Ka = R[0], Kb = R[1], W = R[2];
+            const int off = __float_as_int(R[3].x) - lo;
+#pragma unroll
+            for (int m = 0; m < NSUB; ++m) {
+                const int idx = off + m * kLdsLanesOut + lane;
+                float a[4], c[4];
+                Quad<TS>::unpack(L0[idx], a);
+                Quad<TS>::unpack(L1[idx], c);
+                float g = Ka.x * a[0];
+                g = fmaf(Ka.y, a[1], g);
+                g = fmaf(Ka.z, a[2], g);
+                g = fmaf(Ka.w, a[3], g);
+                g = fmaf(Kb.x, c[0], g);
+                g = fmaf(Kb.y, c[1], g);
+                g = fmaf(Kb.z, c[2], g);
+                g = fmaf(Kb.w, c[3], g);
+                const float g1 = from_next_lane(g);
+                const float g2 = from_next_lane(g1);
+                const float g3 = from_next_lane(g2);
+                float ac = acc[j][m];
+                ac = fmaf(W.x, g, ac);
+                ac = fmaf(W.y, g1, ac);
+                ac = fmaf(W.z, g2, ac);
+                ac = fmaf(W.w, g3, ac);
+                acc[j][m] = ac;
+            }
+        }
+    };
     int cnt = 0;
     int b = 0;
     // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
@@ -333,38 +376,13 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
             const QT *L1 = L0 + NW;
             // every record slot of the tile holds a valid record (slots past the last
-            // observer repeat it), so a wave with any observer runs all kObsPerWave
-            if (obase < O) {
-#pragma unroll
-                for (int j = 0; j < kObsPerWave; ++j) {
-                    const float4 *R = lrec + (q * kObsTile + wv * kObsPerWave + j) * 4;
-                    const float4 Ka = R[0], Kb = R[1], W = R[2];
-                    const int off = __float_as_int(R[3].x) - lo;
-#pragma unroll
-                    for (int m = 0; m < kLdsSub; ++m) {
-                        const int idx = off + m * kLdsLanesOut + lane;
-                        float a[4], c[4];
-                        Quad<TS>::unpack(L0[idx], a);
-                        Quad<TS>::unpack(L1[idx], c);
-                        float g = Ka.x * a[0];
-                        g = fmaf(Ka.y, a[1], g);
-                        g = fmaf(Ka.z, a[2], g);
-                        g = fmaf(Ka.w, a[3], g);
-                        g = fmaf(Kb.x, c[0], g);
-                        g = fmaf(Kb.y, c[1], g);
-                        g = fmaf(Kb.z, c[2], g);
-                        g = fmaf(Kb.w, c[3], g);
-                        const float g1 = from_next_lane(g);
-                        const float g2 = from_next_lane(g1);
-                        const float g3 = from_next_lane(g2);
-                        float ac = acc[j][m];
-                        ac = fmaf(W.x, g, ac);
-                        ac = fmaf(W.y, g1, ac);
-                        ac = fmaf(W.z, g2, ac);
-                        ac = fmaf(W.w, g3, ac);
-                        acc[j][m] = ac;
-                    }
-                }
+            // observer repeat it); the wave skips the sub-rows past its observers' windows
+            switch (nsub) {
+                case 0: break;
+                case 1: panel_work(std::integral_constant<int, 1>{}, lrec, L0, L1, lo, q); break;
+                case 2: panel_work(std::integral_constant<int, 2>{}, lrec, L0, L1, lo, q); break;
+                case 3: panel_work(std::integral_constant<int, 3>{}, lrec, L0, L1, lo, q); break;
+                default: panel_work(std::integral_constant<int, kLdsSub>{}, lrec, L0, L1, lo, q); break;
             }
             if (++cnt == kChunk) {
 #pragma unroll
