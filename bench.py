@@ -102,6 +102,28 @@ def bench_airfoil(steps, sync):
         out[mode] = {"value": U / (ms * 1e-3), "ms_per_step": ms, "err_vs_oracle": err,
                      "stage_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in st.items()}}
         log(f"[bench] airfoil {mode}: {ms:.2f} ms/step, {U / (ms * 1e-3):.3e} units/s, err {err:.3e}")
+        if mode == "f32":
+            # post-processing of Sec. IV C on the device: RMS and Welch PSD (1024-sample Hann segments, 50 %
+            # overlap, spanwise correction 650 / 50.8) of all observers, against the oracle on the sample
+            from oracle import post
+            pt = plan.forward(*d)
+            seg, span = 1024, 650.0 / 50.8
+            plan.post(pt, seg, span)
+            sync()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                psd, rms = plan.post(pt, seg, span)
+            sync()
+            ms_post = (time.perf_counter() - t0) * 1e3 / 5
+            pn = pt.double().cpu().numpy()[sample]
+            nts = plan.window.n_t[sample]
+            e_psd = rel_l2(psd.double().cpu().numpy()[sample], post.welch_all(pn, nts, c.dtau, seg, span),
+                           np.ones((len(sample), seg // 2 + 1)))
+            e_rms = rel_l2(rms.double().cpu().numpy()[sample][:, None], post.rms(pn, nts)[:, None],
+                           np.ones((len(sample), 1)))
+            out["post"] = {"seg_len": seg, "span_ratio": span, "ms": ms_post, "psd_err_vs_oracle": e_psd,
+                           "rms_err_vs_oracle": e_rms}
+            log(f"[bench] airfoil post (RMS + Welch PSD, L={seg}): {ms_post:.3f} ms, errs {e_psd:.2e} {e_rms:.2e}")
         out["units_per_step"] = U
         del plan
         torch.cuda.empty_cache()

@@ -194,6 +194,21 @@ void fwh_batch_destroy(fwh_batch *batch);
 /* Release the plan (host memory only; the workspace stays the caller's). */
 void fwh_destroy(fwh_plan *plan);
 
+/* Post-processing of a forward result p_out ([O][n_t_max] as written by
+ * fwh_forward on this plan, same type) for the comparisons of Sec. IV:
+ *   rms [O] (float): sqrt of the mean of p'^2 over each observer's N_t samples
+ *   (the RMS directivity of Sec. IV A-B);
+ *   psd [O][seg_len/2 + 1] (float): one-sided Welch power spectral density of
+ *   each observer's N_t samples (Sec. IV C): segments of seg_len samples with
+ *   50 % overlap, periodic Hann window, averaged |DFT|^2 scaled to a density
+ *   c_f / (n_seg f_s sum w^2) with f_s = 1/dtau and c_f = 2 except at f = 0
+ *   and f_s/2, times span_ratio (the spanwise correction b_exp / b_m of
+ *   Eq. (PSD_corr); 1 for none).  Frequency f_k = k / (seg_len dtau).
+ * seg_len: power of two in [16, 4096], <= every N_t (FWH_ESIZE otherwise).
+ * Device pointers, caller-owned; enqueued on `stream`, nothing allocated. */
+int fwh_post(const fwh_plan *plan, const void *p_out, int64_t seg_len, double span_ratio, float *psd, float *rms,
+             void *stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *fwh_last_error(void);
 

@@ -26,7 +26,7 @@ ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW
                FWH_ESTATE: "FWH_ESTATE"}
 
 # names declared in include/fwh.h
-EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_profile_enable",
+EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_post", "fwh_profile_enable",
             "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_bind", "fwh_batch_forward",
             "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_last_error",
             "fwh_version"]
@@ -75,6 +75,8 @@ def lib():
         L.fwh_forward.restype = ctypes.c_int
         L.fwh_adjoint.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fwh_adjoint.restype = ctypes.c_int
+        L.fwh_post.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp]
+        L.fwh_post.restype = ctypes.c_int
         L.fwh_profile_enable.argtypes = [vp, ctypes.c_int]
         L.fwh_profile_enable.restype = ctypes.c_int
         L.fwh_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -227,6 +229,20 @@ class Plan:
                                      ctypes.c_void_p(g_u.data_ptr()), ctypes.c_void_p(g_p.data_ptr()),
                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
         return g_r, g_u, g_p
+
+    def post(self, p, seg_len, span_ratio=1.0):
+        """Per-observer RMS [O] and one-sided Welch PSD [O, seg_len/2 + 1] (Hann window, 50 % overlap,
+        times span_ratio) of a forward result p; frequencies k / (seg_len * dtau).  float32 tensors."""
+        import torch
+        if tuple(p.shape) != (self.O, self.window.n_t_max) or p.dtype != self.out_dtype or not p.is_contiguous():
+            raise ValueError("p must be a contiguous forward result of this plan")
+        psd = torch.empty((self.O, seg_len // 2 + 1), dtype=torch.float32, device=self.device)
+        rms = torch.empty((self.O,), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().fwh_post(self._h, ctypes.c_void_p(p.data_ptr()), int(seg_len), float(span_ratio),
+                                  ctypes.c_void_p(psd.data_ptr()), ctypes.c_void_p(rms.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return psd, rms
 
 
 def _stream():

@@ -391,6 +391,26 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
     return FWH_OK;
 }
 
+int fwh_post(const fwh_plan *pl, const void *p_out, int64_t seg_len, double span_ratio, float *psd, float *rms,
+             void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_post: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_post: plan is not set up");
+    if (!p_out || !psd || !rms) return fail(FWH_EINVAL, "fwh_post: null pointer");
+    if (seg_len < 16 || seg_len > 4096 || (seg_len & (seg_len - 1)))
+        return fail(FWH_ESIZE, "fwh_post: seg_len must be a power of two in [16, 4096] (got %lld)",
+                    (long long)seg_len);
+    if (!(span_ratio > 0.0) || !std::isfinite(span_ratio)) return fail(FWH_EINVAL, "fwh_post: span_ratio must be > 0");
+    for (int64_t o = 0; o < pl->O; ++o)
+        if (pl->n_t[o] < seg_len)
+            return fail(FWH_ESIZE, "fwh_post: observer %lld has %lld samples, fewer than seg_len %lld", (long long)o,
+                        (long long)pl->n_t[o], (long long)seg_len);
+    hipError_t e = fwh::launch_post(pl->mode == FWH_MODE_F64 ? 0 : 1, p_out, pl->n_t_max, pl->at<int32_t>(pl->off_nt),
+                                    pl->O, (int)seg_len, pl->flow.dtau, span_ratio, psd, rms, as_stream(stream_));
+    if (e) return hip_fail("fwh_post", e);
+    return FWH_OK;
+}
+
 int fwh_profile_enable(fwh_plan *pl, int enable) {
     g_last_error.clear();
     if (!pl) return fail(FWH_EINVAL, "fwh_profile_enable: null plan");

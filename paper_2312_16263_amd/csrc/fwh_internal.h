@@ -271,4 +271,11 @@ hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *ca
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
                                 int64_t waves_adj, int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream);
 
+// Post-processing: per-observer RMS and one-sided Welch PSD (segments of L
+// samples, 50 % overlap, Hann window), times span_ratio; psd [O][L/2+1], rms [O].
+// real_type 0 = double signals, 1 = float.  L is a power of two in [16, 4096].
+size_t post_shmem(int L);
+hipError_t launch_post(int real_type, const void *p, int64_t ld, const int32_t *nt, int64_t O, int L, double dt,
+                       double span_ratio, float *psd, float *rms, hipStream_t stream);
+
 }  // namespace fwh

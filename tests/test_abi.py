@@ -100,4 +100,6 @@ def test_setup_and_forward_state_checks():
     assert L.fwh_adjoint(h, fwh.FWH_F64, dummy, dummy, dummy, dummy, dummy, dummy, dummy, None) == fwh.FWH_ESTATE
     assert L.fwh_obs_window(h, None, None, None) == fwh.FWH_ESTATE
     assert b"not set up" in L.fwh_last_error()
+    assert L.fwh_post(h, dummy, 256, 1.0, dummy, dummy, None) == fwh.FWH_ESTATE
+    assert L.fwh_post(None, dummy, 256, 1.0, dummy, dummy, None) == fwh.FWH_EINVAL
     L.fwh_destroy(h)

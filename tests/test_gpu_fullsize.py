@@ -124,3 +124,26 @@ def test_fullsize_adjoint_central_differences():
           f"FP32 adjoint vs FD {e32:.3e}", flush=True)
     assert e64 <= 1e-6, e64
     assert e32 <= 1e-4, e32
+
+
+def test_fullsize_post_sampled():
+    """fwh_post at the full size (segments of 1024 samples, several per
+    observer) on the FP32 forward result, against the oracle's RMS and Welch
+    PSD of the oracle's own signals on the sampled observers."""
+    import torch
+
+    from oracle import post
+    st = _setup()
+    c = st["case"]
+    plan = make_plan(c, "f32")
+    p = plan.forward(*to_device(st["data"]))
+    psd, rms = plan.post(p, 1024)
+    torch.cuda.synchronize()
+    nt = st["nt"][SAMPLED]
+    ref_psd = post.welch_all(st["p_ref"], nt, c.dtau, 1024)
+    ref_rms = post.rms(st["p_ref"], nt)
+    e_psd = rel_l2(psd.double().cpu().numpy()[SAMPLED], ref_psd)
+    e_rms = rel_l2(rms.double().cpu().numpy()[SAMPLED], ref_rms)
+    print(f"    PSD rel L2 {e_psd:.3e}, RMS rel L2 {e_rms:.3e}", flush=True)
+    assert e_psd <= 1e-5, e_psd
+    assert e_rms <= 1e-5, e_rms

@@ -180,3 +180,35 @@ def test_autograd_function(mode):
         err = rel_l2(t.grad.double().cpu().numpy(), gr)
         print(f"    autograd {mode}: rel L2 vs oracle = {err:.3e}", flush=True)
         assert err <= TOL_ADJ[mode], err
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+@pytest.mark.parametrize("seg_len", [16, 64, 256])
+def test_post_rms_and_welch(mode, seg_len):
+    """fwh_post (RMS directivity, Welch PSD with the spanwise correction)
+    on the plan's own forward result against the post-processing oracle on the
+    same signal, element by element; seg_len 256 exceeds some windows of the
+    small case and must be rejected."""
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    from oracle import post
+    c = CASES["foil_bb"]
+    rho, u, pp, _, _, nt_ref = _data("foil_bb")
+    plan = make_plan(c, mode)
+    p = plan.forward(*to_device((rho, u, pp)))
+    if seg_len > int(nt_ref.min()):
+        with pytest.raises(fwh.FwhError) as ei:
+            plan.post(p, seg_len)
+        assert ei.value.code == fwh.FWH_ESIZE
+        return
+    psd, rms = plan.post(p, seg_len, span_ratio=650.0 / 50.8)
+    torch.cuda.synchronize()
+    pn = p.double().cpu().numpy()
+    ref_psd = post.welch_all(pn, nt_ref, c.dtau, seg_len, 650.0 / 50.8)
+    ref_rms = post.rms(pn, nt_ref)
+    e_psd = rel_l2(psd.double().cpu().numpy(), ref_psd)
+    e_rms = rel_l2(rms.double().cpu().numpy(), ref_rms)
+    print(f"    post {mode} L={seg_len}: PSD rel L2 {e_psd:.3e}, RMS rel L2 {e_rms:.3e}", flush=True)
+    assert e_psd <= 1e-5, e_psd
+    assert e_rms <= 1e-6, e_rms
