@@ -302,58 +302,134 @@ __device__ __forceinline__ void src_flush(const float *tile, TOut *coef, int64_t
 
 // Interior chunk: rows [R0, R0 + kSrcW) all in [kSrcPivotRows, N - 3], source
 // terms read from rows [R0 - 3, R0 + kSrcW + 2] inside the record, central
-// differences throughout, constant pivot: no branches.  The inputs are loaded
-// kSrcAhead rows ahead of their use (a register ring); the reduced right-hand
-// sides stay in registers and are overwritten by the coefficients during back
-// substitution.  Output: the upper and then the lower half of the chunk go
-// through a [kSrcTC / 2][kSrcRS] LDS tile.
+// differences throughout, constant pivot: no branches.  The block's inputs (5
+// variables x 32 panels per row) are loaded once, cooperatively and coalesced,
+// in groups of kSrcG rows by direct global -> LDS copies into two buffers:
+// group m + 1 is in flight while group m is used, one barrier per group.  The four
+// waves (four base quantities) then read their source-term inputs from LDS
+// (a broadcast: both half-waves read the same panel's row).  The reduced
+// right-hand sides stay in registers and are overwritten by the coefficients
+// during back substitution; the coefficients leave through a
+// [kSrcTC / 4][kSrcRS] LDS tile in four quarters.
+constexpr int kSrcG = 12;                       // rows per staged group
+constexpr int kSrcNX = kSrcW + 6;               // source-term rows R0 - 3 .. R0 + kSrcW + 2
+constexpr int kSrcNG = (kSrcNX + kSrcG - 1) / kSrcG;
+constexpr int kSrcGV = kSrcG * 5 * kSrcPanels;  // values per group
+
+typedef __attribute__((address_space(3))) void *src_lds_ptr_t;
+
+// Direct global -> LDS copies of the staged groups.  Group m goes to
+// dst[var][r][panel]: variables [rho, u1, u2, u3, p'], source-term rows k =
+// m*kSrcG + r, panels pbase .. pbase + 31.  A piece of 64 dwords (4 bytes per lane)
+// is one (variable, row) in FP64 and two rows of a variable in FP32, so its source
+// address is a wave-uniform base plus the lane's fixed offset lane_off (panel,
+// clamped to P - 1, and the dword half or the second row).  Wave wv issues the
+// pieces wv, wv + 4, ...; pieces whose first row lies past the last row read
+// (k = kSrcW + 4) are skipped.
 template <typename TIn>
-struct SrcAhead {
-    static constexpr int value = sizeof(TIn) == 4 ? 8 : 4;
+struct SrcDma {
+    static constexpr int DW = (int)sizeof(TIn) / 4;  // dwords per value
+    static constexpr int RPP = 2 / DW;               // rows per piece
+    static constexpr int PPV = kSrcG / RPP;          // pieces per variable
+    static constexpr int NPIECE = 5 * PPV;
+    static constexpr int NI = (NPIECE + 3) / 4;      // pieces per wave (at most)
+    const unsigned char *base[NI];                   // source of piece i of group 0 (uniform)
+    int r[NI];                                       // its first row in the group
+    int64_t gstride;                                 // bytes from one group to the next
+
+    __device__ __forceinline__ SrcDma(const SrcFwdArgs &a, int64_t R0, int wv) {
+        const int64_t rowb = a.P * (int64_t)sizeof(TIn);
+        gstride = kSrcG * rowb;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            int pc = wv + 4 * i;
+            pc = pc < NPIECE ? pc : NPIECE - 1;
+            const int var = pc / PPV;
+            r[i] = (pc - var * PPV) * RPP;
+            const unsigned char *v =
+                var == 0 ? static_cast<const unsigned char *>(a.rho)
+                         : (var == 4 ? static_cast<const unsigned char *>(a.pp)
+                                     : static_cast<const unsigned char *>(a.u) + (int64_t)(var - 1) * a.N * rowb);
+            base[i] = v + (R0 - 3 + r[i]) * rowb;
+        }
+    }
+
+    __device__ __forceinline__ void issue(int m, TIn *dst, int wv, uint32_t lane_off) const {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int pc = wv + 4 * i;
+            bool go = (NPIECE % 4 == 0 || i + 1 < NI) ? true : pc < NPIECE;
+            if (m == kSrcNG - 1) go = go && m * kSrcG + r[i] <= kSrcW + 4;
+            if (go)
+                __builtin_amdgcn_global_load_lds((const void *)(base[i] + m * gstride + lane_off),
+                                                 (src_lds_ptr_t)((unsigned char *)dst + pc * 256), 4, 0, 0);
+        }
+    }
 };
 
 template <typename TIn, typename TOut>
-__device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t pbk, int64_t i0, float *tile) {
+__device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0,
+                                                   TIn *ring1, float *tile) {
     const int64_t P = a.P;
     const int pl = threadIdx.x & 31;
     const int64_t pbase = pbk * kSrcPanels;
     const int64_t pc = min(pbase + pl, P - 1);
     const SrcLane<TIn> L(a, pc);
     using Raw = typename SrcLane<TIn>::Raw;
-    constexpr int D = SrcAhead<TIn>::value;
     const double cpi = 2.0 - sqrt(3.0);
     const int64_t R0 = i0 - 1 - kSrcH;
-    const int64_t off0 = (R0 - 3) * P;
-    constexpr int NX = kSrcW + 6;  // source-term rows R0 - 3 .. R0 + kSrcW + 2
-    Raw ring[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) ring[k] = L.load(off0 + k * P);
-    // X of row R0 - 3 + k; refills the ring slot with row k + D
-    auto Xk = [&](int k) {
-        const double x = L.X(ring[k % D]);
-        if (k + D < NX) ring[k % D] = L.load(off0 + (k + D) * P);
-        return x;
-    };
-    double Xa = Xk(0), Xb = Xk(1), Xc = Xk(2), Xd = Xk(3), Xe = Xk(4);
-    float dv[kSrcW];
-    double fprev = 0.0, dprev = 0.0;
-    constexpr int ITER = kSrcW + 2;  // n = R0 - 1 .. R0 + kSrcW
-#pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-        const double fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
-        if (it >= 2) {
-            const double d = (6.0 * fprev - dprev) * cpi;
-            dprev = d;
-            dv[it - 2] = (float)d;
-        }
-        fprev = fn;
-        Xa = Xb;
-        Xb = Xc;
-        Xc = Xd;
-        Xd = Xe;
-        if (it + 1 < ITER) Xe = Xk(it + 5);  // the last iteration needs no new row
+    // two buffers of [rho, u1, u2, u3, p'] x kSrcG rows x 32 panels; group m in buffer m & 1
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    uint32_t lane_off;
+    if constexpr (sizeof(TIn) == 8) {
+        const int64_t p = min(pbase + (lane >> 1), P - 1);
+        lane_off = (uint32_t)(p * 8 + (lane & 1) * 4);
+    } else {
+        const int64_t p = min(pbase + (lane & 31), P - 1);
+        lane_off = (uint32_t)((p + (lane >> 5) * P) * 4);
     }
-    (void)Xa;
+    const SrcDma<TIn> dma(a, R0, wv);
+    dma.issue(0, ring0, wv, lane_off);
+    float dv[kSrcW];
+    // Forward sweep over source-term rows k (row R0 - 3 + k).  Step it (it = 0 .. kSrcW + 1,
+    // right-hand side of row n = R0 - 1 + it) takes X of rows k - 2, k - 1, k with k = it + 3.
+    double X0 = 0.0, X1 = 0.0, X2 = 0.0;
+    double fprev = 0.0, dprev = 0.0;
+#pragma unroll
+    for (int m = 0; m < kSrcNG; ++m) {
+        // this wave's copies of group m have landed; the barrier makes every wave's visible
+        // and frees the other buffer (group m - 1 has been read), which then receives m + 1
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (m + 1 < kSrcNG) dma.issue(m + 1, ((m + 1) & 1) ? ring1 : ring0, wv, lane_off);
+        const TIn *buf = (m & 1) ? ring1 : ring0;
+#pragma unroll
+        for (int r = 0; r < kSrcG; ++r) {
+            const int k = m * kSrcG + r;
+            if (k >= 1 && k <= kSrcW + 4) {
+                const TIn *rw = buf + r * kSrcPanels + pl;
+                constexpr int VS = kSrcG * kSrcPanels;  // variable stride
+                const Raw v{rw[0], rw[VS], rw[2 * VS], rw[3 * VS], rw[4 * VS]};
+                X0 = X1;
+                X1 = X2;
+                X2 = L.X(v);
+                if (k >= 3) {
+                    const int it = k - 3;
+                    const double fn = L.s_der * (X2 - X0) + L.s_val * X1;
+                    if (it >= 2) {
+                        const double d = (6.0 * fprev - dprev) * cpi;
+                        dprev = d;
+                        dv[it - 2] = (float)d;
+                        // computed here, not sunk to the back substitution (which would keep
+                        // every row's inputs live)
+                        asm volatile("" : "+v"(dv[it - 2]));
+                    }
+                    fprev = fn;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
     double x = 0.0;
 #pragma unroll
     for (int s = kSrcW - 1; s >= 0; --s) {
@@ -362,14 +438,14 @@ __device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t 
     }
     const int col = L.ch * 32 + pl;
     TOut *coef = static_cast<TOut *>(a.coef);
-    constexpr int HT = kSrcTC / 2;
+    constexpr int QT = kSrcTC / 4;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        if (half) __syncthreads();  // the first half's flush has read the tile
+    for (int qt = 0; qt < 4; ++qt) {
+        __syncthreads();  // the previous quarter's tile has been read
 #pragma unroll
-        for (int q = 0; q < HT; ++q) tile[q * kSrcRS + col] = dv[kSrcH + half * HT + q];
+        for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dv[kSrcH + qt * QT + q];
         __syncthreads();
-        src_flush<TOut, HT>(tile, coef, pbase, P, a.NS, i0 + half * HT);
+        src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
     }
 }
 
@@ -457,8 +533,10 @@ __device__ __forceinline__ void src_chunk_general(const SrcFwdArgs &a, int64_t p
 
 template <typename TIn, typename TOut>
 __device__ __forceinline__ void src_interior_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
-    __shared__ float tile[(kSrcTC / 2) * kSrcRS];
-    src_chunk_interior<TIn, TOut>(a, pbk, k * kSrcTC, tile);
+    __shared__ TIn ring0[kSrcGV];
+    __shared__ TIn ring1[kSrcGV];
+    __shared__ float tile[(kSrcTC / 4) * kSrcRS];
+    src_chunk_interior<TIn, TOut>(a, pbk, k * kSrcTC, ring0, ring1, tile);
 }
 
 template <typename TIn, typename TOut>
