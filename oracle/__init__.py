@@ -9,7 +9,9 @@ oracle's panel-major [P][N]).
 
 Functions pinned by the non-GPU tests (see tests/test_oracle_*.py):
   pair_geometry, source_terms, fd, spline_m/spline_eval, window, forward,
-  forward_sources, adjoint, adjoint_sources.
+  forward_sources, adjoint, adjoint_sources; general motion (Sec. II B):
+  gm_window, gm_forward, gm_forward_samples, gm_channels
+  (tests/test_oracle_gm.py).
 """
 from __future__ import annotations
 
@@ -67,6 +69,14 @@ def _load():
         _lib.orc_adjoint.restype = ctypes.c_int
         _lib.orc_adjoint_sources.argtypes = [i64, i64, i64, D, D, D, D, f64, f64, f64, f64, D, i64, D, D]
         _lib.orc_adjoint_sources.restype = ctypes.c_int
+        _lib.orc_gm_window.argtypes = [i64, i64, i64, D, D, f64, f64, f64, D, I]
+        _lib.orc_gm_window.restype = ctypes.c_int
+        _lib.orc_gm_forward.argtypes = [i64, i64, i64, D, D, D, D, D, f64, f64, f64, D, D, D, I, i64, D, i64]
+        _lib.orc_gm_forward.restype = ctypes.c_int
+        _lib.orc_gm_forward_samples.argtypes = [i64, i64, i64, D, D, D, D, D, f64, f64, f64, D, D, D, I, I, i64, D]
+        _lib.orc_gm_forward_samples.restype = ctypes.c_int
+        _lib.orc_gm_channels.argtypes = [i64, i64, D, D, D, f64, f64, D, D, D, D]
+        _lib.orc_gm_channels.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = ctypes.c_int
     return _lib
@@ -231,3 +241,81 @@ def adjoint_sources(surf, x_obs, mach, aoa_deg, dtau, tau0, n_tau, gbar):
     _check(lib.orc_adjoint_sources(P, O, N, _d(y), _d(nrm), _d(dS), _d(x_obs), float(mach), float(aoa_deg),
                                    float(dtau), float(tau0), _d(gbar), gbar.shape[1], _d(Qb), _d(Lb)))
     return np.ascontiguousarray(Qb.T), np.ascontiguousarray(np.transpose(Lb, (0, 2, 1)))
+
+
+# ------------------------------------------------------------ general motion
+# Moving surface, medium and observers at rest (Sec. II B).  Interface layout
+# (time-major): y, normal, vel [N,P,3]; rho, p' [N,P]; u [3,N,P].
+
+GM_CHANNELS = ("A", "Qn", "L1", "L2", "L3", "Ld1", "Ld2", "Ld3", "LM", "M1", "M2", "M3",
+               "Md1", "Md2", "Md3", "Msq", "Y1", "Y2", "Y3")
+
+
+def _gm_pm(ms, rho, u, pp):
+    vec = lambda a: _f64(np.transpose(np.asarray(a), (2, 1, 0)))      # [N,P,3] -> [3,P,N]
+    return (vec(ms.y), vec(ms.normal), vec(ms.vel), _f64(ms.dS), _f64(np.asarray(rho).T),
+            _f64(np.transpose(np.asarray(u), (0, 2, 1))), _f64(np.asarray(pp).T))
+
+
+def gm_window(ms, x_obs, mach, dtau, tau0=0.0):
+    """(status, t_start [O], n_t [O]) of the general-motion observer window."""
+    lib = _load()
+    y = _f64(np.transpose(np.asarray(ms.y), (2, 1, 0)))
+    x_obs = _f64(x_obs)
+    N, P = ms.y.shape[0], ms.y.shape[1]
+    O = x_obs.shape[0]
+    ts = np.empty(O)
+    nt = np.empty(O, dtype=np.int64)
+    st = lib.orc_gm_window(P, O, N, _d(y), _d(x_obs), float(mach), float(dtau), float(tau0), _d(ts), _i(nt))
+    return int(st), ts, nt
+
+
+def gm_forward(ms, x_obs, mach, dtau, tau0, rho, u, pp, obs_idx=None, nt_stride=None):
+    """p' [n_sel, nt_stride] (zero padded), t_start [O], n_t [O]."""
+    lib = _load()
+    x_obs = _f64(x_obs)
+    O = x_obs.shape[0]
+    N, P = ms.y.shape[0], ms.y.shape[1]
+    st, ts, nt = gm_window(ms, x_obs, mach, dtau, tau0)
+    if st != 0:
+        raise ValueError("empty observer window")
+    if obs_idx is None:
+        obs_idx = np.arange(O)
+    obs_idx = np.ascontiguousarray(np.asarray(obs_idx, dtype=np.int64))
+    if nt_stride is None:
+        nt_stride = int(nt.max())
+    y, n, v, dS, r, uu, p = _gm_pm(ms, rho, u, pp)
+    out = np.empty((obs_idx.size, nt_stride))
+    st = lib.orc_gm_forward(P, O, N, _d(y), _d(n), _d(v), _d(dS), _d(x_obs), float(mach), float(dtau), float(tau0),
+                            _d(r), _d(uu), _d(p), _i(obs_idx), obs_idx.size, _d(out), int(nt_stride))
+    if st != 0:
+        raise ValueError(f"orc_gm_forward status {st}")
+    return out, ts, nt
+
+
+def gm_forward_samples(ms, x_obs, mach, dtau, tau0, rho, u, pp, s_obs, s_k):
+    """p'(o, k) at the listed (observer, sample) pairs."""
+    lib = _load()
+    x_obs = _f64(x_obs)
+    O = x_obs.shape[0]
+    N, P = ms.y.shape[0], ms.y.shape[1]
+    s_obs = np.ascontiguousarray(np.asarray(s_obs, dtype=np.int64))
+    s_k = np.ascontiguousarray(np.asarray(s_k, dtype=np.int64))
+    y, n, v, dS, r, uu, p = _gm_pm(ms, rho, u, pp)
+    out = np.empty(s_obs.size)
+    st = lib.orc_gm_forward_samples(P, O, N, _d(y), _d(n), _d(v), _d(dS), _d(x_obs), float(mach), float(dtau),
+                                    float(tau0), _d(r), _d(uu), _d(p), _i(s_obs), _i(s_k), s_obs.size, _d(out))
+    if st != 0:
+        raise ValueError(f"orc_gm_forward_samples status {st}")
+    return out
+
+
+def gm_channels(ms, mach, dtau, rho, u, pp):
+    """The 19 observer-independent channels, [19, N, P] (order GM_CHANNELS)."""
+    lib = _load()
+    N, P = ms.y.shape[0], ms.y.shape[1]
+    y, n, v, _, r, uu, p = _gm_pm(ms, rho, u, pp)
+    out = np.empty((len(GM_CHANNELS), P, N))
+    lib.orc_gm_channels(P, N, _d(y), _d(n), _d(v), float(mach), float(dtau), _d(r), _d(uu), _d(p), _d(out))
+    return np.ascontiguousarray(np.transpose(out, (0, 2, 1)))
+

@@ -33,6 +33,10 @@
  *
  * Determinism: panels are summed in fixed blocks of ORC_BLOCK, block partial sums
  * are added in block order, so results do not depend on the thread count.
+ *
+ * A second section (orc_gm_*) is the general-motion form of Sec. II B: a surface
+ * in prescribed motion, medium and observers at rest, Eqs. (pT), (pL) at the
+ * retarded time of Eq. (tau); its readings are listed at the section head.
  */
 #include <math.h>
 #include <stdint.h>
@@ -545,6 +549,266 @@ int orc_adjoint_sources(int64_t P, int64_t O, int64_t N, const double *y, const 
 {
     orc_case cs = {P, O, N, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0};
     return adjoint_core(&cs, 1, NULL, NULL, NULL, gbar, nt_stride, Qbar, Lbar, NULL);
+}
+
+/* ============================================ general motion (Sec. II B) */
+
+/* The surface moves with prescribed kinematics sampled at the source frames
+ * (panel positions y, unit normals n, velocities v); the medium and the observers
+ * are at rest.  Nondimensional as in Sec. II D with the reference speed of the
+ * mach argument: rho0 = 1, c0 = 1/M0, M_i = v_i / c0 = M0 v_i.
+ *
+ * Per panel and frame, Eqs. (Qn), (Li) with P_ij = p' delta_ij (Eq. (Pij)):
+ *   Q_i = v_i + rho (u_i - v_i),   Q_n = Q_i n_i,
+ *   L_i = p' n_i + rho u_i (u_j - v_j) n_j,   L_M = L_i M_i (Eq. (LM)),   M^2 = M_i M_i.
+ * Source-time derivatives of Q_i, n_i, L_i, M_i by orc_fd (second order, one-sided
+ * at the first and last frame).  The observer-independent quantities of the
+ * integrand form 19 channels, each interpolated in source time by its own natural
+ * cubic spline (orc_spline_m / orc_spline_eval):
+ *   A = Qd_i n_i + Q_i nd_i,  Q_n,  L_1..3,  Ld_1..3,  L_M,  M_1..3,  Md_1..3,  M^2,  y_1..3.
+ * Retarded time, Eq. (tau): tau + M0 |x - Y(tau)| = t with Y the splined
+ * trajectory; the left side increases with tau for subsonic motion, so the root
+ * is bracketed by [tau_0, tau_{N-1}] for every t in the observer window and found
+ * by bisection.  At tau_ret: r = x - Y, rhat = r/|r|, M_r = M_i rhat_i,
+ * Md_r = Md_i rhat_i, L_r = L_i rhat_i, Ld_r = Ld_i rhat_i (Eqs. (Mr), (Lr)), and the
+ * integrand of Eqs. (pT) + (pL) times dS / (4 pi):
+ *   A/(r (1-M_r)^2) + Q_n (r Md_r + c0 (M_r - M^2)) / (r^2 (1-M_r)^3)
+ *   + Ld_r / (c0 r (1-M_r)^2) + (L_r - L_M) / (r^2 (1-M_r)^2)
+ *   + L_r (r Md_r + c0 (M_r - M^2)) / (c0 r^2 (1-M_r)^3).
+ * Observer window (the general form of Eqs. (t_start), (t_end)):
+ *   t_start = max_p [tau_0 + M0 |x - y_p(tau_0)|],  t_end = min_p [tau_{N-1} + M0 |x - y_p(tau_{N-1})|],
+ *   t_k = t_start + k dtau, N_t = floor((t_end - t_start)/dtau + 1e-9) + 1.
+ *
+ * Layouts (panel-major, contiguous series): y, n, v [3][P][N]; rho, p' [P][N];
+ * u [3][P][N]. */
+enum {
+    GM_A, GM_QN, GM_L1, GM_L2, GM_L3, GM_LD1, GM_LD2, GM_LD3, GM_LM, GM_M1, GM_M2, GM_M3,
+    GM_MD1, GM_MD2, GM_MD3, GM_MSQ, GM_Y1, GM_Y2, GM_Y3, GM_NCH
+};
+
+typedef struct {
+    int64_t P, O, N;
+    const double *y, *nrm, *vel, *dS, *x_obs;
+    double mach, dtau, tau0;
+} orc_gm_case;
+
+/* Channels of panel p: ch[GM_NCH][N].  work: 9 N doubles. */
+static void gm_channels_panel(const orc_gm_case *cs, const double *rho, const double *u, const double *pp,
+                              int64_t p, double *ch, double *work)
+{
+    const int64_t N = cs->N, P = cs->P;
+    const double M0 = cs->mach, h = cs->dtau;
+    double *Q = work, *Qd = work + 3 * N, *nd = work + 6 * N;
+    for (int64_t n = 0; n < N; ++n) {
+        double v[3], nn[3], uu[3];
+        for (int i = 0; i < 3; ++i) {
+            v[i] = cs->vel[(i * P + p) * N + n];
+            nn[i] = cs->nrm[(i * P + p) * N + n];
+            uu[i] = u[(i * P + p) * N + n];
+        }
+        const double r = rho[p * N + n], pr = pp[p * N + n];
+        const double urel_n = (uu[0] - v[0]) * nn[0] + (uu[1] - v[1]) * nn[1] + (uu[2] - v[2]) * nn[2];
+        double qn = 0.0, lm = 0.0, msq = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            Q[i * N + n] = v[i] + r * (uu[i] - v[i]);
+            qn += Q[i * N + n] * nn[i];
+            const double Li = pr * nn[i] + r * uu[i] * urel_n;
+            const double Mi = M0 * v[i];
+            ch[(GM_L1 + i) * N + n] = Li;
+            ch[(GM_M1 + i) * N + n] = Mi;
+            ch[(GM_Y1 + i) * N + n] = cs->y[(i * P + p) * N + n];
+            lm += Li * Mi;
+            msq += Mi * Mi;
+        }
+        ch[GM_QN * N + n] = qn;
+        ch[GM_LM * N + n] = lm;
+        ch[GM_MSQ * N + n] = msq;
+    }
+    for (int i = 0; i < 3; ++i) {
+        orc_fd(N, Q + i * N, h, Qd + i * N);
+        orc_fd(N, cs->nrm + (i * P + p) * N, h, nd + i * N);
+        orc_fd(N, ch + (GM_L1 + i) * N, h, ch + (GM_LD1 + i) * N);
+        orc_fd(N, ch + (GM_M1 + i) * N, h, ch + (GM_MD1 + i) * N);
+    }
+    for (int64_t n = 0; n < N; ++n) {
+        double a = 0.0;
+        for (int i = 0; i < 3; ++i)
+            a += Qd[i * N + n] * cs->nrm[(i * P + p) * N + n] + Q[i * N + n] * nd[i * N + n];
+        ch[GM_A * N + n] = a;
+    }
+}
+
+static double gm_dist(const double *x, const double *y3) /* |x - y| */
+{
+    const double d0 = x[0] - y3[0], d1 = x[1] - y3[1], d2 = x[2] - y3[2];
+    return sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+/* Retarded time of observer time t for one panel (channels ch, spline moments m). */
+static double gm_retarded(const orc_gm_case *cs, const double *ch, const double *m, const double *x, double t)
+{
+    const int64_t N = cs->N;
+    const double h = cs->dtau, tau0 = cs->tau0, M0 = cs->mach;
+    double lo = tau0, hi = tau0 + (double)(N - 1) * h;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double Y[3];
+        for (int i = 0; i < 3; ++i)
+            Y[i] = orc_spline_eval(N, ch + (GM_Y1 + i) * N, m + (GM_Y1 + i) * N, tau0, h, mid);
+        const double g = mid + M0 * gm_dist(x, Y) - t;
+        if (g < 0.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Integrand of one pair at observer time t (dS / (4 pi) included). */
+static double gm_integrand(const orc_gm_case *cs, const double *ch, const double *m, const double *x, double dS,
+                           double t)
+{
+    const int64_t N = cs->N;
+    const double h = cs->dtau, tau0 = cs->tau0, c0 = 1.0 / cs->mach;
+    const double tau = gm_retarded(cs, ch, m, x, t);
+    double q[GM_NCH];
+    for (int c = 0; c < GM_NCH; ++c) q[c] = orc_spline_eval(N, ch + c * N, m + c * N, tau0, h, tau);
+    double rv[3] = {x[0] - q[GM_Y1], x[1] - q[GM_Y2], x[2] - q[GM_Y3]};
+    const double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+    double Mr = 0.0, Mdr = 0.0, Lr = 0.0, Ldr = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double rh = rv[i] / r;
+        Mr += q[GM_M1 + i] * rh;
+        Mdr += q[GM_MD1 + i] * rh;
+        Lr += q[GM_L1 + i] * rh;
+        Ldr += q[GM_LD1 + i] * rh;
+    }
+    const double om = 1.0 - Mr;
+    const double conv = r * Mdr + c0 * (Mr - q[GM_MSQ]);
+    const double pT = q[GM_A] / (r * om * om) + q[GM_QN] * conv / (r * r * om * om * om);
+    const double pL = Ldr / (c0 * r * om * om) + (Lr - q[GM_LM]) / (r * r * om * om)
+                      + Lr * conv / (c0 * r * r * om * om * om);
+    return (pT + pL) * dS / (4.0 * ORC_PI);
+}
+
+int orc_gm_window(int64_t P, int64_t O, int64_t N, const double *y, const double *x_obs, double mach, double dtau,
+                  double tau0, double *t_start, int64_t *n_t)
+{
+    int st = 0;
+    for (int64_t o = 0; o < O; ++o) {
+        const double *x = x_obs + 3 * o;
+        double ts = -INFINITY, te = INFINITY;
+        for (int64_t p = 0; p < P; ++p) {
+            double y0[3], y1[3];
+            for (int i = 0; i < 3; ++i) {
+                y0[i] = y[(i * P + p) * N];
+                y1[i] = y[(i * P + p) * N + N - 1];
+            }
+            const double a0 = tau0 + mach * gm_dist(x, y0);
+            const double a1 = tau0 + (double)(N - 1) * dtau + mach * gm_dist(x, y1);
+            if (a0 > ts) ts = a0;
+            if (a1 < te) te = a1;
+        }
+        t_start[o] = ts;
+        if (te < ts) {
+            n_t[o] = 0;
+            st = -1;
+        } else {
+            n_t[o] = (int64_t)floor((te - ts) / dtau + 1e-9) + 1;
+        }
+    }
+    return st;
+}
+
+/* p'(o, k) for the requested (observer, sample) pairs, or, with s_k == NULL, every
+ * sample k < N_t of observers s_obs[0..n_s-1] into out[n_s][nt_stride] (zero
+ * padded).  Returns 0, -1 (empty window), -2 (stride too small), -3 (bad sizes). */
+static int gm_core(const orc_gm_case *cs, const double *rho, const double *u, const double *pp, const int64_t *s_obs,
+                   const int64_t *s_k, int64_t n_s, double *out, int64_t nt_stride)
+{
+    const int64_t P = cs->P, N = cs->N, O = cs->O;
+    if (P < 1 || O < 1 || N < 4 || !(cs->mach > 0.0 && cs->mach < 1.0) || !(cs->dtau > 0.0)) return -3;
+    double *t_start = xmalloc((size_t)O);
+    int64_t *n_t = (int64_t *)malloc((size_t)O * sizeof(int64_t));
+    if (orc_gm_window(P, O, N, cs->y, cs->x_obs, cs->mach, cs->dtau, cs->tau0, t_start, n_t) != 0) {
+        free(t_start); free(n_t); return -1;
+    }
+    int64_t n_out;
+    if (s_k == NULL) {
+        for (int64_t s = 0; s < n_s; ++s)
+            if (n_t[s_obs[s]] > nt_stride) { free(t_start); free(n_t); return -2; }
+        n_out = n_s * nt_stride;
+    } else {
+        n_out = n_s;
+    }
+    const int64_t nblk = (P + ORC_BLOCK - 1) / ORC_BLOCK;
+    double *part = (double *)calloc((size_t)nblk * (size_t)n_out, sizeof(double));
+#pragma omp parallel
+    {
+        double *ch = xmalloc((size_t)2 * GM_NCH * N + 10 * (size_t)N);
+        double *m = ch + GM_NCH * N, *work = ch + 2 * GM_NCH * N;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int64_t p_end = (b + 1) * ORC_BLOCK < P ? (b + 1) * ORC_BLOCK : P;
+            double *acc = part + b * n_out;
+            for (int64_t p = b * ORC_BLOCK; p < p_end; ++p) {
+                gm_channels_panel(cs, rho, u, pp, p, ch, work);
+                for (int c = 0; c < GM_NCH; ++c) orc_spline_m(N, ch + c * N, cs->dtau, m + c * N, work);
+                for (int64_t s = 0; s < n_s; ++s) {
+                    const int64_t o = s_obs[s];
+                    const double *x = cs->x_obs + 3 * o;
+                    if (s_k == NULL) {
+                        for (int64_t k = 0; k < n_t[o]; ++k)
+                            acc[s * nt_stride + k] +=
+                                gm_integrand(cs, ch, m, x, cs->dS[p], t_start[o] + (double)k * cs->dtau);
+                    } else {
+                        acc[s] += gm_integrand(cs, ch, m, x, cs->dS[p], t_start[o] + (double)s_k[s] * cs->dtau);
+                    }
+                }
+            }
+        }
+        free(ch);
+    }
+    memset(out, 0, sizeof(double) * (size_t)n_out);
+    for (int64_t b = 0; b < nblk; ++b)                     /* surface sum, fixed order */
+        for (int64_t i = 0; i < n_out; ++i) out[i] += part[b * n_out + i];
+    free(part);
+    free(t_start);
+    free(n_t);
+    return 0;
+}
+
+int orc_gm_forward(int64_t P, int64_t O, int64_t N, const double *y, const double *nrm, const double *vel,
+                   const double *dS, const double *x_obs, double mach, double dtau, double tau0, const double *rho,
+                   const double *u, const double *pp, const int64_t *obs_idx, int64_t n_sel, double *out,
+                   int64_t nt_stride)
+{
+    orc_gm_case cs = {P, O, N, y, nrm, vel, dS, x_obs, mach, dtau, tau0};
+    return gm_core(&cs, rho, u, pp, obs_idx, NULL, n_sel, out, nt_stride);
+}
+
+int orc_gm_forward_samples(int64_t P, int64_t O, int64_t N, const double *y, const double *nrm, const double *vel,
+                           const double *dS, const double *x_obs, double mach, double dtau, double tau0,
+                           const double *rho, const double *u, const double *pp, const int64_t *s_obs,
+                           const int64_t *s_k, int64_t n_s, double *out)
+{
+    orc_gm_case cs = {P, O, N, y, nrm, vel, dS, x_obs, mach, dtau, tau0};
+    return gm_core(&cs, rho, u, pp, s_obs, s_k, n_s, out, 0);
+}
+
+/* Channels of every panel, [GM_NCH][P][N] (exposed for the tests). */
+void orc_gm_channels(int64_t P, int64_t N, const double *y, const double *nrm, const double *vel, double mach,
+                     double dtau, const double *rho, const double *u, const double *pp, double *out)
+{
+    orc_gm_case cs = {P, 1, N, y, nrm, vel, NULL, NULL, mach, dtau, 0.0};
+#pragma omp parallel
+    {
+        double *ch = xmalloc((size_t)GM_NCH * N + 9 * (size_t)N);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < P; ++p) {
+            gm_channels_panel(&cs, rho, u, pp, p, ch, ch + GM_NCH * N);
+            for (int c = 0; c < GM_NCH; ++c) memcpy(out + ((int64_t)c * P + p) * N, ch + c * N, sizeof(double) * N);
+        }
+        free(ch);
+    }
 }
 
 int orc_num_threads(void)
