@@ -209,6 +209,66 @@ void fwh_destroy(fwh_plan *plan);
 int fwh_post(const fwh_plan *plan, const void *p_out, int64_t seg_len, double span_ratio, float *psd, float *rms,
              void *stream);
 
+/* ------------------------------------------------------------------------
+ * General motion (Sec. II B, Eqs. (pT), (pL), (tau)): a permeable surface in
+ * prescribed motion, the medium and the observers at rest.  Nondimensional as
+ * in Sec. II D with a reference speed: rho0 = 1, c0 = 1/mach (mach = reference
+ * speed / c0), every speed in units of the reference speed.
+ *
+ * Device pointers (caller-owned, FP64, time-major; the kinematics must stay valid
+ * until the last call on the plan):
+ *   y, normal, vel [N][P][3]   panel centre, unit outward normal and velocity at
+ *                              tau_n = tau0 + n dtau (rigid panels: dS constant)
+ *   dS [P], x_obs [O][3]       panel areas (> 0), observer positions
+ * and, per forward call, rho [N][P], u [3][N][P] (fluid velocity in the medium
+ * frame), pp [N][P] (pressure pulsation p - p0).
+ *
+ * What is computed: per panel and frame Q_i = v_i + rho (u_i - v_i) and
+ * L_i = p' n_i + rho u_i (u_j - v_j) n_j (Eqs. (Qn), (Li), P_ij = p' delta_ij),
+ * M_i = mach v_i; second-order source-time differences (one-sided at the first
+ * and last frame); the 19 observer-independent quantities of the integrand
+ * (Qd.n + Q.nd, Q_n, L_i, Ld_i, L_M, M_i, Md_i, M^2, y_i) are each interpolated
+ * in source time by a natural cubic spline.  For every observer sample
+ * t_k = t_start + k dtau and panel, the retarded time solves tau + mach |x - Y(tau)|
+ * = t_k on the splined trajectory Y (Eq. (tau)), and the integrand of
+ * Eqs. (pT) + (pL) times dS / (4 pi) is evaluated there and summed over panels.
+ * Window: t_start(o) = max_p [tau0 + mach |x_o - y_p(tau0)|],
+ *         t_end(o) = min_p [tau_{N-1} + mach |x_o - y_p(tau_{N-1})|],
+ *         N_t(o) = floor((t_end - t_start) / dtau + 1e-9) + 1.
+ * The surface must move subsonically (mach |v| < 1); N_t < 2N then holds.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_panels, n_obs, n_tau;      /* P >= 1, O >= 1, N >= 4 */
+    double mach, dtau, tau0;             /* 0 < mach < 1, dtau > 0, tau0 finite */
+    const double *y, *normal, *vel;      /* device, [N][P][3] */
+    const double *dS, *x_obs;            /* device, [P], [O][3] */
+} fwh_gm_args;
+
+typedef struct fwh_gm_plan fwh_gm_plan;
+
+/* Host only: validates sizes and scalars (the device arrays are not read here)
+ * and returns the workspace size in bytes (caller-owned, 256-byte aligned).
+ * FWH_ESIZE / FWH_EDOMAIN / FWH_EINVAL on bad arguments. */
+int fwh_gm_plan_create(const fwh_gm_args *args, fwh_gm_plan **out, size_t *workspace_bytes);
+
+/* Binds the workspace, computes the observer window on the device (enqueued on
+ * `stream`, then waits for the stream) and keeps t_start and N_t on the plan.
+ * FWH_EWINDOW if some observer's window is empty, FWH_ESIZE if N_t >= 2N (the
+ * surface moved supersonically). */
+int fwh_gm_window(fwh_gm_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Host copies of the window (after fwh_gm_window): t_start [O], n_t [O] (may be
+ * NULL), n_t_max. */
+int fwh_gm_obs_window(const fwh_gm_plan *plan, double *t_start, int64_t *n_t, int64_t *n_t_max);
+
+/* p_out [O][n_t_max] (FP64, device) = p'(x_o, t_start(o) + k dtau) for k < N_t(o),
+ * 0 beyond.  Enqueued on `stream`; nothing allocated. */
+int fwh_gm_forward(fwh_gm_plan *plan, const double *rho, const double *u, const double *pp, double *p_out,
+                   void *stream);
+
+/* Frees the host side of the plan (the workspace is the caller's). */
+void fwh_gm_destroy(fwh_gm_plan *plan);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *fwh_last_error(void);
 

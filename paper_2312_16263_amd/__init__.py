@@ -28,7 +28,8 @@ ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW
 # names declared in include/fwh.h
 EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_post", "fwh_profile_enable",
             "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_bind", "fwh_batch_forward",
-            "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_last_error",
+            "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_gm_plan_create",
+            "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_destroy", "fwh_last_error",
             "fwh_version"]
 STAGES = {"setup": 0, "source": 1, "gather": 2, "reduce": 3, "adj_gather": 4, "source_adj": 5}
 
@@ -45,6 +46,13 @@ class SetupArgs(ctypes.Structure):
                 ("dS", ctypes.POINTER(ctypes.c_double)), ("x_obs", ctypes.POINTER(ctypes.c_double)),
                 ("mach", ctypes.c_double), ("aoa_deg", ctypes.c_double), ("dtau", ctypes.c_double),
                 ("tau0", ctypes.c_double), ("mode", ctypes.c_int32)]
+
+
+class GmArgs(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int64), ("n_obs", ctypes.c_int64), ("n_tau", ctypes.c_int64),
+                ("mach", ctypes.c_double), ("dtau", ctypes.c_double), ("tau0", ctypes.c_double),
+                ("y", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("vel", ctypes.c_void_p),
+                ("dS", ctypes.c_void_p), ("x_obs", ctypes.c_void_p)]
 
 
 class BatchCaseC(ctypes.Structure):
@@ -95,6 +103,16 @@ def lib():
         L.fwh_batch_info.restype = ctypes.c_int
         L.fwh_batch_destroy.argtypes = [vp]
         L.fwh_batch_destroy.restype = None
+        L.fwh_gm_plan_create.argtypes = [ctypes.POINTER(GmArgs), ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.fwh_gm_plan_create.restype = ctypes.c_int
+        L.fwh_gm_window.argtypes = [vp, vp, sz, vp]
+        L.fwh_gm_window.restype = ctypes.c_int
+        L.fwh_gm_obs_window.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fwh_gm_obs_window.restype = ctypes.c_int
+        L.fwh_gm_forward.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fwh_gm_forward.restype = ctypes.c_int
+        L.fwh_gm_destroy.argtypes = [vp]
+        L.fwh_gm_destroy.restype = None
         L.fwh_destroy.argtypes = [vp]
         L.fwh_destroy.restype = None
         L.fwh_last_error.argtypes = []
@@ -414,3 +432,64 @@ def fwh_apply(plan: Plan, rho, u, pp):
 
 def version() -> str:
     return lib().fwh_version().decode()
+
+
+class GMPlan:
+    """General-motion plan (moving surface, medium and observers at rest) on
+    the current CUDA(HIP) device.
+
+    y, normal, vel [N,P,3], dS [P], x_obs [O,3]: float64 tensors on the device
+    (kept referenced by the plan); mach, dtau, tau0: scalars.  The observer
+    window is computed at construction (``self.window``)."""
+
+    def __init__(self, y, normal, vel, dS, x_obs, mach, dtau, tau0=0.0):
+        import torch
+        L = lib()
+        N, P = int(y.shape[0]), int(y.shape[1])
+        O = int(x_obs.shape[0])
+        for name, t, shape in (("y", y, (N, P, 3)), ("normal", normal, (N, P, 3)), ("vel", vel, (N, P, 3)),
+                               ("dS", dS, (P,)), ("x_obs", x_obs, (O, 3))):
+            if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        self.device = y.device
+        self._keep = (y, normal, vel, dS, x_obs)
+        args = GmArgs(P, O, N, float(mach), float(dtau), float(tau0), y.data_ptr(), normal.data_ptr(),
+                      vel.data_ptr(), dS.data_ptr(), x_obs.data_ptr())
+        h = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(L.fwh_gm_plan_create(ctypes.byref(args), ctypes.byref(h), ctypes.byref(nbytes)))
+        self._h = h
+        self.P, self.O, self.N = P, O, N
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(L.fwh_gm_window(self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        ts = np.empty(O)
+        nt = np.empty(O, dtype=np.int64)
+        ntm = ctypes.c_int64()
+        _check(L.fwh_gm_obs_window(self._h, _dptr(ts), nt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   ctypes.byref(ntm)))
+        self.window = Window(ts, nt, int(ntm.value))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fwh_gm_destroy(h)
+            self._h = None
+
+    def forward(self, rho, u, pp, out=None):
+        """p'(o, k) as a float64 [O, n_t_max] tensor (0 past each observer's N_t)."""
+        import torch
+        for name, t, shape in (("rho", rho, (self.N, self.P)), ("u", u, (3, self.N, self.P)),
+                               ("p", pp, (self.N, self.P))):
+            if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError(f"{name} must be a contiguous float64 tensor of shape {shape} on {self.device}")
+        if out is None:
+            out = torch.empty((self.O, self.window.n_t_max), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().fwh_gm_forward(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                        ctypes.c_void_p(pp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return out
+

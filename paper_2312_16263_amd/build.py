@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwh.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fwh_api.hip", "fwh_setup.hip", "fwh_source.hip", "fwh_gather.hip", "fwh_post.hip"]
+SOURCES = ["fwh_api.hip", "fwh_setup.hip", "fwh_source.hip", "fwh_gather.hip", "fwh_post.hip", "fwh_gm.hip"]
 ARCH = os.environ.get("FWH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          # no packed FP32 instructions anywhere in the device code

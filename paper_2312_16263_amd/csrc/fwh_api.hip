@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <new>
 
 #include "fwh_internal.h"
 
@@ -668,6 +669,188 @@ void fwh_destroy(fwh_plan *pl) {
         }
     delete pl;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ general motion
+
+struct fwh_gm_plan {
+    fwh_gm_args a{};
+    int64_t NS = 0, nt_cap = 0;
+    int splits = 1;
+    int64_t p_chunk = 0;
+    std::vector<double> inv_beta;
+    std::vector<double> t_start;
+    std::vector<int64_t> n_t;
+    int64_t n_t_max = 0;
+    size_t off_chan = 0, off_traj = 0, off_ib = 0, off_ts = 0, off_nt = 0, off_part = 0, ws_bytes = 0;
+    char *ws = nullptr;
+    bool ready = false;
+};
+
+extern "C" {
+
+int fwh_gm_plan_create(const fwh_gm_args *a, fwh_gm_plan **out, size_t *workspace_bytes) {
+    g_last_error.clear();
+    if (!a || !out) return fail(FWH_EINVAL, "fwh_gm_plan_create: null argument");
+    *out = nullptr;
+    if (a->n_panels < 1 || a->n_obs < 1 || a->n_tau < 4)
+        return fail(FWH_ESIZE, "fwh_gm_plan_create: need n_panels >= 1, n_obs >= 1, n_tau >= 4 (got %lld, %lld, %lld)",
+                    (long long)a->n_panels, (long long)a->n_obs, (long long)a->n_tau);
+    if (a->n_tau > (1 << 20) || a->n_panels > ((int64_t)1 << 26) || a->n_obs > ((int64_t)1 << 20) ||
+        a->n_panels * a->n_tau > ((int64_t)1 << 36))
+        return fail(FWH_ESIZE, "fwh_gm_plan_create: sizes beyond the supported range");
+    if (!a->y || !a->normal || !a->vel || !a->dS || !a->x_obs)
+        return fail(FWH_EINVAL, "fwh_gm_plan_create: null kinematics pointer");
+    if (!(a->mach > 0.0 && a->mach < 1.0))
+        return fail(FWH_EDOMAIN, "fwh_gm_plan_create: mach must be in (0, 1), got %g", a->mach);
+    if (!(a->dtau > 0.0) || !std::isfinite(a->dtau))
+        return fail(FWH_EDOMAIN, "fwh_gm_plan_create: dtau must be positive, got %g", a->dtau);
+    if (!std::isfinite(a->tau0)) return fail(FWH_EINVAL, "fwh_gm_plan_create: tau0 must be finite");
+    fwh_gm_plan *pl = new (std::nothrow) fwh_gm_plan;
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_plan_create: out of host memory");
+    pl->a = *a;
+    const int64_t P = a->n_panels, O = a->n_obs, N = a->n_tau;
+    pl->NS = N + 2;
+    pl->nt_cap = 2 * N;
+    // Thomas pivots of tridiag(1, 4, 1): c'_1 = 1/4, c'_n = 1 / (4 - c'_{n-1})
+    pl->inv_beta.assign(fwh::kGmPivots, 0.0);
+    double c = 0.0;
+    for (int n = 1; n < fwh::kGmPivots; ++n) {
+        c = 1.0 / (4.0 - c);
+        pl->inv_beta[n] = c;
+    }
+    // panel splits: about 16384 waves of (observer, 64 samples, panel range)
+    const int64_t nkb = (N + 63) / 64;
+    int64_t sp = (16384 + O * nkb - 1) / (O * nkb);
+    sp = std::max<int64_t>(1, std::min<int64_t>(sp, std::max<int64_t>(1, P / 16)));
+    pl->splits = (int)std::min<int64_t>(sp, 1024);
+    pl->p_chunk = (P + pl->splits - 1) / pl->splits;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    pl->off_chan = take((size_t)P * pl->NS * 16 * sizeof(double));
+    pl->off_traj = take((size_t)P * pl->NS * 4 * sizeof(double));
+    pl->off_ib = take(fwh::kGmPivots * sizeof(double));
+    pl->off_ts = take((size_t)O * sizeof(double));
+    pl->off_nt = take((size_t)O * sizeof(int32_t));
+    pl->off_part = take((size_t)pl->splits * O * pl->nt_cap * sizeof(double));
+    pl->ws_bytes = off;
+    if (workspace_bytes) *workspace_bytes = pl->ws_bytes;
+    *out = pl;
+    return FWH_OK;
+}
+
+int fwh_gm_window(fwh_gm_plan *pl, void *workspace, size_t workspace_bytes, void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_window: null plan");
+    if (!workspace) return fail(FWH_EWORKSPACE, "fwh_gm_window: null workspace");
+    if (workspace_bytes < pl->ws_bytes)
+        return fail(FWH_EWORKSPACE, "fwh_gm_window: workspace of %zu bytes, need %zu", workspace_bytes, pl->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(FWH_EWORKSPACE, "fwh_gm_window: workspace must be %zu-byte aligned", kAlign);
+    pl->ready = false;
+    pl->ws = static_cast<char *>(workspace);
+    hipStream_t st = as_stream(stream_);
+    const int64_t O = pl->a.n_obs;
+    hipError_t e = hipMemcpyAsync(pl->ws + pl->off_ib, pl->inv_beta.data(), fwh::kGmPivots * sizeof(double),
+                                  hipMemcpyHostToDevice, st);
+    if (e) return hip_fail("fwh_gm_window: pivot table copy", e);
+    fwh::GmWinArgs w{};
+    w.y = pl->a.y;
+    w.x_obs = pl->a.x_obs;
+    w.mach = pl->a.mach;
+    w.dtau = pl->a.dtau;
+    w.tau0 = pl->a.tau0;
+    w.P = pl->a.n_panels;
+    w.O = O;
+    w.N = pl->a.n_tau;
+    w.t_start = reinterpret_cast<double *>(pl->ws + pl->off_ts);
+    w.n_t = reinterpret_cast<int32_t *>(pl->ws + pl->off_nt);
+    e = fwh::launch_gm_window(w, st);
+    if (e) return hip_fail("fwh_gm_window: window kernel", e);
+    pl->t_start.assign(O, 0.0);
+    std::vector<int32_t> nt32(O, 0);
+    e = hipMemcpyAsync(pl->t_start.data(), w.t_start, O * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (!e) e = hipMemcpyAsync(nt32.data(), w.n_t, O * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (!e) e = hipStreamSynchronize(st);
+    if (e) return hip_fail("fwh_gm_window: window copy", e);
+    pl->n_t.assign(O, 0);
+    pl->n_t_max = 0;
+    for (int64_t o = 0; o < O; ++o) {
+        if (nt32[o] < 1)
+            return fail(FWH_EWINDOW, "fwh_gm_window: observer %lld has an empty window", (long long)o);
+        if (nt32[o] >= pl->nt_cap)
+            return fail(FWH_ESIZE, "fwh_gm_window: observer %lld has N_t = %d >= 2N (supersonic surface motion?)",
+                        (long long)o, nt32[o]);
+        pl->n_t[o] = nt32[o];
+        pl->n_t_max = std::max<int64_t>(pl->n_t_max, nt32[o]);
+    }
+    pl->ready = true;
+    return FWH_OK;
+}
+
+int fwh_gm_obs_window(const fwh_gm_plan *pl, double *t_start, int64_t *n_t, int64_t *n_t_max) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_obs_window: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_gm_obs_window: no window computed");
+    if (t_start) std::copy(pl->t_start.begin(), pl->t_start.end(), t_start);
+    if (n_t) std::copy(pl->n_t.begin(), pl->n_t.end(), n_t);
+    if (n_t_max) *n_t_max = pl->n_t_max;
+    return FWH_OK;
+}
+
+int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const double *pp, double *p_out,
+                   void *stream_) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_forward: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_gm_forward: no window computed");
+    if (!rho || !u || !pp || !p_out) return fail(FWH_EINVAL, "fwh_gm_forward: null data pointer");
+    hipStream_t st = as_stream(stream_);
+    fwh::GmChanArgs c{};
+    c.y = pl->a.y;
+    c.normal = pl->a.normal;
+    c.vel = pl->a.vel;
+    c.rho = rho;
+    c.u = u;
+    c.pp = pp;
+    c.mach = pl->a.mach;
+    c.dtau = pl->a.dtau;
+    c.P = pl->a.n_panels;
+    c.N = pl->a.n_tau;
+    c.NS = pl->NS;
+    c.chan = reinterpret_cast<double *>(pl->ws + pl->off_chan);
+    c.traj = reinterpret_cast<double *>(pl->ws + pl->off_traj);
+    hipError_t e = fwh::launch_gm_source(c, reinterpret_cast<const double *>(pl->ws + pl->off_ib), st);
+    if (e) return hip_fail("fwh_gm_forward: source stage", e);
+    fwh::GmGatherArgs g{};
+    g.chan = c.chan;
+    g.traj = c.traj;
+    g.dS = pl->a.dS;
+    g.x_obs = pl->a.x_obs;
+    g.t_start = reinterpret_cast<const double *>(pl->ws + pl->off_ts);
+    g.n_t = reinterpret_cast<const int32_t *>(pl->ws + pl->off_nt);
+    g.mach = pl->a.mach;
+    g.dtau = pl->a.dtau;
+    g.tau0 = pl->a.tau0;
+    g.P = pl->a.n_panels;
+    g.O = pl->a.n_obs;
+    g.N = pl->a.n_tau;
+    g.NS = pl->NS;
+    g.nt_stride = pl->n_t_max;
+    g.nkb = (pl->n_t_max + 63) / 64;
+    g.p_chunk = pl->p_chunk;
+    g.splits = pl->splits;
+    g.part = reinterpret_cast<double *>(pl->ws + pl->off_part);
+    e = fwh::launch_gm_gather(g, p_out, st);
+    if (e) return hip_fail("fwh_gm_forward: gather", e);
+    return FWH_OK;
+}
+
+void fwh_gm_destroy(fwh_gm_plan *pl) { delete pl; }
 
 const char *fwh_last_error(void) { return g_last_error.c_str(); }
 

@@ -1,0 +1,341 @@
+// General-motion form (Sec. II B): a permeable surface in prescribed motion,
+// medium and observers at rest, Eqs. (pT), (pL) at the retarded time of
+// Eq. (tau).  FP64 throughout.  Nondimensional (Sec. II D) with rho0 = 1,
+// c0 = 1/M0 and M_i = M0 v_i.
+//
+// Stages:
+//  1. gm_channels_kernel, one thread per (frame n, panel p): Q_i, n_i, L_i, M_i
+//     of Eqs. (Qn), (Li) (P_ij = p' delta_ij) at the frames of the second-order
+//     source-time difference of frame n (central; one-sided three-point at the
+//     first and last frame), recomputed from the inputs, giving the 19
+//     observer-independent channels: the record chan[p][n + 1][16] = [A, Q_n,
+//     L_1..3, Ld_1..3, L_M, M_1..3, Md_1..3, M^2] with A = Qd_i n_i + Q_i nd_i, and
+//     traj[p][n + 1][4] = [y_1..3, 0].
+//  2. gm_prefilter_kernel, one thread per (panel, channel): the natural cubic
+//     spline of each channel in source time as uniform cubic B-spline
+//     coefficients c_{-1..N} (storage index n + 1), in place: c_0 = f_0,
+//     c_{N-1} = f_{N-1}, c_{n-1} + 4 c_n + c_{n+1} = 6 f_n, c_{-1} = 2 c_0 - c_1,
+//     c_N = 2 c_{N-1} - c_{N-2}; Thomas sweeps with the pivot table inv_beta.
+//  3. gm_window_kernel, one block per observer: t_start = max_p [tau_0 +
+//     M0 |x - y_p(tau_0)|], t_end = min_p [tau_{N-1} + M0 |x - y_p(tau_{N-1})|],
+//     N_t = floor((t_end - t_start)/dtau + 1e-9) + 1 (-1 for an empty window).
+//  4. gm_gather_kernel: a wave owns (observer, 64 consecutive samples, panel
+//     range); per panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton
+//     steps on the splined trajectory (started from its solution for the
+//     previous panel), evaluates the 16 channels at tau_ret with the four
+//     B-spline taps and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi)
+//     in FP64.  Panel ranges (splits) are summed by gm_reduce_kernel in fixed
+//     order.
+#include "fwh_internal.h"
+
+namespace fwh {
+namespace {
+
+constexpr int kGmChan = 16;  // doubles per chan record
+constexpr int kGmTraj = 4;   // doubles per traj record
+constexpr int kGmNewtonMax = 40;
+constexpr double kPiD = 3.14159265358979323846;
+
+struct GmFrame {
+    double Q[3], n[3], L[3], M[3], y[3];
+};
+
+// Frame quantities of panel p at frame m (time-major inputs).
+__device__ __forceinline__ GmFrame gm_frame(const GmChanArgs &a, int64_t m, int64_t p) {
+    const int64_t P = a.P, NP = a.N * a.P;
+    const int64_t i1 = m * P + p, i3 = 3 * i1;
+    GmFrame f;
+    double v[3], u[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f.y[i] = a.y[i3 + i];
+        f.n[i] = a.normal[i3 + i];
+        v[i] = a.vel[i3 + i];
+        u[i] = a.u[i * NP + i1];
+    }
+    const double rho = a.rho[i1], pp = a.pp[i1];
+    const double urel_n = (u[0] - v[0]) * f.n[0] + (u[1] - v[1]) * f.n[1] + (u[2] - v[2]) * f.n[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f.Q[i] = v[i] + rho * (u[i] - v[i]);
+        f.L[i] = pp * f.n[i] + rho * u[i] * urel_n;
+        f.M[i] = a.mach * v[i];
+    }
+    return f;
+}
+
+__global__ __launch_bounds__(256) void gm_channels_kernel(GmChanArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t P = a.P, N = a.N;
+    if (e >= N * P) return;
+    const int64_t n = e / P, p = e - n * P;
+    // stencil frames and weights of the second-order difference at frame n
+    int64_t f0, f1, f2;
+    double w0, w1, w2;
+    if (n == 0) {
+        f0 = 0; f1 = 1; f2 = 2; w0 = -3.0; w1 = 4.0; w2 = -1.0;
+    } else if (n == N - 1) {
+        f0 = N - 3; f1 = N - 2; f2 = N - 1; w0 = 1.0; w1 = -4.0; w2 = 3.0;
+    } else {
+        f0 = n - 1; f1 = n; f2 = n + 1; w0 = -1.0; w1 = 0.0; w2 = 1.0;
+    }
+    const GmFrame F0 = gm_frame(a, f0, p), F1 = gm_frame(a, f1, p), F2 = gm_frame(a, f2, p);
+    const GmFrame &C = n == 0 ? F0 : (n == N - 1 ? F2 : F1);  // the frame itself
+    const double i2h = 1.0 / (2.0 * a.dtau);
+    double Qd[3], nd[3], Ld[3], Md[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Qd[i] = (w0 * F0.Q[i] + w1 * F1.Q[i] + w2 * F2.Q[i]) * i2h;
+        nd[i] = (w0 * F0.n[i] + w1 * F1.n[i] + w2 * F2.n[i]) * i2h;
+        Ld[i] = (w0 * F0.L[i] + w1 * F1.L[i] + w2 * F2.L[i]) * i2h;
+        Md[i] = (w0 * F0.M[i] + w1 * F1.M[i] + w2 * F2.M[i]) * i2h;
+    }
+    double rec[kGmChan];
+    rec[0] = Qd[0] * C.n[0] + Qd[1] * C.n[1] + Qd[2] * C.n[2] + C.Q[0] * nd[0] + C.Q[1] * nd[1] + C.Q[2] * nd[2];
+    rec[1] = C.Q[0] * C.n[0] + C.Q[1] * C.n[1] + C.Q[2] * C.n[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        rec[2 + i] = C.L[i];
+        rec[5 + i] = Ld[i];
+        rec[9 + i] = C.M[i];
+        rec[12 + i] = Md[i];
+    }
+    rec[8] = C.L[0] * C.M[0] + C.L[1] * C.M[1] + C.L[2] * C.M[2];
+    rec[15] = C.M[0] * C.M[0] + C.M[1] * C.M[1] + C.M[2] * C.M[2];
+    const int64_t s = (p * a.NS + n + 1);
+    double4 *dst = reinterpret_cast<double4 *>(a.chan + s * kGmChan);
+#pragma unroll
+    for (int q = 0; q < kGmChan / 4; ++q) dst[q] = make_double4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+    reinterpret_cast<double4 *>(a.traj)[s] = make_double4(C.y[0], C.y[1], C.y[2], 0.0);
+}
+
+// Natural cubic spline -> B-spline coefficients, in place, for the series
+// base[(p * NS + s) * W + c] (s = n + 1 holds f_n on entry, c_{s-1} on exit).
+template <int W>
+__global__ __launch_bounds__(256) void gm_prefilter_kernel(double *base, int64_t P, int64_t N, int64_t NS, int nch,
+                                                         const double *__restrict__ inv_beta) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = e / W;
+    const int c = (int)(e - p * W);
+    if (p >= P || c >= nch) return;
+    double *f = base + p * NS * W + c;  // f[s * W]
+    const double f0 = f[1 * W], fN1 = f[N * W];
+    // forward sweep over rows n = 1 .. N-2 (storage n + 1): d_n = (rhs_n - d_{n-1}) / beta_n
+    double d = 0.0;
+    for (int64_t n = 1; n <= N - 2; ++n) {
+        double rhs = 6.0 * f[(n + 1) * W];
+        if (n == 1) rhs -= f0;
+        if (n == N - 2) rhs -= fN1;
+        const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
+        d = (rhs - (n > 1 ? d : 0.0)) * ib;
+        f[(n + 1) * W] = d;
+    }
+    // back substitution: c_{N-2} = d_{N-2}, c_n = d_n - c_{n+1} / beta_n
+    double c_next = 0.0;
+    for (int64_t n = N - 2; n >= 1; --n) {
+        const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
+        const double dn = f[(n + 1) * W];
+        const double cc = n == N - 2 ? dn : dn - c_next * ib;
+        f[(n + 1) * W] = cc;
+        c_next = cc;
+    }
+    // end coefficients (c_0 = f_0 and c_{N-1} = f_{N-1} are already in place)
+    f[0] = 2.0 * f0 - f[2 * W];
+    f[(N + 1) * W] = 2.0 * fN1 - f[(N - 1) * W];
+}
+
+__global__ __launch_bounds__(256) void gm_window_kernel(GmWinArgs a) {
+    const int64_t o = blockIdx.x;
+    const double x0 = a.x_obs[3 * o], x1 = a.x_obs[3 * o + 1], x2 = a.x_obs[3 * o + 2];
+    const int64_t P = a.P, N = a.N;
+    const double tlast = a.tau0 + (double)(N - 1) * a.dtau;
+    double ts = -INFINITY, te = INFINITY;
+    for (int64_t p = threadIdx.x; p < P; p += 256) {
+        const double *y0 = a.y + 3 * p, *y1 = a.y + 3 * ((N - 1) * P + p);
+        const double d00 = x0 - y0[0], d01 = x1 - y0[1], d02 = x2 - y0[2];
+        const double d10 = x0 - y1[0], d11 = x1 - y1[1], d12 = x2 - y1[2];
+        const double a0 = a.tau0 + a.mach * sqrt(d00 * d00 + d01 * d01 + d02 * d02);
+        const double a1 = tlast + a.mach * sqrt(d10 * d10 + d11 * d11 + d12 * d12);
+        ts = fmax(ts, a0);
+        te = fmin(te, a1);
+    }
+    __shared__ double smax[256], smin[256];
+    smax[threadIdx.x] = ts;
+    smin[threadIdx.x] = te;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double t0 = smax[0], t1 = smin[0];
+        a.t_start[o] = t0;
+        a.n_t[o] = t1 < t0 ? -1 : (int32_t)(floor((t1 - t0) / a.dtau + 1e-9) + 1.0);
+    }
+}
+
+// Uniform cubic B-spline weights of frac u for c_{j-1..j+2} and their derivatives.
+__device__ __forceinline__ void bspline_w(double u, double w[4], double dw[4]) {
+    const double v = 1.0 - u, u2 = u * u;
+    w[0] = v * v * v * (1.0 / 6.0);
+    w[1] = (3.0 * u2 * u - 6.0 * u2 + 4.0) * (1.0 / 6.0);
+    w[2] = (-3.0 * u2 * u + 3.0 * u2 + 3.0 * u + 1.0) * (1.0 / 6.0);
+    w[3] = u2 * u * (1.0 / 6.0);
+    dw[0] = -0.5 * v * v;
+    dw[1] = 1.5 * u2 - 2.0 * u;
+    dw[2] = -1.5 * u2 + u + 0.5;
+    dw[3] = 0.5 * u2;
+}
+
+// Interval j in [0, N-2] and frac u in [0, 1] of source time tau.
+__device__ __forceinline__ int64_t gm_locate(double tau, double tau0, double dtau, int64_t N, double &u) {
+    const double xs = (tau - tau0) / dtau;
+    double jf = floor(xs);
+    jf = fmin(fmax(jf, 0.0), (double)(N - 2));
+    u = fmin(fmax(xs - jf, 0.0), 1.0);
+    return (int64_t)jf;
+}
+
+__global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nkb = a.nkb, O = a.O;
+    if (wave >= (int64_t)a.splits * O * nkb) return;
+    const int64_t z = wave / (O * nkb);
+    const int64_t rem = wave - z * O * nkb;
+    const int64_t o = rem / nkb;
+    const int64_t k = (rem - o * nkb) * 64 + lane;
+    const int64_t nt = a.n_t[o];
+    const bool active = k < nt;
+    const double x0 = a.x_obs[3 * o], x1 = a.x_obs[3 * o + 1], x2 = a.x_obs[3 * o + 2];
+    const double t = a.t_start[o] + (double)k * a.dtau;
+    const int64_t N = a.N, NS = a.NS;
+    const double M0 = a.mach, c0 = 1.0 / M0, tau0 = a.tau0, dtau = a.dtau;
+    const double tmax = tau0 + (double)(N - 1) * dtau;
+    const double tol = 1e-11 * dtau;
+    const int64_t pb = z * a.p_chunk;
+    const int64_t pe = min(pb + a.p_chunk, a.P);
+    double acc = 0.0;
+    double tau = 0.0;
+    bool warm = false;
+    for (int64_t p = pb; p < pe; ++p) {
+        const double4 *tr = reinterpret_cast<const double4 *>(a.traj) + p * NS;
+        if (!warm) {  // first panel of the range: start from the emission time of frame 0's position
+            const double4 y0 = tr[1];
+            const double d0 = x0 - y0.x, d1 = x1 - y0.y, d2 = x2 - y0.z;
+            tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
+            warm = true;
+        }
+        // Newton on g(tau) = tau + M0 |x - Y(tau)| - t, g' = 1 - M0 rhat . Y'(tau)
+        for (int it = 0; it < kGmNewtonMax; ++it) {
+            double u;
+            const int64_t j = gm_locate(tau, tau0, dtau, N, u);
+            double w[4], dw[4];
+            bspline_w(u, w, dw);
+            double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double4 c = tr[j + q];
+                Y0 += w[q] * c.x;
+                Y1 += w[q] * c.y;
+                Y2 += w[q] * c.z;
+                D0 += dw[q] * c.x;
+                D1 += dw[q] * c.y;
+                D2 += dw[q] * c.z;
+            }
+            const double r0 = x0 - Y0, r1 = x1 - Y1, r2 = x2 - Y2;
+            const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+            const double g = tau + M0 * r - t;
+            const double gd = 1.0 - M0 * (r0 * D0 + r1 * D1 + r2 * D2) / (r * dtau);
+            double step = active ? g / gd : 0.0;
+            const double tn = fmin(fmax(tau - step, tau0), tmax);
+            step = tau - tn;
+            tau = tn;
+            const bool done = !(fabs(step) > tol);
+            if (__all(done)) break;
+        }
+        // channels at tau_ret and the integrand
+        double u;
+        const int64_t j = gm_locate(tau, tau0, dtau, N, u);
+        double w[4], dw[4];
+        bspline_w(u, w, dw);
+        double q[kGmChan + 3];
+#pragma unroll
+        for (int c = 0; c < kGmChan + 3; ++c) q[c] = 0.0;
+        const double4 *ch = reinterpret_cast<const double4 *>(a.chan) + (p * NS + j) * (kGmChan / 4);
+#pragma unroll
+        for (int tq = 0; tq < 4; ++tq) {
+#pragma unroll
+            for (int g4 = 0; g4 < kGmChan / 4; ++g4) {
+                const double4 c = ch[tq * (kGmChan / 4) + g4];
+                q[4 * g4] += w[tq] * c.x;
+                q[4 * g4 + 1] += w[tq] * c.y;
+                q[4 * g4 + 2] += w[tq] * c.z;
+                q[4 * g4 + 3] += w[tq] * c.w;
+            }
+            const double4 c = tr[j + tq];
+            q[16] += w[tq] * c.x;
+            q[17] += w[tq] * c.y;
+            q[18] += w[tq] * c.z;
+        }
+        const double r0 = x0 - q[16], r1 = x1 - q[17], r2 = x2 - q[18];
+        const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+        const double ir = 1.0 / r;
+        const double h0 = r0 * ir, h1 = r1 * ir, h2 = r2 * ir;
+        const double Mr = q[9] * h0 + q[10] * h1 + q[11] * h2;
+        const double Mdr = q[12] * h0 + q[13] * h1 + q[14] * h2;
+        const double Lr = q[2] * h0 + q[3] * h1 + q[4] * h2;
+        const double Ldr = q[5] * h0 + q[6] * h1 + q[7] * h2;
+        const double iom = 1.0 / (1.0 - Mr);
+        const double conv = r * Mdr + c0 * (Mr - q[15]);
+        // A/(r om^2) + Qn conv/(r^2 om^3) + Ld_r/(c0 r om^2) + (L_r - L_M)/(r^2 om^2) + L_r conv/(c0 r^2 om^3)
+        const double F = ir * iom * iom * (q[0] + M0 * Ldr + ir * (Lr - q[8]) + ir * iom * conv * (q[1] + M0 * Lr));
+        if (active) acc += F * a.dS[p];
+    }
+    if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = active ? acc * (1.0 / (4.0 * kPiD)) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void gm_reduce_kernel(const double *__restrict__ part, int splits, int64_t n,
+                                                      double *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + e];
+    out[e] = s;
+}
+
+}  // namespace
+
+hipError_t launch_gm_source(const GmChanArgs &a, const double *inv_beta, hipStream_t stream) {
+    const int64_t NP = a.N * a.P;
+    gm_channels_kernel<<<dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, stream>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    gm_prefilter_kernel<kGmChan><<<dim3((unsigned)((a.P * kGmChan + 255) / 256)), dim3(256), 0, stream>>>(
+        a.chan, a.P, a.N, a.NS, kGmChan, inv_beta);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    gm_prefilter_kernel<kGmTraj><<<dim3((unsigned)((a.P * kGmTraj + 255) / 256)), dim3(256), 0, stream>>>(
+        a.traj, a.P, a.N, a.NS, 3, inv_beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_window(const GmWinArgs &a, hipStream_t stream) {
+    gm_window_kernel<<<dim3((unsigned)a.O), dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_gather(const GmGatherArgs &a, double *out, hipStream_t stream) {
+    const int64_t waves = (int64_t)a.splits * a.O * a.nkb;
+    gm_gather_kernel<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = a.O * a.nt_stride;
+    gm_reduce_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(a.part, a.splits, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace fwh

@@ -278,4 +278,33 @@ size_t post_shmem(int L);
 hipError_t launch_post(int real_type, const void *p, int64_t ld, const int32_t *nt, int64_t O, int L, double dt,
                        double span_ratio, float *psd, float *rms, hipStream_t stream);
 
+// ------------------------------------------------ general motion (fwh_gm.hip)
+constexpr int kGmPivots = 64;  // inv_beta[n] = 1 / beta_n of tridiag(1, 4, 1), n < 64 (constant past 64)
+
+struct GmChanArgs {
+    const double *y, *normal, *vel;  // [N][P][3]
+    const double *rho, *u, *pp;      // [N][P], [3][N][P], [N][P]
+    double mach, dtau;
+    int64_t P, N, NS;                // NS = N + 2 records per panel
+    double *chan, *traj;             // [P][NS][16], [P][NS][4]
+};
+struct GmWinArgs {
+    const double *y, *x_obs;
+    double mach, dtau, tau0;
+    int64_t P, O, N;
+    double *t_start;
+    int32_t *n_t;
+};
+struct GmGatherArgs {
+    const double *chan, *traj, *dS, *x_obs, *t_start;
+    const int32_t *n_t;
+    double mach, dtau, tau0;
+    int64_t P, O, N, NS, nkb, nt_stride, p_chunk;
+    int splits;
+    double *part;                    // [splits][O][nt_stride]
+};
+hipError_t launch_gm_source(const GmChanArgs &a, const double *inv_beta, hipStream_t stream);
+hipError_t launch_gm_window(const GmWinArgs &a, hipStream_t stream);
+hipError_t launch_gm_gather(const GmGatherArgs &a, double *out, hipStream_t stream);
+
 }  // namespace fwh

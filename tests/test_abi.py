@@ -103,3 +103,42 @@ def test_setup_and_forward_state_checks():
     assert L.fwh_post(h, dummy, 256, 1.0, dummy, dummy, None) == fwh.FWH_ESTATE
     assert L.fwh_post(None, dummy, 256, 1.0, dummy, dummy, None) == fwh.FWH_EINVAL
     L.fwh_destroy(h)
+
+
+# ------------------------------------------------------------ general motion
+
+def _gm_args(**kw):
+    d = dict(P=10, O=3, N=32, mach=0.3, dtau=0.01, tau0=0.0, ptr=0x1000)
+    d.update(kw)
+    p = d["ptr"]
+    return fwh.GmArgs(d["P"], d["O"], d["N"], d["mach"], d["dtau"], d["tau0"], p, p, p, p, p)
+
+
+def test_gm_plan_create_reports_workspace():
+    """The device pointers are not read by plan creation (host only); the
+    workspace covers the two record arrays [P][N+2][16 + 4] FP64 at least."""
+    L = fwh.lib()
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.fwh_gm_plan_create(ctypes.byref(_gm_args(P=100, N=64)), ctypes.byref(h), ctypes.byref(nb)) == 0
+    assert nb.value >= 100 * 66 * 20 * 8 and nb.value % 256 == 0
+    # no window yet: state errors, not HIP calls
+    assert L.fwh_gm_obs_window(h, None, None, None) == fwh.FWH_ESTATE
+    assert L.fwh_gm_forward(h, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                            None) == fwh.FWH_ESTATE
+    assert L.fwh_gm_window(h, None, nb.value, None) == fwh.FWH_EWORKSPACE
+    assert L.fwh_gm_window(h, ctypes.c_void_p(256), nb.value - 1, None) == fwh.FWH_EWORKSPACE
+    assert L.fwh_gm_window(h, ctypes.c_void_p(257), nb.value, None) == fwh.FWH_EWORKSPACE
+    L.fwh_gm_destroy(h)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(P=0), fwh.FWH_ESIZE), (dict(O=0), fwh.FWH_ESIZE), (dict(N=3), fwh.FWH_ESIZE),
+    (dict(N=1 << 21), fwh.FWH_ESIZE), (dict(mach=0.0), fwh.FWH_EDOMAIN), (dict(mach=1.0), fwh.FWH_EDOMAIN),
+    (dict(dtau=0.0), fwh.FWH_EDOMAIN), (dict(dtau=float("nan")), fwh.FWH_EDOMAIN),
+    (dict(tau0=float("inf")), fwh.FWH_EINVAL), (dict(ptr=0), fwh.FWH_EINVAL)])
+def test_gm_plan_create_rejects(kw, code):
+    L = fwh.lib()
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.fwh_gm_plan_create(ctypes.byref(_gm_args(**kw)), ctypes.byref(h), ctypes.byref(nb)) == code
+    assert not h.value
+    assert fwh.lib().fwh_last_error().decode()

@@ -1,0 +1,116 @@
+"""GPU parity of the general-motion path (moving surface, medium and observers
+at rest; Sec. II B) with the FP64 oracle: element by element on small ragged
+cases of every motion kind, edge cases (one panel, the minimum record, zero
+padding), and sampled outputs at the benchmark size.  Both sides compute in
+FP64; the GPU solves the retarded time by Newton steps and evaluates the
+splines in B-spline form, the oracle bisects and uses the second-derivative
+form, so they agree to rounding: tolerance 1e-9 of the largest |p'|."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import analytic, motion, surfaces
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _run_gpu(ms, x, mach, dtau, tau0, rho, u, pp):
+    import torch
+    import paper_2312_16263_amd as fwh
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    plan = fwh.GMPlan(d(ms.y), d(ms.normal), d(ms.vel), d(ms.dS), d(x), mach, dtau, tau0)
+    p = plan.forward(d(rho), d(u), d(pp))
+    torch.cuda.synchronize()
+    return plan, p.cpu().numpy()
+
+
+def _case(kind, n_theta=10, N=200, dtau=1 / 64, M0=0.3, n_obs=5, tau0=0.0):
+    if kind == "translate_dipole":
+        fl = analytic.Flow(0.4, 20.0)
+        body = surfaces.sphere(1.0, n_theta, 2 * n_theta)
+        ms, rho, u, pp = motion.translating_convected_series(body, fl, 4 * math.pi * 1e-3, 2 * math.pi, N, dtau, tau0,
+                                                             kind="dipole")
+        M0 = 0.4
+    else:
+        kw = {"static": dict(), "orbit": dict(spin=0.5),
+              "oscillate": dict(spin=0.4, amplitude=0.3, omega_m=1.5)}[kind]
+        body = surfaces.sphere(1.2, n_theta, 2 * n_theta, center=(0.3, 0.0, 0.0))
+        ms = motion.moving_surface(body, kind, N, dtau, tau0, **kw)
+        rho, u, pp = motion.quiescent_monopole_series(ms, M0, 4 * math.pi * 1e-3, 2 * math.pi, dtau, tau0,
+                                                      source=(0.05, 0.02, 0.0))
+    x = surfaces.observer_circle(n_obs, 15.0, start_deg=7.0)
+    x[:, 2] = np.linspace(-3.0, 4.0, n_obs)
+    return ms, x, M0, dtau, tau0, rho, u, pp
+
+
+@pytest.mark.parametrize("kind", ["static", "orbit", "oscillate", "translate_dipole"])
+def test_gm_parity_small(kind):
+    ms, x, M0, dtau, tau0, rho, u, pp = _case(kind)
+    print(f"[gm parity] {kind}: P={ms.n_panels} N={ms.n_tau} O={x.shape[0]}", flush=True)
+    plan, p = _run_gpu(ms, x, M0, dtau, tau0, rho, u, pp)
+    ref, ts, nt = oracle.gm_forward(ms, x, M0, dtau, tau0, rho, u, pp)
+    np.testing.assert_array_equal(plan.window.n_t, nt)
+    np.testing.assert_allclose(plan.window.t_start, ts, rtol=1e-14, atol=0)
+    assert p.shape == ref.shape
+    assert nt.min() != nt.max() and nt.max() % 64 != 0     # ragged windows and a ragged last block
+    scale = np.abs(ref).max()
+    err = np.abs(p - ref).max() / scale
+    assert err < TOL, err
+    for o in range(x.shape[0]):
+        assert np.all(p[o, nt[o]:] == 0.0)
+
+
+def test_gm_parity_tau0_and_long_record():
+    """Nonzero tau0 and a record spanning several 64-sample blocks per observer."""
+    ms, x, M0, dtau, tau0, rho, u, pp = _case("orbit", n_theta=6, N=700, dtau=1 / 128, n_obs=3, tau0=1.375)
+    plan, p = _run_gpu(ms, x, M0, dtau, tau0, rho, u, pp)
+    ref, ts, nt = oracle.gm_forward(ms, x, M0, dtau, tau0, rho, u, pp)
+    np.testing.assert_array_equal(plan.window.n_t, nt)
+    assert nt.min() > 5 * 64
+    assert np.abs(p - ref).max() / np.abs(ref).max() < TOL
+
+
+def test_gm_edge_cases():
+    """One panel and one observer; the minimum record N = 4."""
+    ms, x, M0, dtau, tau0, rho, u, pp = _case("oscillate", n_theta=4, N=64)
+    one = motion.MovingSurface(ms.y[:, 5:6].copy(), ms.normal[:, 5:6].copy(), ms.vel[:, 5:6].copy(), ms.dS[5:6].copy())
+    r1, u1, p1 = rho[:, 5:6].copy(), u[:, :, 5:6].copy(), pp[:, 5:6].copy()
+    plan, p = _run_gpu(one, x[:1], M0, dtau, tau0, r1, u1, p1)
+    ref, _, nt = oracle.gm_forward(one, x[:1], M0, dtau, tau0, r1, u1, p1)
+    assert np.abs(p - ref).max() / np.abs(ref).max() < TOL
+    ms, x, M0, dtau, tau0, rho, u, pp = _case("orbit", n_theta=4, N=4, dtau=0.5)
+    plan, p = _run_gpu(ms, x, M0, dtau, tau0, rho, u, pp)
+    ref, _, nt = oracle.gm_forward(ms, x, M0, dtau, tau0, rho, u, pp)
+    np.testing.assert_array_equal(plan.window.n_t, nt)
+    assert np.abs(p - ref).max() / np.abs(ref).max() < TOL
+
+
+def test_gm_empty_window_is_reported():
+    import paper_2312_16263_amd as fwh
+    ms, x, M0, dtau, tau0, rho, u, pp = _case("static", n_theta=4, N=4, dtau=1 / 64)
+    with pytest.raises(fwh.FwhError) as ei:
+        _run_gpu(ms, x, M0, dtau, tau0, rho, u, pp)
+    assert ei.value.code == fwh.FWH_EWINDOW
+
+
+def test_gm_fullsize_sampled():
+    """The benchmark workload (orbiting sphere, 8192 panels, 1024 frames, 72
+    observers): 48 sampled (observer, sample) outputs against the oracle."""
+    c = motion.orbiting_sphere_case()
+    print(f"[gm fullsize] {c.name}: P={c.ms.n_panels} N={c.ms.n_tau} O={c.x_obs.shape[0]}", flush=True)
+    plan, p = _run_gpu(c.ms, c.x_obs, c.mach, c.dtau, c.tau0, c.rho, c.u, c.pp)
+    st, ts, nt = oracle.gm_window(c.ms, c.x_obs, c.mach, c.dtau, c.tau0)
+    np.testing.assert_array_equal(plan.window.n_t, nt)
+    rng = np.random.default_rng(7)
+    so = rng.integers(0, c.x_obs.shape[0], 48)
+    sk = np.array([rng.integers(0, nt[o]) for o in so])
+    sk[:4] = 0
+    sk[4:8] = nt[so[4:8]] - 1
+    ref = oracle.gm_forward_samples(c.ms, c.x_obs, c.mach, c.dtau, c.tau0, c.rho, c.u, c.pp, so, sk)
+    got = p[so, sk]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < TOL, err

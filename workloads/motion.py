@@ -155,3 +155,33 @@ def translating_convected_pressure(x_obs: np.ndarray, flow: analytic.Flow, ampli
     pts = x_obs[:, None, :] + t[..., None] * U[None, None, :]
     _, p_hat = analytic.field_amplitudes(kind, pts.reshape(-1, 3), flow, amplitude, omega)
     return (p_hat.reshape(t.shape) * np.exp(1j * omega * t)).real
+
+
+@dataclass
+class GMCase:
+    """A general-motion case: kinematics, observers, surface data."""
+    name: str
+    ms: MovingSurface
+    x_obs: np.ndarray   # [O,3]
+    mach: float
+    dtau: float
+    tau0: float
+    rho: np.ndarray     # [N,P]
+    u: np.ndarray       # [3,N,P]
+    pp: np.ndarray      # [N,P]
+
+
+def orbiting_sphere_case(n_theta: int = 64, n_phi: int = 128, n_tau: int = 1024, dtau: float = 1 / 128,
+                         n_obs: int = 72, mach: float = 0.3, spin: float = 0.5, amplitude: float = 4 * math.pi * 1e-3,
+                         omega: float = 2 * math.pi, obs_radius: float = 20.0, obs_height: float = 3.0) -> GMCase:
+    """Sphere of radius 1.2 centred at (0.3, 0, 0) spinning at `spin` about the z
+    axis through the origin (its centre circles the origin), around a still-air
+    monopole at (0.05, 0.02, 0); observers on a circle of radius obs_radius at
+    height obs_height.  Default size: 8192 panels, 1024 frames, 72 observers."""
+    body = surfaces.sphere(1.2, n_theta, n_phi, center=(0.3, 0.0, 0.0))
+    ms = moving_surface(body, "orbit", n_tau, dtau, spin=spin)
+    src = (0.05, 0.02, 0.0)
+    rho, u, pp = quiescent_monopole_series(ms, mach, amplitude, omega, dtau, source=src)
+    x = surfaces.observer_circle(n_obs, obs_radius, start_deg=2.5)
+    x[:, 2] = obs_height
+    return GMCase(f"orbiting_sphere_{n_theta * n_phi}", ms, x, mach, dtau, 0.0, rho, u, pp)
