@@ -132,6 +132,71 @@ def bench_airfoil(steps, sync):
     return out
 
 
+GM_FLOP_PER_UNIT = 402  # final evaluation 222 (19 channels x 4 taps, weights, integrand) + 2 Newton steps x 90
+
+
+def bench_general_motion(steps, sync, profile_only=False):
+    """General-motion form (Sec. II B): a 64 x 128 sphere (8192 panels) spinning
+    about an axis off its centre around a still-air monopole, 1024 frames, 72
+    observers at rest; FP64.  Forward time (channels + spline coefficients,
+    retarded-time gather), throughput, roofline of the gather (FP64 VALU),
+    error against the oracle on sampled outputs and against the closed form."""
+    import torch
+
+    import oracle
+    import paper_2312_16263_amd as fwh
+    from workloads import motion
+    c = motion.orbiting_sphere_case()
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    plan = fwh.GMPlan(dv(c.ms.y), dv(c.ms.normal), dv(c.ms.vel), dv(c.ms.dS), dv(c.x_obs), c.mach, c.dtau, c.tau0)
+    data = [dv(c.rho), dv(c.u), dv(c.pp)]
+    P, O, N = plan.P, plan.O, plan.N
+    U = int(P * int(plan.window.n_t.sum()))
+    log(f"[bench] general motion: P={P} O={O} N={N}, {U:.3e} units per forward")
+    p = plan.forward(*data)
+    sync()
+    if profile_only:
+        for _ in range(steps):
+            plan.forward(*data, out=p)
+        sync()
+        return None
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(*data, out=p)
+    sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = plan.profile_read()
+    src_ms = st["source"][0] / max(st["source"][1], 1)
+    gat_ms = st["gather"][0] / max(st["gather"][1], 1)
+    ph = p.cpu().numpy()
+    rng = np.random.default_rng(11)
+    so = rng.integers(0, O, 24)
+    sk = np.array([rng.integers(0, plan.window.n_t[o]) for o in so])
+    ref = oracle.gm_forward_samples(c.ms, c.x_obs, c.mach, c.dtau, c.tau0, c.rho, c.u, c.pp, so, sk)
+    err = float(np.abs(ph[so, sk] - ref).max() / np.abs(ref).max())
+    t = plan.window.t_start[:, None] + c.dtau * np.arange(ph.shape[1])[None, :]
+    ex = c.exact(t)
+    m = (np.arange(ph.shape[1])[None, :] < plan.window.n_t[:, None]).astype(float)
+    err_exact = rel_l2(ph, ex, m)
+    achieved = GM_FLOP_PER_UNIT * U / (gat_ms * 1e-3) / 1e12
+    out = {"workload": "sphere r=1.2 (64x128 = 8192 panels) centred at (0.3,0,0) spinning at 0.5 about the z axis "
+                       "around a still-air monopole (w = 2 pi), N=1024 at dtau=1/128, 72 observers at r=20, z=3, "
+                       "M0=0.3; FP64; forward = channels + spline coefficients + retarded-time gather",
+           "units_per_forward": U, "ms_per_forward": ms, "value": U / (ms * 1e-3), "unit": "panel-obs-samples/s",
+           "stage_ms": {"source": src_ms, "gather": gat_ms},
+           "err_vs_oracle_sampled": err, "err_vs_closed_form": err_exact,
+           "roofline": {"bound": "alu", "kernel": "gm_gather_kernel + gm_reduce_kernel", "achieved": achieved,
+                        "peak": 78.6432, "unit": "TFLOP/s", "frac": achieved / 78.6432,
+                        "flop_per_unit": GM_FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": gat_ms,
+                        "traffic": None}}
+    log(f"[bench] general motion: {ms:.2f} ms/forward (source {src_ms:.2f}, gather {gat_ms:.2f}), "
+        f"{U / (ms * 1e-3):.3e} units/s, err vs oracle {err:.2e}, vs closed form {err_exact:.2e}")
+    del plan, data, p
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(replays, sync):
     """64 seeded uneven cases (spheres with analytic sources, extruded contours
     with broadband data; P 2048-32768, N 512-2048, O 8-360, M0 0.1-0.5, AoA
@@ -206,7 +271,8 @@ def main():
                     help="short run for rocprofv3: 1 warmup + `--steps` FP32 steps, then a 1 GiB device copy "
                          "(the reference kernel for HBM byte counters); prints no JSON")
     ap.add_argument("--mode", default="f32", choices=["f32", "bf16"], help="mode of the profile run")
-    ap.add_argument("--workload", default="dipole_sphere", choices=["dipole_sphere", "airfoil_broadband"],
+    ap.add_argument("--workload", default="dipole_sphere",
+                    choices=["dipole_sphere", "airfoil_broadband", "general_motion"],
                     help="workload of the profile run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -224,6 +290,14 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     sync = torch.cuda.synchronize
+    if args.profile_run and args.workload == "general_motion":
+        bench_general_motion(args.steps, sync, profile_only=True)
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        log(f"[bench] profile run done: 1 + {args.steps} general-motion forwards, then a 1 GiB copy")
+        return
     if args.profile_run:
         c = configs.by_name(args.workload)
         log(f"[bench] profile run: workload {c.name}: P={c.n_panels} O={c.n_obs} N={c.n_tau}")
@@ -349,6 +423,7 @@ def main():
         torch.cuda.empty_cache()
         extra["airfoil_broadband"] = bench_airfoil(3, sync)
         extra["batched"] = bench_batch(5, sync)
+        extra["general_motion"] = bench_general_motion(5, sync)
 
     out = {
         "metric": "FW-H panel-obs-samples/s (fwd, adjoint) vs FP64 plain at stated err; % HBM peak",

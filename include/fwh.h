@@ -266,6 +266,17 @@ int fwh_gm_obs_window(const fwh_gm_plan *plan, double *t_start, int64_t *n_t, in
 int fwh_gm_forward(fwh_gm_plan *plan, const double *rho, const double *u, const double *pp, double *p_out,
                    void *stream);
 
+/* Optional event timing of the two stages of fwh_gm_forward on its stream:
+ * FWH_GM_STAGE_SOURCE (channels and spline coefficients) and
+ * FWH_GM_STAGE_GATHER (retarded-time gather and the sum of panel ranges).
+ * fwh_gm_profile_read waits for the recorded events, returns their total
+ * milliseconds and count, and clears them. */
+#define FWH_GM_STAGE_SOURCE 0
+#define FWH_GM_STAGE_GATHER 1
+#define FWH_GM_NUM_STAGES   2
+int fwh_gm_profile_enable(fwh_gm_plan *plan, int enable);
+int fwh_gm_profile_read(fwh_gm_plan *plan, int32_t stage, double *total_ms, int64_t *launches);
+
 /* Frees the host side of the plan (the workspace is the caller's). */
 void fwh_gm_destroy(fwh_gm_plan *plan);
 

@@ -29,7 +29,8 @@ ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW
 EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_post", "fwh_profile_enable",
             "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_bind", "fwh_batch_forward",
             "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_gm_plan_create",
-            "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_destroy", "fwh_last_error",
+            "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_profile_enable",
+            "fwh_gm_profile_read", "fwh_gm_destroy", "fwh_last_error",
             "fwh_version"]
 STAGES = {"setup": 0, "source": 1, "gather": 2, "reduce": 3, "adj_gather": 4, "source_adj": 5}
 
@@ -111,6 +112,10 @@ def lib():
         L.fwh_gm_obs_window.restype = ctypes.c_int
         L.fwh_gm_forward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fwh_gm_forward.restype = ctypes.c_int
+        L.fwh_gm_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.fwh_gm_profile_enable.restype = ctypes.c_int
+        L.fwh_gm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.fwh_gm_profile_read.restype = ctypes.c_int
         L.fwh_gm_destroy.argtypes = [vp]
         L.fwh_gm_destroy.restype = None
         L.fwh_destroy.argtypes = [vp]
@@ -477,6 +482,19 @@ class GMPlan:
         if h is not None and h.value:
             lib().fwh_gm_destroy(h)
             self._h = None
+
+    def profile(self, enable: bool = True):
+        """Bracket the source and gather stages of forward() with HIP events."""
+        _check(lib().fwh_gm_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} of the recorded events (then cleared)."""
+        out = {}
+        for name, st in (("source", 0), ("gather", 1)):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(lib().fwh_gm_profile_read(self._h, st, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def forward(self, rho, u, pp, out=None):
         """p'(o, k) as a float64 [O, n_t_max] tensor (0 past each observer's N_t)."""

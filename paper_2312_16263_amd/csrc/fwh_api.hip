@@ -686,7 +686,29 @@ struct fwh_gm_plan {
     size_t off_chan = 0, off_traj = 0, off_ib = 0, off_ts = 0, off_nt = 0, off_part = 0, ws_bytes = 0;
     char *ws = nullptr;
     bool ready = false;
+    // optional per-stage event timing (FWH_GM_STAGE_SOURCE, FWH_GM_STAGE_GATHER)
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[FWH_GM_NUM_STAGES];
 };
+
+namespace {
+struct GmStageScope {
+    fwh_gm_plan *pl;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    GmStageScope(fwh_gm_plan *p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
+        if (pl->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+    }
+    ~GmStageScope() {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            pl->events[stage].emplace_back(a, b);
+        }
+    }
+};
+}  // namespace
 
 extern "C" {
 
@@ -824,7 +846,11 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     c.NS = pl->NS;
     c.chan = reinterpret_cast<double *>(pl->ws + pl->off_chan);
     c.traj = reinterpret_cast<double *>(pl->ws + pl->off_traj);
-    hipError_t e = fwh::launch_gm_source(c, reinterpret_cast<const double *>(pl->ws + pl->off_ib), st);
+    hipError_t e;
+    {
+        GmStageScope sc(pl, FWH_GM_STAGE_SOURCE, st);
+        e = fwh::launch_gm_source(c, reinterpret_cast<const double *>(pl->ws + pl->off_ib), st);
+    }
     if (e) return hip_fail("fwh_gm_forward: source stage", e);
     fwh::GmGatherArgs g{};
     g.chan = c.chan;
@@ -845,12 +871,52 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     g.p_chunk = pl->p_chunk;
     g.splits = pl->splits;
     g.part = reinterpret_cast<double *>(pl->ws + pl->off_part);
-    e = fwh::launch_gm_gather(g, p_out, st);
+    {
+        GmStageScope sc(pl, FWH_GM_STAGE_GATHER, st);
+        e = fwh::launch_gm_gather(g, p_out, st);
+    }
     if (e) return hip_fail("fwh_gm_forward: gather", e);
     return FWH_OK;
 }
 
-void fwh_gm_destroy(fwh_gm_plan *pl) { delete pl; }
+int fwh_gm_profile_enable(fwh_gm_plan *pl, int enable) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_profile_enable: null plan");
+    pl->profiling = enable != 0;
+    return FWH_OK;
+}
+
+int fwh_gm_profile_read(fwh_gm_plan *pl, int32_t stage, double *total_ms, int64_t *launches) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_gm_profile_read: null plan");
+    if (stage < 0 || stage >= FWH_GM_NUM_STAGES) return fail(FWH_EINVAL, "fwh_gm_profile_read: bad stage %d", stage);
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto &ab : pl->events[stage]) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(ab.second);
+        if (!e) e = hipEventElapsedTime(&ms, ab.first, ab.second);
+        if (e) return hip_fail("fwh_gm_profile_read", e);
+        tot += ms;
+        ++n;
+        (void)hipEventDestroy(ab.first);
+        (void)hipEventDestroy(ab.second);
+    }
+    pl->events[stage].clear();
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
+    return FWH_OK;
+}
+
+void fwh_gm_destroy(fwh_gm_plan *pl) {
+    if (!pl) return;
+    for (auto &v : pl->events)
+        for (auto &ab : v) {
+            (void)hipEventDestroy(ab.first);
+            (void)hipEventDestroy(ab.second);
+        }
+    delete pl;
+}
 
 const char *fwh_last_error(void) { return g_last_error.c_str(); }
 

@@ -169,6 +169,13 @@ class GMCase:
     rho: np.ndarray     # [N,P]
     u: np.ndarray       # [3,N,P]
     pp: np.ndarray      # [N,P]
+    amplitude: float = 0.0
+    omega: float = 0.0
+    source: tuple = (0.0, 0.0, 0.0)
+
+    def exact(self, t: np.ndarray) -> np.ndarray:
+        """Closed-form p' of the still-air monopole at the observers, t [O,K]."""
+        return quiescent_monopole_pressure(self.x_obs, self.mach, self.amplitude, self.omega, t, self.source)
 
 
 def orbiting_sphere_case(n_theta: int = 64, n_phi: int = 128, n_tau: int = 1024, dtau: float = 1 / 128,
@@ -184,4 +191,4 @@ def orbiting_sphere_case(n_theta: int = 64, n_phi: int = 128, n_tau: int = 1024,
     rho, u, pp = quiescent_monopole_series(ms, mach, amplitude, omega, dtau, source=src)
     x = surfaces.observer_circle(n_obs, obs_radius, start_deg=2.5)
     x[:, 2] = obs_height
-    return GMCase(f"orbiting_sphere_{n_theta * n_phi}", ms, x, mach, dtau, 0.0, rho, u, pp)
+    return GMCase(f"orbiting_sphere_{n_theta * n_phi}", ms, x, mach, dtau, 0.0, rho, u, pp, amplitude, omega, src)
