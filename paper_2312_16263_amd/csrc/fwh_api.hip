@@ -683,7 +683,7 @@ struct fwh_gm_plan {
     std::vector<double> t_start;
     std::vector<int64_t> n_t;
     int64_t n_t_max = 0;
-    size_t off_chan = 0, off_traj = 0, off_ib = 0, off_ts = 0, off_nt = 0, off_part = 0, ws_bytes = 0;
+    size_t off_coef = 0, off_ib = 0, off_ts = 0, off_nt = 0, off_part = 0, ws_bytes = 0;
     char *ws = nullptr;
     bool ready = false;
     // optional per-stage event timing (FWH_GM_STAGE_SOURCE, FWH_GM_STAGE_GATHER)
@@ -754,8 +754,7 @@ int fwh_gm_plan_create(const fwh_gm_args *a, fwh_gm_plan **out, size_t *workspac
         off = align_up(off + bytes);
         return o;
     };
-    pl->off_chan = take((size_t)P * pl->NS * 16 * sizeof(double));
-    pl->off_traj = take((size_t)P * pl->NS * 4 * sizeof(double));
+    pl->off_coef = take((size_t)P * fwh::kGmRows * pl->NS * sizeof(double));
     pl->off_ib = take(fwh::kGmPivots * sizeof(double));
     pl->off_ts = take((size_t)O * sizeof(double));
     pl->off_nt = take((size_t)O * sizeof(int32_t));
@@ -844,8 +843,7 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     c.P = pl->a.n_panels;
     c.N = pl->a.n_tau;
     c.NS = pl->NS;
-    c.chan = reinterpret_cast<double *>(pl->ws + pl->off_chan);
-    c.traj = reinterpret_cast<double *>(pl->ws + pl->off_traj);
+    c.coef = reinterpret_cast<double *>(pl->ws + pl->off_coef);
     hipError_t e;
     {
         GmStageScope sc(pl, FWH_GM_STAGE_SOURCE, st);
@@ -853,8 +851,7 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     }
     if (e) return hip_fail("fwh_gm_forward: source stage", e);
     fwh::GmGatherArgs g{};
-    g.chan = c.chan;
-    g.traj = c.traj;
+    g.coef = c.coef;
     g.dS = pl->a.dS;
     g.x_obs = pl->a.x_obs;
     g.t_start = reinterpret_cast<const double *>(pl->ws + pl->off_ts);

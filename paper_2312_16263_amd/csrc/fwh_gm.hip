@@ -8,10 +8,12 @@
 //     of Eqs. (Qn), (Li) (P_ij = p' delta_ij) at the frames of the second-order
 //     source-time difference of frame n (central; one-sided three-point at the
 //     first and last frame), recomputed from the inputs, giving the 19
-//     observer-independent channels: the record chan[p][n + 1][16] = [A, Q_n,
-//     L_1..3, Ld_1..3, L_M, M_1..3, Md_1..3, M^2] with A = Qd_i n_i + Q_i nd_i, and
-//     traj[p][n + 1][4] = [y_1..3, 0].
-//  2. gm_prefilter_kernel, one thread per (panel, channel): the natural cubic
+//     observer-independent channels, channel-major per panel: coef[p][c][n + 1]
+//     for c = [A, Q_n, L_1..3, Ld_1..3, L_M, M_1..3, Md_1..3, M^2, y_1..3] with
+//     A = Qd_i n_i + Q_i nd_i.  A block computes 16 panels x 16 frames and writes
+//     through an LDS transpose, so that both the time-major reads and the
+//     time-contiguous writes are coalesced.
+//  2. gm_prefilter_kernel, one thread per (panel, channel) row: the natural cubic
 //     spline of each channel in source time as uniform cubic B-spline
 //     coefficients c_{-1..N} (storage index n + 1), in place: c_0 = f_0,
 //     c_{N-1} = f_{N-1}, c_{n-1} + 4 c_n + c_{n+1} = 6 f_n, c_{-1} = 2 c_0 - c_1,
@@ -22,19 +24,20 @@
 //  4. gm_gather_kernel: a wave owns (observer, 64 consecutive samples, panel
 //     range); per panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton
 //     steps on the splined trajectory (started from its solution for the
-//     previous panel), evaluates the 16 channels at tau_ret with the four
-//     B-spline taps and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi)
-//     in FP64.  Panel ranges (splits) are summed by gm_reduce_kernel in fixed
-//     order.
+//     previous panel; a step below 1e-6 dtau is accepted without a further
+//     check, the iteration being quadratic), evaluates the channels at tau_ret
+//     with the four B-spline taps (two contiguous 16-byte loads per channel and
+//     lane) and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi) in FP64.
+//     Panel ranges (splits) are summed by gm_reduce_kernel in fixed order.
 #include "fwh_internal.h"
 
 namespace fwh {
 namespace {
 
-constexpr int kGmChan = 16;  // doubles per chan record
-constexpr int kGmTraj = 4;   // doubles per traj record
 constexpr int kGmNewtonMax = 40;
 constexpr double kPiD = 3.14159265358979323846;
+// channel rows of coef[p][kGmRows][NS]
+enum { GA, GQN, GL1, GL2, GL3, GLD1, GLD2, GLD3, GLM, GM1, GM2, GM3, GMD1, GMD2, GMD3, GMSQ, GY1, GY2, GY3 };
 
 struct GmFrame {
     double Q[3], n[3], L[3], M[3], y[3];
@@ -64,84 +67,142 @@ __device__ __forceinline__ GmFrame gm_frame(const GmChanArgs &a, int64_t m, int6
     return f;
 }
 
+constexpr int kGmTP = 16;  // panels per channel block
+constexpr int kGmTF = 16;  // frames per channel block
+
+// Block (bx, by): panels bx*16 .. +15 (thread & 15), frames by*16 .. +15 (thread >> 4).
 __global__ __launch_bounds__(256) void gm_channels_kernel(GmChanArgs a) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ double tile[kGmRows][kGmTP][kGmTF + 1];
     const int64_t P = a.P, N = a.N;
-    if (e >= N * P) return;
-    const int64_t n = e / P, p = e - n * P;
-    // stencil frames and weights of the second-order difference at frame n
-    int64_t f0, f1, f2;
-    double w0, w1, w2;
-    if (n == 0) {
-        f0 = 0; f1 = 1; f2 = 2; w0 = -3.0; w1 = 4.0; w2 = -1.0;
-    } else if (n == N - 1) {
-        f0 = N - 3; f1 = N - 2; f2 = N - 1; w0 = 1.0; w1 = -4.0; w2 = 3.0;
-    } else {
-        f0 = n - 1; f1 = n; f2 = n + 1; w0 = -1.0; w1 = 0.0; w2 = 1.0;
-    }
-    const GmFrame F0 = gm_frame(a, f0, p), F1 = gm_frame(a, f1, p), F2 = gm_frame(a, f2, p);
-    const GmFrame &C = n == 0 ? F0 : (n == N - 1 ? F2 : F1);  // the frame itself
-    const double i2h = 1.0 / (2.0 * a.dtau);
-    double Qd[3], nd[3], Ld[3], Md[3];
+    const int pl = threadIdx.x & 15, fl = threadIdx.x >> 4;
+    const int64_t p = (int64_t)blockIdx.x * kGmTP + pl, n = (int64_t)blockIdx.y * kGmTF + fl;
+    if (p < P && n < N) {
+        // stencil frames and weights of the second-order difference at frame n
+        int64_t f0, f1, f2;
+        double w0, w1, w2;
+        if (n == 0) {
+            f0 = 0; f1 = 1; f2 = 2; w0 = -3.0; w1 = 4.0; w2 = -1.0;
+        } else if (n == N - 1) {
+            f0 = N - 3; f1 = N - 2; f2 = N - 1; w0 = 1.0; w1 = -4.0; w2 = 3.0;
+        } else {
+            f0 = n - 1; f1 = n; f2 = n + 1; w0 = -1.0; w1 = 0.0; w2 = 1.0;
+        }
+        const GmFrame F0 = gm_frame(a, f0, p), F1 = gm_frame(a, f1, p), F2 = gm_frame(a, f2, p);
+        const GmFrame &C = n == 0 ? F0 : (n == N - 1 ? F2 : F1);  // the frame itself
+        const double i2h = 1.0 / (2.0 * a.dtau);
+        double Qd[3], nd[3];
+        double A = 0.0, Qn = 0.0, LM = 0.0, Msq = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        Qd[i] = (w0 * F0.Q[i] + w1 * F1.Q[i] + w2 * F2.Q[i]) * i2h;
-        nd[i] = (w0 * F0.n[i] + w1 * F1.n[i] + w2 * F2.n[i]) * i2h;
-        Ld[i] = (w0 * F0.L[i] + w1 * F1.L[i] + w2 * F2.L[i]) * i2h;
-        Md[i] = (w0 * F0.M[i] + w1 * F1.M[i] + w2 * F2.M[i]) * i2h;
+        for (int i = 0; i < 3; ++i) {
+            Qd[i] = (w0 * F0.Q[i] + w1 * F1.Q[i] + w2 * F2.Q[i]) * i2h;
+            nd[i] = (w0 * F0.n[i] + w1 * F1.n[i] + w2 * F2.n[i]) * i2h;
+            tile[GLD1 + i][pl][fl] = (w0 * F0.L[i] + w1 * F1.L[i] + w2 * F2.L[i]) * i2h;
+            tile[GMD1 + i][pl][fl] = (w0 * F0.M[i] + w1 * F1.M[i] + w2 * F2.M[i]) * i2h;
+            tile[GL1 + i][pl][fl] = C.L[i];
+            tile[GM1 + i][pl][fl] = C.M[i];
+            tile[GY1 + i][pl][fl] = C.y[i];
+            A += Qd[i] * C.n[i] + C.Q[i] * nd[i];
+            Qn += C.Q[i] * C.n[i];
+            LM += C.L[i] * C.M[i];
+            Msq += C.M[i] * C.M[i];
+        }
+        tile[GA][pl][fl] = A;
+        tile[GQN][pl][fl] = Qn;
+        tile[GLM][pl][fl] = LM;
+        tile[GMSQ][pl][fl] = Msq;
     }
-    double rec[kGmChan];
-    rec[0] = Qd[0] * C.n[0] + Qd[1] * C.n[1] + Qd[2] * C.n[2] + C.Q[0] * nd[0] + C.Q[1] * nd[1] + C.Q[2] * nd[2];
-    rec[1] = C.Q[0] * C.n[0] + C.Q[1] * C.n[1] + C.Q[2] * C.n[2];
+    __syncthreads();
+    // write out with frames fastest: thread -> (panel t >> 4, frame t & 15)
+    const int wp = threadIdx.x >> 4, wf = threadIdx.x & 15;
+    const int64_t p2 = (int64_t)blockIdx.x * kGmTP + wp, n2 = (int64_t)blockIdx.y * kGmTF + wf;
+    if (p2 < P && n2 < N) {
+        double *dst = a.coef + p2 * kGmRows * a.NS + n2 + 1;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        rec[2 + i] = C.L[i];
-        rec[5 + i] = Ld[i];
-        rec[9 + i] = C.M[i];
-        rec[12 + i] = Md[i];
+        for (int c = 0; c < kGmRows; ++c) dst[(int64_t)c * a.NS] = tile[c][wp][wf];
     }
-    rec[8] = C.L[0] * C.M[0] + C.L[1] * C.M[1] + C.L[2] * C.M[2];
-    rec[15] = C.M[0] * C.M[0] + C.M[1] * C.M[1] + C.M[2] * C.M[2];
-    const int64_t s = (p * a.NS + n + 1);
-    double4 *dst = reinterpret_cast<double4 *>(a.chan + s * kGmChan);
-#pragma unroll
-    for (int q = 0; q < kGmChan / 4; ++q) dst[q] = make_double4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
-    reinterpret_cast<double4 *>(a.traj)[s] = make_double4(C.y[0], C.y[1], C.y[2], 0.0);
 }
 
-// Natural cubic spline -> B-spline coefficients, in place, for the series
-// base[(p * NS + s) * W + c] (s = n + 1 holds f_n on entry, c_{s-1} on exit).
-template <int W>
-__global__ __launch_bounds__(256) void gm_prefilter_kernel(double *base, int64_t P, int64_t N, int64_t NS, int nch,
+// Natural cubic spline -> B-spline coefficients, in place, for each row
+// coef[row * NS + s] (s = n + 1 holds f_n on entry, c_{s-1} on exit).  A block
+// owns 256 rows (one per thread) and moves through time in chunks of 16
+// positions staged in an LDS tile [256][17]: chunk loads and stores are
+// coalesced (16 lanes per 128-byte row segment), the per-row recurrences read
+// the tile conflict-free.
+constexpr int kPfRows = 256;
+constexpr int kPfT = 16;
+
+__global__ __launch_bounds__(256) void gm_prefilter_kernel(double *coef, int64_t rows, int64_t N, int64_t NS,
                                                          const double *__restrict__ inv_beta) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t p = e / W;
-    const int c = (int)(e - p * W);
-    if (p >= P || c >= nch) return;
-    double *f = base + p * NS * W + c;  // f[s * W]
-    const double f0 = f[1 * W], fN1 = f[N * W];
-    // forward sweep over rows n = 1 .. N-2 (storage n + 1): d_n = (rhs_n - d_{n-1}) / beta_n
+    __shared__ double tile[kPfRows][kPfT + 1];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kPfRows;
+    const int64_t row = r0 + tid;
+    const bool valid = row < rows;
+    const double *fr = coef + (valid ? row : r0) * NS;
+    const double f0 = fr[1], fN1 = fr[N];
+    auto move = [&](int64_t c0, int len, bool to_lds) {
+#pragma unroll 4
+        for (int i = 0; i < kPfRows / 16; ++i) {
+            const int rr = i * 16 + (tid >> 4), ss = tid & 15;
+            const int64_t g = r0 + rr;
+            if (g < rows && ss < len) {
+                if (to_lds)
+                    tile[rr][ss] = coef[g * NS + c0 + ss];
+                else
+                    coef[g * NS + c0 + ss] = tile[rr][ss];
+            }
+        }
+    };
+    // forward sweep over rows n = 1 .. N-2 (storage n + 1 = 2 .. N-1): d_n = (rhs_n - d_{n-1}) / beta_n
     double d = 0.0;
-    for (int64_t n = 1; n <= N - 2; ++n) {
-        double rhs = 6.0 * f[(n + 1) * W];
-        if (n == 1) rhs -= f0;
-        if (n == N - 2) rhs -= fN1;
-        const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
-        d = (rhs - (n > 1 ? d : 0.0)) * ib;
-        f[(n + 1) * W] = d;
+    for (int64_t c0 = 2; c0 <= N - 1; c0 += kPfT) {
+        const int len = (int)min<int64_t>(kPfT, N - c0);
+        __syncthreads();
+        move(c0, len, true);
+        __syncthreads();
+        if (valid) {
+            for (int ss = 0; ss < len; ++ss) {
+                const int64_t n = c0 + ss - 1;
+                double rhs = 6.0 * tile[tid][ss];
+                if (n == 1) rhs -= f0;
+                if (n == N - 2) rhs -= fN1;
+                const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
+                d = (rhs - (n > 1 ? d : 0.0)) * ib;
+                tile[tid][ss] = d;
+            }
+        }
+        __syncthreads();
+        move(c0, len, false);
     }
-    // back substitution: c_{N-2} = d_{N-2}, c_n = d_n - c_{n+1} / beta_n
-    double c_next = 0.0;
-    for (int64_t n = N - 2; n >= 1; --n) {
-        const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
-        const double dn = f[(n + 1) * W];
-        const double cc = n == N - 2 ? dn : dn - c_next * ib;
-        f[(n + 1) * W] = cc;
-        c_next = cc;
+    // back substitution from storage N - 1 down to 2: c_{N-2} = d_{N-2}, c_n = d_n - c_{n+1} / beta_n
+    const int64_t nchunk = (N - 2 + kPfT - 1) / kPfT;
+    double c_next = 0.0, c_top = 0.0;
+    for (int64_t ci = nchunk - 1; ci >= 0; --ci) {
+        const int64_t c0 = 2 + ci * kPfT;
+        const int len = (int)min<int64_t>(kPfT, N - c0);
+        __syncthreads();
+        move(c0, len, true);
+        __syncthreads();
+        if (valid) {
+            for (int ss = len - 1; ss >= 0; --ss) {
+                const int64_t n = c0 + ss - 1;
+                const double ib = inv_beta[n < kGmPivots ? n : kGmPivots - 1];
+                const double dn = tile[tid][ss];
+                const double cc = n == N - 2 ? dn : dn - c_next * ib;
+                if (n == N - 2) c_top = cc;
+                tile[tid][ss] = cc;
+                c_next = cc;
+            }
+        }
+        __syncthreads();
+        move(c0, len, false);
     }
-    // end coefficients (c_0 = f_0 and c_{N-1} = f_{N-1} are already in place)
-    f[0] = 2.0 * f0 - f[2 * W];
-    f[(N + 1) * W] = 2.0 * fN1 - f[(N - 1) * W];
+    // end coefficients (c_0 = f_0 and c_{N-1} = f_{N-1} are already in place); c_next = c_1
+    if (valid) {
+        double *f = coef + row * NS;
+        f[0] = 2.0 * f0 - c_next;
+        f[N + 1] = 2.0 * fN1 - c_top;
+    }
 }
 
 __global__ __launch_bounds__(256) void gm_window_kernel(GmWinArgs a) {
@@ -199,6 +260,15 @@ __device__ __forceinline__ int64_t gm_locate(double tau, double tau0, double dta
     return (int64_t)jf;
 }
 
+typedef double gm_d2 __attribute__((ext_vector_type(2), aligned(8)));
+
+// Value of a channel row at the taps of interval j (weights w): two 16-byte loads.
+__device__ __forceinline__ double gm_tap(const double *row, int64_t j, const double w[4]) {
+    const gm_d2 lo = *reinterpret_cast<const gm_d2 *>(row + j);
+    const gm_d2 hi = *reinterpret_cast<const gm_d2 *>(row + j + 2);
+    return w[0] * lo.x + w[1] * lo.y + w[2] * hi.x + w[3] * hi.y;
+}
+
 __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -215,17 +285,17 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int64_t N = a.N, NS = a.NS;
     const double M0 = a.mach, c0 = 1.0 / M0, tau0 = a.tau0, dtau = a.dtau;
     const double tmax = tau0 + (double)(N - 1) * dtau;
-    const double tol = 1e-11 * dtau;
+    const double accept = 1e-6 * dtau;
     const int64_t pb = z * a.p_chunk;
     const int64_t pe = min(pb + a.p_chunk, a.P);
     double acc = 0.0;
     double tau = 0.0;
     bool warm = false;
     for (int64_t p = pb; p < pe; ++p) {
-        const double4 *tr = reinterpret_cast<const double4 *>(a.traj) + p * NS;
+        const double *cf = a.coef + p * kGmRows * NS;
+        const double *ry0 = cf + GY1 * NS, *ry1 = cf + GY2 * NS, *ry2 = cf + GY3 * NS;
         if (!warm) {  // first panel of the range: start from the emission time of frame 0's position
-            const double4 y0 = tr[1];
-            const double d0 = x0 - y0.x, d1 = x1 - y0.y, d2 = x2 - y0.z;
+            const double d0 = x0 - ry0[1], d1 = x1 - ry1[1], d2 = x2 - ry2[1];
             tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
             warm = true;
         }
@@ -235,17 +305,15 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
             const int64_t j = gm_locate(tau, tau0, dtau, N, u);
             double w[4], dw[4];
             bspline_w(u, w, dw);
-            double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double4 c = tr[j + q];
-                Y0 += w[q] * c.x;
-                Y1 += w[q] * c.y;
-                Y2 += w[q] * c.z;
-                D0 += dw[q] * c.x;
-                D1 += dw[q] * c.y;
-                D2 += dw[q] * c.z;
-            }
+            const gm_d2 a0 = *reinterpret_cast<const gm_d2 *>(ry0 + j), b0 = *reinterpret_cast<const gm_d2 *>(ry0 + j + 2);
+            const gm_d2 a1 = *reinterpret_cast<const gm_d2 *>(ry1 + j), b1 = *reinterpret_cast<const gm_d2 *>(ry1 + j + 2);
+            const gm_d2 a2 = *reinterpret_cast<const gm_d2 *>(ry2 + j), b2 = *reinterpret_cast<const gm_d2 *>(ry2 + j + 2);
+            const double Y0 = w[0] * a0.x + w[1] * a0.y + w[2] * b0.x + w[3] * b0.y;
+            const double Y1 = w[0] * a1.x + w[1] * a1.y + w[2] * b1.x + w[3] * b1.y;
+            const double Y2 = w[0] * a2.x + w[1] * a2.y + w[2] * b2.x + w[3] * b2.y;
+            const double D0 = dw[0] * a0.x + dw[1] * a0.y + dw[2] * b0.x + dw[3] * b0.y;
+            const double D1 = dw[0] * a1.x + dw[1] * a1.y + dw[2] * b1.x + dw[3] * b1.y;
+            const double D2 = dw[0] * a2.x + dw[1] * a2.y + dw[2] * b2.x + dw[3] * b2.y;
             const double r0 = x0 - Y0, r1 = x1 - Y1, r2 = x2 - Y2;
             const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
             const double g = tau + M0 * r - t;
@@ -254,7 +322,8 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
             const double tn = fmin(fmax(tau - step, tau0), tmax);
             step = tau - tn;
             tau = tn;
-            const bool done = !(fabs(step) > tol);
+            // quadratic convergence: after a step below 1e-6 dtau the error is far below rounding
+            const bool done = !(fabs(step) > accept);
             if (__all(done)) break;
         }
         // channels at tau_ret and the integrand
@@ -262,37 +331,20 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const int64_t j = gm_locate(tau, tau0, dtau, N, u);
         double w[4], dw[4];
         bspline_w(u, w, dw);
-        double q[kGmChan + 3];
-#pragma unroll
-        for (int c = 0; c < kGmChan + 3; ++c) q[c] = 0.0;
-        const double4 *ch = reinterpret_cast<const double4 *>(a.chan) + (p * NS + j) * (kGmChan / 4);
-#pragma unroll
-        for (int tq = 0; tq < 4; ++tq) {
-#pragma unroll
-            for (int g4 = 0; g4 < kGmChan / 4; ++g4) {
-                const double4 c = ch[tq * (kGmChan / 4) + g4];
-                q[4 * g4] += w[tq] * c.x;
-                q[4 * g4 + 1] += w[tq] * c.y;
-                q[4 * g4 + 2] += w[tq] * c.z;
-                q[4 * g4 + 3] += w[tq] * c.w;
-            }
-            const double4 c = tr[j + tq];
-            q[16] += w[tq] * c.x;
-            q[17] += w[tq] * c.y;
-            q[18] += w[tq] * c.z;
-        }
-        const double r0 = x0 - q[16], r1 = x1 - q[17], r2 = x2 - q[18];
+        const double r0 = x0 - gm_tap(ry0, j, w), r1 = x1 - gm_tap(ry1, j, w), r2 = x2 - gm_tap(ry2, j, w);
         const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
         const double ir = 1.0 / r;
         const double h0 = r0 * ir, h1 = r1 * ir, h2 = r2 * ir;
-        const double Mr = q[9] * h0 + q[10] * h1 + q[11] * h2;
-        const double Mdr = q[12] * h0 + q[13] * h1 + q[14] * h2;
-        const double Lr = q[2] * h0 + q[3] * h1 + q[4] * h2;
-        const double Ldr = q[5] * h0 + q[6] * h1 + q[7] * h2;
+        auto ch = [&](int c) { return gm_tap(cf + c * NS, j, w); };
+        const double Mr = ch(GM1) * h0 + ch(GM2) * h1 + ch(GM3) * h2;
+        const double Mdr = ch(GMD1) * h0 + ch(GMD2) * h1 + ch(GMD3) * h2;
+        const double Lr = ch(GL1) * h0 + ch(GL2) * h1 + ch(GL3) * h2;
+        const double Ldr = ch(GLD1) * h0 + ch(GLD2) * h1 + ch(GLD3) * h2;
         const double iom = 1.0 / (1.0 - Mr);
-        const double conv = r * Mdr + c0 * (Mr - q[15]);
+        const double conv = r * Mdr + c0 * (Mr - ch(GMSQ));
         // A/(r om^2) + Qn conv/(r^2 om^3) + Ld_r/(c0 r om^2) + (L_r - L_M)/(r^2 om^2) + L_r conv/(c0 r^2 om^3)
-        const double F = ir * iom * iom * (q[0] + M0 * Ldr + ir * (Lr - q[8]) + ir * iom * conv * (q[1] + M0 * Lr));
+        const double F =
+            ir * iom * iom * (ch(GA) + M0 * Ldr + ir * (Lr - ch(GLM)) + ir * iom * conv * (ch(GQN) + M0 * Lr));
         if (active) acc += F * a.dS[p];
     }
     if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = active ? acc * (1.0 / (4.0 * kPiD)) : 0.0;
@@ -310,16 +362,13 @@ __global__ __launch_bounds__(256) void gm_reduce_kernel(const double *__restrict
 }  // namespace
 
 hipError_t launch_gm_source(const GmChanArgs &a, const double *inv_beta, hipStream_t stream) {
-    const int64_t NP = a.N * a.P;
-    gm_channels_kernel<<<dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, stream>>>(a);
+    gm_channels_kernel<<<dim3((unsigned)((a.P + kGmTP - 1) / kGmTP), (unsigned)((a.N + kGmTF - 1) / kGmTF)), dim3(256), 0,
+                         stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    gm_prefilter_kernel<kGmChan><<<dim3((unsigned)((a.P * kGmChan + 255) / 256)), dim3(256), 0, stream>>>(
-        a.chan, a.P, a.N, a.NS, kGmChan, inv_beta);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    gm_prefilter_kernel<kGmTraj><<<dim3((unsigned)((a.P * kGmTraj + 255) / 256)), dim3(256), 0, stream>>>(
-        a.traj, a.P, a.N, a.NS, 3, inv_beta);
+    const int64_t rows = a.P * kGmRows;
+    gm_prefilter_kernel<<<dim3((unsigned)((rows + kPfRows - 1) / kPfRows)), dim3(256), 0, stream>>>(a.coef, rows, a.N,
+                                                                                                  a.NS, inv_beta);
     return hipGetLastError();
 }
 

@@ -280,13 +280,14 @@ hipError_t launch_post(int real_type, const void *p, int64_t ld, const int32_t *
 
 // ------------------------------------------------ general motion (fwh_gm.hip)
 constexpr int kGmPivots = 64;  // inv_beta[n] = 1 / beta_n of tridiag(1, 4, 1), n < 64 (constant past 64)
+constexpr int kGmRows = 19;    // channel rows per panel: A, Q_n, L_1..3, Ld_1..3, L_M, M_1..3, Md_1..3, M^2, y_1..3
 
 struct GmChanArgs {
     const double *y, *normal, *vel;  // [N][P][3]
     const double *rho, *u, *pp;      // [N][P], [3][N][P], [N][P]
     double mach, dtau;
-    int64_t P, N, NS;                // NS = N + 2 records per panel
-    double *chan, *traj;             // [P][NS][16], [P][NS][4]
+    int64_t P, N, NS;                // NS = N + 2 coefficients per row
+    double *coef;                    // [P][kGmRows][NS]
 };
 struct GmWinArgs {
     const double *y, *x_obs;
@@ -296,7 +297,7 @@ struct GmWinArgs {
     int32_t *n_t;
 };
 struct GmGatherArgs {
-    const double *chan, *traj, *dS, *x_obs, *t_start;
+    const double *coef, *dS, *x_obs, *t_start;
     const int32_t *n_t;
     double mach, dtau, tau0;
     int64_t P, O, N, NS, nkb, nt_stride, p_chunk;

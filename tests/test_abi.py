@@ -116,11 +116,11 @@ def _gm_args(**kw):
 
 def test_gm_plan_create_reports_workspace():
     """The device pointers are not read by plan creation (host only); the
-    workspace covers the two record arrays [P][N+2][16 + 4] FP64 at least."""
+    workspace covers the coefficient rows [P][19][N+2] FP64 at least."""
     L = fwh.lib()
     h, nb = ctypes.c_void_p(), ctypes.c_size_t()
     assert L.fwh_gm_plan_create(ctypes.byref(_gm_args(P=100, N=64)), ctypes.byref(h), ctypes.byref(nb)) == 0
-    assert nb.value >= 100 * 66 * 20 * 8 and nb.value % 256 == 0
+    assert nb.value >= 100 * 19 * 66 * 8 and nb.value % 256 == 0
     # no window yet: state errors, not HIP calls
     assert L.fwh_gm_obs_window(h, None, None, None) == fwh.FWH_ESTATE
     assert L.fwh_gm_forward(h, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
