@@ -216,7 +216,6 @@ __device__ __forceinline__ void source_fwd_body(const SrcFwdArgs &a, int64_t bx,
 // leave through an LDS tile [kSrcTC][257] as 16-byte (8-byte for BF16) quads
 // of the interleaved layout.
 constexpr int kSrcRS = 257;  // LDS row: 8 channels x 32 panels + 1
-constexpr int kSrcPF = 8;    // source-term rows loaded ahead
 
 // Per-thread source-term form X = a p' + rho (b.u - g) u.n - d, which covers
 // Q (a = 0, b = 0, g = -1, d = U0.n) and L_i (a = n_i, b = e_i, g = U0_i, d = 0).
@@ -300,17 +299,25 @@ __device__ __forceinline__ void src_flush(const float *tile, TOut *coef, int64_t
     }
 }
 
-// Interior chunk: rows [R0, R0 + kSrcW) all in [kSrcPivotRows, N - 3], source
-// terms read from rows [R0 - 3, R0 + kSrcW + 2] inside the record, central
-// differences throughout, constant pivot: no branches.  The block's inputs (5
-// variables x 32 panels per row) are loaded once, cooperatively and coalesced,
-// in groups of kSrcG rows by direct global -> LDS copies into two buffers:
-// group m + 1 is in flight while group m is used, one barrier per group.  The four
-// waves (four base quantities) then read their source-term inputs from LDS
-// (a broadcast: both half-waves read the same panel's row).  The reduced
-// right-hand sides stay in registers and are overwritten by the coefficients
-// during back substitution; the coefficients leave through a
-// [kSrcTC / 4][kSrcRS] LDS tile in four quarters.
+// Chunk of kSrcTC coefficient indices i0 .. i0 + 63 for 32 panels: the
+// Thomas forward elimination over the kSrcW rows [R0, R0 + kSrcW), R0 = i0 - 17,
+// and the back substitution from the top of that window, reduced right-hand
+// sides in registers, overwritten by the coefficients.  The block's inputs (5
+// variables x 32 panels per source-term row, rows R0 - 3 .. R0 + kSrcW + 2) are
+// loaded once, cooperatively, in groups of kSrcG rows by direct global -> LDS
+// copies into two buffers: group m + 1 is in flight while group m is used, one
+// barrier per group.  The four waves (four base quantities) read their inputs
+// from LDS (both half-waves read the same panel's row: a broadcast).
+//
+// GEN = false: interior chunk (every row in [kSrcPivotRows, N - 3]): central
+// differences, constant pivot, no end rows, no branches.  GEN = true: a chunk
+// with a record end in reach: zero source terms outside the record, one-sided
+// differences at the first and last frame, exact pivots, the end rows'
+// right-hand-side corrections and the end coefficients c_{-1}, c_0, c_{N-1},
+// c_N, zero padding past c_N.  Row positions are compile-time (unrolled) and
+// the end rules block-uniform predicates, so both kinds keep the right-hand
+// sides in registers.  The coefficients leave through a [kSrcTC / 4][kSrcRS]
+// LDS tile in four quarters.
 constexpr int kSrcG = 12;                       // rows per staged group
 constexpr int kSrcNX = kSrcW + 6;               // source-term rows R0 - 3 .. R0 + kSrcW + 2
 constexpr int kSrcNG = (kSrcNX + kSrcG - 1) / kSrcG;
@@ -320,12 +327,11 @@ typedef __attribute__((address_space(3))) void *src_lds_ptr_t;
 
 // Direct global -> LDS copies of the staged groups.  Group m goes to
 // dst[var][r][panel]: variables [rho, u1, u2, u3, p'], source-term rows k =
-// m*kSrcG + r, panels pbase .. pbase + 31.  A piece of 64 dwords (4 bytes per lane)
-// is one (variable, row) in FP64 and two rows of a variable in FP32, so its source
-// address is a wave-uniform base plus the lane's fixed offset lane_off (panel,
-// clamped to P - 1, and the dword half or the second row).  Wave wv issues the
-// pieces wv, wv + 4, ...; pieces whose first row lies past the last row read
-// (k = kSrcW + 4) are skipped.
+// m*kSrcG + r (record row R0 - 3 + k, clamped to [0, N-1]), panels pbase ..
+// pbase + 31.  A piece of 64 dwords (4 bytes per lane) is one (variable, row) in
+// FP64 and two rows of a variable in FP32; the lane's panel (clamped to P - 1),
+// dword half and row within the piece are fixed.  Wave wv issues the pieces wv,
+// wv + 4, ...; pieces whose first row lies past the staged rows are skipped.
 template <typename TIn>
 struct SrcDma {
     static constexpr int DW = (int)sizeof(TIn) / 4;  // dwords per value
@@ -333,44 +339,47 @@ struct SrcDma {
     static constexpr int PPV = kSrcG / RPP;          // pieces per variable
     static constexpr int NPIECE = 5 * PPV;
     static constexpr int NI = (NPIECE + 3) / 4;      // pieces per wave (at most)
-    const unsigned char *base[NI];                   // source of piece i of group 0 (uniform)
+    const unsigned char *vbase[NI];                  // variable base of piece i (uniform)
     int r[NI];                                       // its first row in the group
-    int64_t gstride;                                 // bytes from one group to the next
+    int64_t rowb;                                    // bytes per record row (P values)
 
-    __device__ __forceinline__ SrcDma(const SrcFwdArgs &a, int64_t R0, int wv) {
-        const int64_t rowb = a.P * (int64_t)sizeof(TIn);
-        gstride = kSrcG * rowb;
+    __device__ __forceinline__ SrcDma(const SrcFwdArgs &a, int wv) {
+        rowb = a.P * (int64_t)sizeof(TIn);
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             int pc = wv + 4 * i;
             pc = pc < NPIECE ? pc : NPIECE - 1;
             const int var = pc / PPV;
             r[i] = (pc - var * PPV) * RPP;
-            const unsigned char *v =
-                var == 0 ? static_cast<const unsigned char *>(a.rho)
-                         : (var == 4 ? static_cast<const unsigned char *>(a.pp)
-                                     : static_cast<const unsigned char *>(a.u) + (int64_t)(var - 1) * a.N * rowb);
-            base[i] = v + (R0 - 3 + r[i]) * rowb;
+            vbase[i] = var == 0 ? static_cast<const unsigned char *>(a.rho)
+                                : (var == 4 ? static_cast<const unsigned char *>(a.pp)
+                                            : static_cast<const unsigned char *>(a.u) + (int64_t)(var - 1) * a.N * rowb);
         }
     }
 
-    __device__ __forceinline__ void issue(int m, TIn *dst, int wv, uint32_t lane_off) const {
+    // lane_row: row of this lane within a piece (0, or lane >> 5 in FP32);
+    // lane_off: byte offset of the lane's panel and dword half within a row
+    __device__ __forceinline__ void issue(int m, TIn *dst, int wv, int lane_row, uint32_t lane_off, int64_t R0,
+                                          int64_t N) const {
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int pc = wv + 4 * i;
-            bool go = (NPIECE % 4 == 0 || i + 1 < NI) ? true : pc < NPIECE;
-            if (m == kSrcNG - 1) go = go && m * kSrcG + r[i] <= kSrcW + 4;
-            if (go)
-                __builtin_amdgcn_global_load_lds((const void *)(base[i] + m * gstride + lane_off),
+            const int k0 = m * kSrcG + r[i];
+            const bool go = (NPIECE % 4 == 0 || i + 1 < NI ? true : pc < NPIECE) && k0 < kSrcNX;
+            if (go) {
+                int64_t row = R0 - 3 + k0 + lane_row;
+                row = row < 0 ? 0 : (row > N - 1 ? N - 1 : row);
+                __builtin_amdgcn_global_load_lds((const void *)(vbase[i] + row * rowb + lane_off),
                                                  (src_lds_ptr_t)((unsigned char *)dst + pc * 256), 4, 0, 0);
+            }
         }
     }
 };
 
-template <typename TIn, typename TOut>
-__device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0,
-                                                   TIn *ring1, float *tile) {
-    const int64_t P = a.P;
+template <typename TIn, typename TOut, bool GEN>
+__device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0, TIn *ring1,
+                                          float *tile, float *dvt) {
+    const int64_t P = a.P, N = a.N;
     const int pl = threadIdx.x & 31;
     const int64_t pbase = pbk * kSrcPanels;
     const int64_t pc = min(pbase + pl, P - 1);
@@ -378,51 +387,109 @@ __device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t 
     using Raw = typename SrcLane<TIn>::Raw;
     const double cpi = 2.0 - sqrt(3.0);
     const int64_t R0 = i0 - 1 - kSrcH;
+    // Exact Thomas pivots of tridiag(1, 4, 1) (GEN): c'_1 = 1/4, c'_n = 1/(4 - c'_{n-1}), in closed
+    // form c'_n = cpi (1 - q^n) / (1 - q^(n+1)) with q = cpi^2, carried as a running power of q
+    // (equal to cpi to double precision past n = 14)
+    const double q = cpi * cpi;
+    double qf = 0.0;  // q^rr of the next forward row rr >= 1
+    if constexpr (GEN) qf = exp((double)max<int64_t>(R0, 1) * log(q));
+    // 32-bit copies for the block-uniform end rules (records are far below 2^31 frames)
+    const int R0i = (int)R0, Ni = (int)N;
     // two buffers of [rho, u1, u2, u3, p'] x kSrcG rows x 32 panels; group m in buffer m & 1
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    int lane_row;
     uint32_t lane_off;
     if constexpr (sizeof(TIn) == 8) {
-        const int64_t p = min(pbase + (lane >> 1), P - 1);
-        lane_off = (uint32_t)(p * 8 + (lane & 1) * 4);
+        lane_row = 0;
+        lane_off = (uint32_t)(min(pbase + (lane >> 1), P - 1) * 8 + (lane & 1) * 4);
     } else {
-        const int64_t p = min(pbase + (lane & 31), P - 1);
-        lane_off = (uint32_t)((p + (lane >> 5) * P) * 4);
+        lane_row = lane >> 5;
+        lane_off = (uint32_t)(min(pbase + (lane & 31), P - 1) * 4);
     }
-    const SrcDma<TIn> dma(a, R0, wv);
-    dma.issue(0, ring0, wv, lane_off);
-    float dv[kSrcW];
-    // Forward sweep over source-term rows k (row R0 - 3 + k).  Step it (it = 0 .. kSrcW + 1,
-    // right-hand side of row n = R0 - 1 + it) takes X of rows k - 2, k - 1, k with k = it + 3.
-    double X0 = 0.0, X1 = 0.0, X2 = 0.0;
-    double fprev = 0.0, dprev = 0.0;
+    const SrcDma<TIn> dma(a, wv);
+    dma.issue(0, ring0, wv, lane_row, lane_off, R0, N);
+    // reduced right-hand sides, then coefficients, of window rows s: registers (interior) or the
+    // LDS tile dvt[s][kSrcRS] (GEN, whose end rules would otherwise keep too much live)
+    const int col = L.ch * 32 + pl;
+    float dvr[GEN ? 1 : kSrcW];
+    auto DV = [&](int s_) -> float & {
+        if constexpr (GEN) return dvt[s_ * kSrcRS + col];
+        else return dvr[s_];
+    };
+    // Forward sweep over source-term rows k (record row R0 - 3 + k).  Step it (it = 0 .. kSrcW + 1,
+    // right-hand side of frame n = R0 - 1 + it) takes X of frames n - 2 .. n + 2 = rows it .. it + 4.
+    double Xa = 0.0, Xb = 0.0, Xc = 0.0, Xd = 0.0, Xe = 0.0;
+    double fprev = 0.0, dprev = 0.0, f0 = 0.0, fN1 = 0.0, dN2 = 0.0;
 #pragma unroll
     for (int m = 0; m < kSrcNG; ++m) {
         // this wave's copies of group m have landed; the barrier makes every wave's visible
         // and frees the other buffer (group m - 1 has been read), which then receives m + 1
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (m + 1 < kSrcNG) dma.issue(m + 1, ((m + 1) & 1) ? ring1 : ring0, wv, lane_off);
+        if (m + 1 < kSrcNG) dma.issue(m + 1, ((m + 1) & 1) ? ring1 : ring0, wv, lane_row, lane_off, R0, N);
         const TIn *buf = (m & 1) ? ring1 : ring0;
 #pragma unroll
         for (int r = 0; r < kSrcG; ++r) {
             const int k = m * kSrcG + r;
-            if (k >= 1 && k <= kSrcW + 4) {
+            if (k < kSrcNX) {
                 const TIn *rw = buf + r * kSrcPanels + pl;
                 constexpr int VS = kSrcG * kSrcPanels;  // variable stride
                 const Raw v{rw[0], rw[VS], rw[2 * VS], rw[3 * VS], rw[4 * VS]};
-                X0 = X1;
-                X1 = X2;
-                X2 = L.X(v);
-                if (k >= 3) {
-                    const int it = k - 3;
-                    const double fn = L.s_der * (X2 - X0) + L.s_val * X1;
+                double Xn = L.X(v);
+                if constexpr (GEN) {
+                    const int mrow = R0i - 3 + k;
+                    if ((unsigned)mrow >= (unsigned)Ni) Xn = 0.0;
+                }
+                Xa = Xb;
+                Xb = Xc;
+                Xc = Xd;
+                Xd = Xe;
+                Xe = Xn;
+                if (k >= 4) {
+                    const int it = k - 4;
+                    const int n = R0i - 1 + it;
+                    double fn;
+                    if constexpr (!GEN) {
+                        fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
+                    } else {
+                        fn = 0.0;
+                        if ((unsigned)n < (unsigned)Ni) {
+                            const double dx = n == 0 ? -3.0 * Xc + 4.0 * Xd - Xe
+                                                     : (n == Ni - 1 ? 3.0 * Xc - 4.0 * Xb + Xa : Xd - Xb);
+                            fn = L.s_der * dx + L.s_val * Xc;
+                        }
+                        if (n == 0) f0 = fn;
+                        if (n == Ni - 1) fN1 = fn;
+                    }
                     if (it >= 2) {
-                        const double d = (6.0 * fprev - dprev) * cpi;
-                        dprev = d;
-                        dv[it - 2] = (float)d;
-                        // computed here, not sunk to the back substitution (which would keep
-                        // every row's inputs live)
-                        asm volatile("" : "+v"(dv[it - 2]));
+                        float dvs;
+                        if constexpr (!GEN) {
+                            const double d = (6.0 * fprev - dprev) * cpi;
+                            dprev = d;
+                            dvs = (float)d;
+                        } else {
+                            const int rr = n - 1;  // system row
+                            dvs = 0.f;
+                            if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) {
+                                double rhs = 6.0 * fprev;
+                                if (rr == 1) rhs -= f0;
+                                if (rr == Ni - 2) rhs -= fn;
+                                const double piv = cpi * (1.0 - qf) / (1.0 - qf * q);
+                                qf *= q;
+                                const double d = (rhs - dprev) * piv;
+                                dprev = d;
+                                dvs = (float)d;
+                                if (rr == Ni - 2) dN2 = d;
+                            }
+                        }
+                        if constexpr (GEN) {
+                            DV(it - 2) = dvs;
+                        } else {
+                            dvr[it - 2] = dvs;
+                            // computed here, not sunk to the back substitution (which would keep
+                            // every row's inputs live)
+                            asm volatile("" : "+v"(dvr[it - 2]));
+                        }
                     }
                     fprev = fn;
                 }
@@ -430,121 +497,56 @@ __device__ __forceinline__ void src_chunk_interior(const SrcFwdArgs &a, int64_t 
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+    // back substitution from the top of the window; window row s holds coefficient index i = R0 + s + 1
     double x = 0.0;
+    double qb = 0.0;  // q^rr of the current backward row (GEN; underflows harmlessly to 0 for large rr)
+    if constexpr (GEN) qb = exp((double)(R0 + kSrcW - 1) * log(q));
+    const double iq = 1.0 / q;
 #pragma unroll
     for (int s = kSrcW - 1; s >= 0; --s) {
-        x = (double)dv[s] - cpi * x;
-        dv[s] = (float)x;
-    }
-    const int col = L.ch * 32 + pl;
-    TOut *coef = static_cast<TOut *>(a.coef);
-    constexpr int QT = kSrcTC / 4;
-#pragma unroll
-    for (int qt = 0; qt < 4; ++qt) {
-        __syncthreads();  // the previous quarter's tile has been read
-#pragma unroll
-        for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dv[kSrcH + qt * QT + q];
-        __syncthreads();
-        src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
-    }
-}
-
-// General chunk (either record end in reach): one-sided differences at the
-// first and last frame, zero source terms outside the record, the end rows'
-// right-hand-side corrections, exact pivots, end coefficients c_{-1}, c_0,
-// c_{N-1}, c_N and zero padding.  Reduced right-hand sides go to the LDS tile
-// [kSrcW][kSrcRS]; the output values overwrite them in place.
-template <typename TIn>
-__device__ __forceinline__ void src_chunk_general(const SrcFwdArgs &a, int64_t pbk, int64_t i0, float *tile) {
-    const int64_t P = a.P, N = a.N;
-    const int pl = threadIdx.x & 31;
-    const int64_t pbase = pbk * kSrcPanels;
-    const int64_t pc = min(pbase + pl, P - 1);
-    const SrcLane<TIn> L(a, pc);
-    const double *__restrict__ cp = a.cp;
-    const double cpi = 2.0 - sqrt(3.0);
-    const double sfd = L.s_der;  // 1/(2 dtau) on derivative lanes
-    const int col = L.ch * 32 + pl;
-    const int64_t R0 = i0 - 1 - kSrcH;
-    auto X = [&](int64_t m) -> double { return (m >= 0 && m < N) ? L.X(m * P) : 0.0; };
-    double Xa = X(R0 - 3), Xb = X(R0 - 2), Xc = X(R0 - 1), Xd = X(R0), Xe = X(R0 + 1);
-    double fprev = 0.0, f0 = 0.0, fN1 = 0.0, dprev = 0.0, dN2 = 0.0;
-    constexpr int ITER = kSrcW + 2;
-    for (int g0 = 0; g0 < ITER; g0 += kSrcPF) {
-        double Xf[kSrcPF];
-#pragma unroll
-        for (int q = 0; q < kSrcPF; ++q) Xf[q] = X(R0 + 2 + g0 + q);
-#pragma unroll
-        for (int q = 0; q < kSrcPF; ++q) {
-            const int it = g0 + q;
-            if (it < ITER) {
-                const int64_t n = R0 - 1 + it;  // Xa..Xe = X(n-2) .. X(n+2)
-                double fn = 0.0;
-                if (n >= 0 && n < N) {
-                    double dx;
-                    if (n == 0) dx = -3.0 * Xc + 4.0 * Xd - Xe;
-                    else if (n == N - 1) dx = 3.0 * Xc - 4.0 * Xb + Xa;
-                    else dx = Xd - Xb;
-                    fn = sfd * dx + L.s_val * Xc;
-                }
-                if (n == 0) f0 = fn;
-                if (n == N - 1) fN1 = fn;
-                if (it >= 2) {
-                    const int64_t r = n - 1;
-                    float dvs = 0.f;
-                    if (r >= 1 && r <= N - 2) {
-                        double rhs = 6.0 * fprev;
-                        if (r == 1) rhs -= f0;
-                        if (r == N - 2) rhs -= fn;
-                        const double d = (rhs - dprev) * (r < 64 ? cp[r] : cpi);
-                        dprev = d;
-                        dvs = (float)d;
-                        if (r == N - 2) dN2 = d;
-                    }
-                    tile[(it - 2) * kSrcRS + col] = dvs;
-                }
-                fprev = fn;
-                Xa = Xb;
-                Xb = Xc;
-                Xc = Xd;
-                Xd = Xe;
-                Xe = Xf[q];
+        if constexpr (!GEN) {
+            x = (double)dvr[s] - cpi * x;
+            dvr[s] = (float)x;
+        } else {
+            const int rr = R0i + s;
+            if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) x = (double)DV(s) - cpi * (1.0 - qb) / (1.0 - qb * q) * x;
+            qb *= iq;
+            if (s >= kSrcH && s < kSrcH + kSrcTC) {
+                const int i = rr + 1;
+                double v;
+                if (i == 0) v = 2.0 * f0 - x;
+                else if (i == 1) v = f0;
+                else if (i < Ni) v = x;
+                else if (i == Ni) v = fN1;
+                else if (i == Ni + 1) v = 2.0 * fN1 - dN2;
+                else v = 0.0;
+                DV(s) = (float)v;
             }
         }
     }
-    // back substitution from the top of the window; coefficient index i = r + 1
-    double x = 0.0;
-    for (int s = kSrcW - 1; s >= 0; --s) {
-        const int64_t r = R0 + s;
-        if (r >= 1 && r <= N - 2) x = (double)tile[s * kSrcRS + col] - (r < 64 ? cp[r] : cpi) * x;
-        if (s >= kSrcH && s < kSrcH + kSrcTC) {
-            const int64_t i = r + 1;
-            double v;
-            if (i == 0) v = 2.0 * f0 - x;
-            else if (i == 1) v = f0;
-            else if (i < N) v = x;
-            else if (i == N) v = fN1;
-            else if (i == N + 1) v = 2.0 * fN1 - dN2;
-            else v = 0.0;
-            tile[s * kSrcRS + col] = (float)v;
+    TOut *coef = static_cast<TOut *>(a.coef);
+    if constexpr (GEN) {
+        __syncthreads();
+        src_flush(dvt + kSrcH * kSrcRS, coef, pbase, P, a.NS, i0);
+    } else {
+        constexpr int QT = kSrcTC / 4;
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) {
+            __syncthreads();  // the previous quarter's tile has been read
+#pragma unroll
+            for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dvr[kSrcH + qt * QT + q];
+            __syncthreads();
+            src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
         }
     }
 }
 
-template <typename TIn, typename TOut>
-__device__ __forceinline__ void src_interior_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
+template <typename TIn, typename TOut, bool GEN>
+__device__ __forceinline__ void src_chunk_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
     __shared__ TIn ring0[kSrcGV];
     __shared__ TIn ring1[kSrcGV];
-    __shared__ float tile[(kSrcTC / 4) * kSrcRS];
-    src_chunk_interior<TIn, TOut>(a, pbk, k * kSrcTC, ring0, ring1, tile);
-}
-
-template <typename TIn, typename TOut>
-__device__ __forceinline__ void src_general_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
-    __shared__ float tile[kSrcW * kSrcRS];
-    src_chunk_general<TIn>(a, pbk, k * kSrcTC, tile);
-    __syncthreads();
-    src_flush(tile + kSrcH * kSrcRS, static_cast<TOut *>(a.coef), pbk * kSrcPanels, a.P, a.NS, k * kSrcTC);
+    __shared__ float tile[GEN ? kSrcW * kSrcRS : (kSrcTC / 4) * kSrcRS];
+    src_chunk<TIn, TOut, GEN>(a, pbk, k * kSrcTC, ring0, ring1, tile, tile);
 }
 
 // ------------------------------------------------ chunked source adjoint stage
@@ -977,12 +979,12 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(SrcFwdArgs a) {
 // grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_kernel(SrcFwdArgs a) {
-    src_interior_block<TIn, TOut>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
+    src_chunk_block<TIn, TOut, false>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
 }
 // grid (panel blocks, general chunks)
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void src_general_kernel(SrcFwdArgs a) {
-    src_general_block<TIn, TOut>(a, blockIdx.x, src_general_chunk(blockIdx.y, src_interior_chunks(a.N)));
+    src_chunk_block<TIn, TOut, true>(a, blockIdx.x, src_general_chunk(blockIdx.y, src_interior_chunks(a.N)));
 }
 // batched: blocks of case c are [start[c], start[c+1]), panel block major
 template <typename TIn, typename TOut>
@@ -992,7 +994,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int64_t local = (int64_t)blockIdx.x - start[c];
     const int64_t nk = src_interior_chunks(cases[c].src.N);
     const int64_t pbk = local / nk;
-    src_interior_block<TIn, TOut>(cases[c].src, pbk, 1 + local - pbk * nk);
+    src_chunk_block<TIn, TOut, false>(cases[c].src, pbk, 1 + local - pbk * nk);
 }
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void src_general_batched(const BatchCase *__restrict__ cases,
@@ -1002,7 +1004,7 @@ __global__ __launch_bounds__(256) void src_general_batched(const BatchCase *__re
     const int64_t nint = src_interior_chunks(cases[c].src.N);
     const int64_t ng = cases[c].src.NS / kSrcTC - nint;
     const int64_t pbk = local / ng;
-    src_general_block<TIn, TOut>(cases[c].src, pbk, src_general_chunk(local - pbk * ng, nint));
+    src_chunk_block<TIn, TOut, true>(cases[c].src, pbk, src_general_chunk(local - pbk * ng, nint));
 }
 
 template <typename TR>
