@@ -25,7 +25,9 @@
 //     range); per panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton
 //     steps on the splined trajectory (started from its solution for the
 //     previous panel; a step below 1e-6 dtau is accepted without a further
-//     check, the iteration being quadratic), evaluates the channels at tau_ret
+//     check, the iteration being quadratic, and the position at tau_ret is the
+//     last evaluation advanced by that step; the next panel's first taps are
+//     fetched together with this panel's channel taps), evaluates the channels at tau_ret
 //     with the four B-spline taps (two contiguous 16-byte loads per channel and
 //     lane) and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi) in FP64.
 //     Panel ranges (splits) are summed by gm_reduce_kernel in fixed order.
@@ -269,6 +271,19 @@ __device__ __forceinline__ double gm_tap(const double *row, int64_t j, const dou
     return w[0] * lo.x + w[1] * lo.y + w[2] * hi.x + w[3] * hi.y;
 }
 
+// The six 16-byte loads of the trajectory taps of interval j (rows y_1..3).
+struct GmTraj {
+    gm_d2 a0, b0, a1, b1, a2, b2;
+    __device__ __forceinline__ void load(const double *ry0, const double *ry1, const double *ry2, int64_t j) {
+        a0 = *reinterpret_cast<const gm_d2 *>(ry0 + j);
+        b0 = *reinterpret_cast<const gm_d2 *>(ry0 + j + 2);
+        a1 = *reinterpret_cast<const gm_d2 *>(ry1 + j);
+        b1 = *reinterpret_cast<const gm_d2 *>(ry1 + j + 2);
+        a2 = *reinterpret_cast<const gm_d2 *>(ry2 + j);
+        b2 = *reinterpret_cast<const gm_d2 *>(ry2 + j + 2);
+    }
+};
+
 __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -289,35 +304,50 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int64_t pb = z * a.p_chunk;
     const int64_t pe = min(pb + a.p_chunk, a.P);
     double acc = 0.0;
-    double tau = 0.0;
-    bool warm = false;
+    if (pb >= pe) {
+        if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = 0.0;
+        return;
+    }
+    // first panel of the range: start from the emission time of frame 0's position
+    double tau;
+    {
+        const double *cf = a.coef + pb * kGmRows * NS;
+        const double d0 = x0 - cf[GY1 * NS + 1], d1 = x1 - cf[GY2 * NS + 1], d2 = x2 - cf[GY3 * NS + 1];
+        tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
+    }
+    // taps of the current panel at the current guess (loaded ahead: for the next panel they are
+    // fetched together with this panel's channel taps)
+    GmTraj tr;
+    {
+        double u;
+        const int64_t j = gm_locate(tau, tau0, dtau, N, u);
+        const double *cf = a.coef + pb * kGmRows * NS;
+        tr.load(cf + GY1 * NS, cf + GY2 * NS, cf + GY3 * NS, j);
+    }
     for (int64_t p = pb; p < pe; ++p) {
         const double *cf = a.coef + p * kGmRows * NS;
         const double *ry0 = cf + GY1 * NS, *ry1 = cf + GY2 * NS, *ry2 = cf + GY3 * NS;
-        if (!warm) {  // first panel of the range: start from the emission time of frame 0's position
-            const double d0 = x0 - ry0[1], d1 = x1 - ry1[1], d2 = x2 - ry2[1];
-            tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
-            warm = true;
-        }
-        // Newton on g(tau) = tau + M0 |x - Y(tau)| - t, g' = 1 - M0 rhat . Y'(tau)
+        // Newton on g(tau) = tau + M0 |x - Y(tau)| - t, g' = 1 - M0 rhat . Y'(tau); the first step
+        // uses the preloaded taps.  Y and dY/dtau of the last evaluation are kept.
+        double Y0, Y1, Y2, V0, V1, V2, taue;
         for (int it = 0; it < kGmNewtonMax; ++it) {
             double u;
             const int64_t j = gm_locate(tau, tau0, dtau, N, u);
             double w[4], dw[4];
             bspline_w(u, w, dw);
-            const gm_d2 a0 = *reinterpret_cast<const gm_d2 *>(ry0 + j), b0 = *reinterpret_cast<const gm_d2 *>(ry0 + j + 2);
-            const gm_d2 a1 = *reinterpret_cast<const gm_d2 *>(ry1 + j), b1 = *reinterpret_cast<const gm_d2 *>(ry1 + j + 2);
-            const gm_d2 a2 = *reinterpret_cast<const gm_d2 *>(ry2 + j), b2 = *reinterpret_cast<const gm_d2 *>(ry2 + j + 2);
-            const double Y0 = w[0] * a0.x + w[1] * a0.y + w[2] * b0.x + w[3] * b0.y;
-            const double Y1 = w[0] * a1.x + w[1] * a1.y + w[2] * b1.x + w[3] * b1.y;
-            const double Y2 = w[0] * a2.x + w[1] * a2.y + w[2] * b2.x + w[3] * b2.y;
-            const double D0 = dw[0] * a0.x + dw[1] * a0.y + dw[2] * b0.x + dw[3] * b0.y;
-            const double D1 = dw[0] * a1.x + dw[1] * a1.y + dw[2] * b1.x + dw[3] * b1.y;
-            const double D2 = dw[0] * a2.x + dw[1] * a2.y + dw[2] * b2.x + dw[3] * b2.y;
+            if (it > 0) tr.load(ry0, ry1, ry2, j);
+            Y0 = w[0] * tr.a0.x + w[1] * tr.a0.y + w[2] * tr.b0.x + w[3] * tr.b0.y;
+            Y1 = w[0] * tr.a1.x + w[1] * tr.a1.y + w[2] * tr.b1.x + w[3] * tr.b1.y;
+            Y2 = w[0] * tr.a2.x + w[1] * tr.a2.y + w[2] * tr.b2.x + w[3] * tr.b2.y;
+            const double idt = 1.0 / dtau;
+            V0 = (dw[0] * tr.a0.x + dw[1] * tr.a0.y + dw[2] * tr.b0.x + dw[3] * tr.b0.y) * idt;
+            V1 = (dw[0] * tr.a1.x + dw[1] * tr.a1.y + dw[2] * tr.b1.x + dw[3] * tr.b1.y) * idt;
+            V2 = (dw[0] * tr.a2.x + dw[1] * tr.a2.y + dw[2] * tr.b2.x + dw[3] * tr.b2.y) * idt;
+            taue = tau;
             const double r0 = x0 - Y0, r1 = x1 - Y1, r2 = x2 - Y2;
             const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
             const double g = tau + M0 * r - t;
-            const double gd = 1.0 - M0 * (r0 * D0 + r1 * D1 + r2 * D2) / (r * dtau);
+            const double gd = 1.0 - M0 * (r0 * V0 + r1 * V1 + r2 * V2) / r;
             double step = active ? g / gd : 0.0;
             const double tn = fmin(fmax(tau - step, tau0), tmax);
             step = tau - tn;
@@ -326,12 +356,19 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
             const bool done = !(fabs(step) > accept);
             if (__all(done)) break;
         }
-        // channels at tau_ret and the integrand
+        // position at tau_ret from the last evaluation by its first-order step (the step is below
+        // 1e-6 dtau, the remainder O(step^2 |Y''|) is below rounding)
+        const double dt_last = tau - taue;
+        const double r0 = x0 - (Y0 + V0 * dt_last), r1 = x1 - (Y1 + V1 * dt_last), r2 = x2 - (Y2 + V2 * dt_last);
         double u;
         const int64_t j = gm_locate(tau, tau0, dtau, N, u);
         double w[4], dw[4];
         bspline_w(u, w, dw);
-        const double r0 = x0 - gm_tap(ry0, j, w), r1 = x1 - gm_tap(ry1, j, w), r2 = x2 - gm_tap(ry2, j, w);
+        // next panel's first Newton taps at this panel's retarded time (issued with the channel taps)
+        if (p + 1 < pe) {
+            const double *cn = cf + kGmRows * NS;
+            tr.load(cn + GY1 * NS, cn + GY2 * NS, cn + GY3 * NS, j);
+        }
         const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
         const double ir = 1.0 / r;
         const double h0 = r0 * ir, h1 = r1 * ir, h2 = r2 * ir;
