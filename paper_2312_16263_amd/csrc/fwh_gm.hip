@@ -142,16 +142,24 @@ __global__ __launch_bounds__(256) void gm_prefilter_kernel(double *coef, int64_t
     const bool valid = row < rows;
     const double *fr = coef + (valid ? row : r0) * NS;
     const double f0 = fr[1], fN1 = fr[N];
+    // chunk moves: all 16 loads of a thread are issued before the LDS stores
     auto move = [&](int64_t c0, int len, bool to_lds) {
-#pragma unroll 4
-        for (int i = 0; i < kPfRows / 16; ++i) {
-            const int rr = i * 16 + (tid >> 4), ss = tid & 15;
-            const int64_t g = r0 + rr;
-            if (g < rows && ss < len) {
-                if (to_lds)
-                    tile[rr][ss] = coef[g * NS + c0 + ss];
-                else
-                    coef[g * NS + c0 + ss] = tile[rr][ss];
+        const int ss = tid & 15;
+        if (to_lds) {
+            double v[kPfRows / 16];
+#pragma unroll
+            for (int i = 0; i < kPfRows / 16; ++i) {
+                const int64_t g = r0 + i * 16 + (tid >> 4);
+                v[i] = (g < rows && ss < len) ? coef[g * NS + c0 + ss] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < kPfRows / 16; ++i) tile[i * 16 + (tid >> 4)][ss] = v[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < kPfRows / 16; ++i) {
+                const int rr = i * 16 + (tid >> 4);
+                const int64_t g = r0 + rr;
+                if (g < rows && ss < len) coef[g * NS + c0 + ss] = tile[rr][ss];
             }
         }
     };
