@@ -265,7 +265,9 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     const int64_t k0 = kb * kLdsK;
     const int64_t pb = z * p_chunk;
     const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
-    const int64_t obase = t * kObsTile + (int64_t)wv * kObsPerWave;
+    // wave wv takes the tile's observers wv, wv + 8, wv + 16, wv + 24, so that a partly filled
+    // tile spreads its observers over all waves
+    const int64_t tbase = t * kObsTile;
     const int2 *twt = tw + t * P;
     const int64_t ot_last = (O - 1 - t * kObsTile) < kObsTile - 1 ? (O - 1 - t * kObsTile) : kObsTile - 1;
 
@@ -307,19 +309,27 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             acc[j][m] = 0.f;
             accd[j][m] = 0.0;
         }
-    // sub-rows of 61 samples below the largest window of this wave's observers (0: nothing to do)
-    int nt_wave = 0;
+    // this wave's valid observers (a prefix j < nobs) and the sub-rows of 61 samples below the
+    // largest of their windows (0: nothing to do)
+    int nt_wave = 0, nobs = 0;
 #pragma unroll
-    for (int j = 0; j < kObsPerWave; ++j)
-        if (obase + j < O) nt_wave = nt[obase + j] > nt_wave ? nt[obase + j] : nt_wave;
+    for (int j = 0; j < kObsPerWave; ++j) {
+        const int64_t o = tbase + j * kLdsWaves + wv;
+        if (o < O) {
+            nt_wave = nt[o] > nt_wave ? nt[o] : nt_wave;
+            nobs = j + 1;
+        }
+    }
+    nobs = __builtin_amdgcn_readfirstlane(nobs);
     int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
     nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > kLdsSub ? kLdsSub : nsub));
-    // one panel of the stage for this wave's observers, NSUB sub-rows
-    auto panel_work = [&](auto nsub_c, const float4 *lrec, const QT *L0, const QT *L1, int lo, int q) {
+    // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows
+    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const QT *L0, const QT *L1, int lo, int q) {
+        constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
-        for (int j = 0; j < kObsPerWave; ++j) {
-            const float4 *R = lrec + (q * kObsTile + wv * kObsPerWave + j) * 4;
+        for (int j = 0; j < NOBS; ++j) {
+            const float4 *R = lrec + (q * kObsTile + j * kLdsWaves + wv) * 4;
             const float4 Ka = R[0], Kb = R[1], W = R[2];
             const int off = __float_as_int(R[3].x) - lo;
 #pragma unroll
@@ -376,13 +386,22 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
             const QT *L1 = L0 + NW;
             // every record slot of the tile holds a valid record (slots past the last
-            // observer repeat it); the wave skips the sub-rows past its observers' windows
-            switch (nsub) {
+            // observer repeat it); the wave skips the sub-rows past its observers' windows and
+            // the observer slots past its last valid one (3 valid slots run as 4)
+            auto by_sub = [&](auto nobs_c) {
+                switch (nsub) {
+                    case 0: break;
+                    case 1: panel_work(nobs_c, std::integral_constant<int, 1>{}, lrec, L0, L1, lo, q); break;
+                    case 2: panel_work(nobs_c, std::integral_constant<int, 2>{}, lrec, L0, L1, lo, q); break;
+                    case 3: panel_work(nobs_c, std::integral_constant<int, 3>{}, lrec, L0, L1, lo, q); break;
+                    default: panel_work(nobs_c, std::integral_constant<int, kLdsSub>{}, lrec, L0, L1, lo, q); break;
+                }
+            };
+            switch (nobs) {
                 case 0: break;
-                case 1: panel_work(std::integral_constant<int, 1>{}, lrec, L0, L1, lo, q); break;
-                case 2: panel_work(std::integral_constant<int, 2>{}, lrec, L0, L1, lo, q); break;
-                case 3: panel_work(std::integral_constant<int, 3>{}, lrec, L0, L1, lo, q); break;
-                default: panel_work(std::integral_constant<int, kLdsSub>{}, lrec, L0, L1, lo, q); break;
+                case 1: by_sub(std::integral_constant<int, 1>{}); break;
+                case 2: by_sub(std::integral_constant<int, 2>{}); break;
+                default: by_sub(std::integral_constant<int, kObsPerWave>{}); break;
             }
             if (++cnt == kChunk) {
 #pragma unroll
@@ -399,7 +418,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     if (lane < kLdsLanesOut) {
 #pragma unroll
         for (int j = 0; j < kObsPerWave; ++j) {
-            const int64_t o = obase + j;
+            const int64_t o = tbase + j * kLdsWaves + wv;
             if (o < O) {
                 const int64_t ntl = nt[o];
 #pragma unroll
