@@ -142,3 +142,18 @@ def test_gm_plan_create_rejects(kw, code):
     assert L.fwh_gm_plan_create(ctypes.byref(_gm_args(**kw)), ctypes.byref(h), ctypes.byref(nb)) == code
     assert not h.value
     assert fwh.lib().fwh_last_error().decode()
+
+
+def test_gm_profile_entry_points_host_only():
+    """Enabling and reading the stage timers needs no GPU while nothing was recorded."""
+    L = fwh.lib()
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.fwh_gm_plan_create(ctypes.byref(_gm_args()), ctypes.byref(h), ctypes.byref(nb)) == 0
+    assert L.fwh_gm_profile_enable(h, 1) == 0
+    ms, n = ctypes.c_double(-1.0), ctypes.c_int64(-1)
+    for stage in (0, 1):
+        assert L.fwh_gm_profile_read(h, stage, ctypes.byref(ms), ctypes.byref(n)) == 0
+        assert ms.value == 0.0 and n.value == 0
+    assert L.fwh_gm_profile_read(h, 2, ctypes.byref(ms), ctypes.byref(n)) == fwh.FWH_EINVAL
+    assert L.fwh_gm_profile_enable(None, 1) == fwh.FWH_EINVAL
+    L.fwh_gm_destroy(h)
