@@ -23,8 +23,8 @@
 //     N_t = floor((t_end - t_start)/dtau + 1e-9) + 1 (-1 for an empty window).
 //  4. gm_gather_kernel: a wave owns (observer, 64 consecutive samples, panel
 //     range); per panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton
-//     steps on the splined trajectory (started from its solution for the
-//     previous panel; a step below 1e-6 dtau is accepted without a further
+//     steps on the splined trajectory (started from the linear extrapolation of
+//     its solutions for the two previous panels; a step below 1e-6 dtau is accepted without a further
 //     check, the iteration being quadratic, and the position at tau_ret is the
 //     last evaluation advanced by that step; the next panel's first taps are
 //     fetched together with this panel's channel taps), evaluates the channels at tau_ret
@@ -324,7 +324,9 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
     }
     // taps of the current panel at the current guess (loaded ahead: for the next panel they are
-    // fetched together with this panel's channel taps)
+    // fetched together with this panel's channel taps); the guess for the next panel extrapolates
+    // the retarded times of the last two panels (neighbouring panels are visited in order)
+    double tau_prev = 0.0;
     GmTraj tr;
     {
         double u;
@@ -372,10 +374,14 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const int64_t j = gm_locate(tau, tau0, dtau, N, u);
         double w[4], dw[4];
         bspline_w(u, w, dw);
-        // next panel's first Newton taps at this panel's retarded time (issued with the channel taps)
+        // next panel's guess and first Newton taps (issued with the channel taps)
+        const double tau_next = p == pb ? tau : fmin(fmax(2.0 * tau - tau_prev, tau0), tmax);
+        tau_prev = tau;
         if (p + 1 < pe) {
+            double un;
+            const int64_t jn = gm_locate(tau_next, tau0, dtau, N, un);
             const double *cn = cf + kGmRows * NS;
-            tr.load(cn + GY1 * NS, cn + GY2 * NS, cn + GY3 * NS, j);
+            tr.load(cn + GY1 * NS, cn + GY2 * NS, cn + GY3 * NS, jn);
         }
         const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
         const double ir = 1.0 / r;
@@ -391,6 +397,7 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const double F =
             ir * iom * iom * (ch(GA) + M0 * Ldr + ir * (Lr - ch(GLM)) + ir * iom * conv * (ch(GQN) + M0 * Lr));
         if (active) acc += F * a.dS[p];
+        tau = tau_next;
     }
     if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = active ? acc * (1.0 / (4.0 * kPiD)) : 0.0;
 }
