@@ -257,6 +257,57 @@ def bench_batch(replays, sync):
     return out
 
 
+def bench_ingest(sync, n_frames=256, n_ascii=8, threads=16):
+    """Ingestion of OpenCFD-FWH dataset files (Appendix A layouts) for the
+    dipole workload's 32768 panels: n_frames binary frames (40 B per panel)
+    written to a temporary directory, read by the library's threaded reader into
+    page-locked FP64 host tensors, then copied to the device; a few ASCII
+    frames for comparison.  The files were just written, so reads come from the
+    page cache: this is parse + scatter speed, not disk speed."""
+    import tempfile
+
+    import torch
+
+    from paper_2312_16263_amd import fileio
+    from workloads import configs
+    c = configs.dipole_sphere(n_tau=n_frames)
+    rho, u, pp = c.data()
+    dims = np.array([[128, 256, 1]], dtype=np.int64)
+    P = c.n_panels
+    out = {"workload": f"dipole sphere, {P} panels, one Face; {n_frames} binary frames, {n_ascii} ASCII frames; "
+                       f"{threads} reader threads; warm page cache", "panels": P}
+    with tempfile.TemporaryDirectory(prefix="fwh_ingest_") as d:
+        for fmt, nf, key in ((fileio.BINARY, n_frames, "binary"), (fileio.ASCII, n_ascii, "ascii")):
+            for k in range(nf):
+                fileio.write_frame(fileio.frame_path(d, k), fmt, dims, rho[k], u[:, k], pp[k])
+            nbytes = sum(os.path.getsize(fileio.frame_path(d, k)) for k in range(nf))
+            host = (torch.empty((nf, P), dtype=torch.float64, pin_memory=True),
+                    torch.empty((3, nf, P), dtype=torch.float64, pin_memory=True),
+                    torch.empty((nf, P), dtype=torch.float64, pin_memory=True))
+            fileio.read_frames(d, 0, 1, nf, fmt, dims, out=host, threads=threads)  # warm
+            t0 = time.perf_counter()
+            fileio.read_frames(d, 0, 1, nf, fmt, dims, out=host, threads=threads)
+            t_read = time.perf_counter() - t0
+            assert np.array_equal(host[1].numpy(), u[:, :nf])
+            dev = [torch.empty_like(h, device="cuda") for h in host]
+            sync()
+            t0 = time.perf_counter()
+            for dv, h in zip(dev, host):
+                dv.copy_(h, non_blocking=True)
+            sync()
+            t_h2d = time.perf_counter() - t0
+            arr = 5 * nf * P * 8
+            out[key] = {"frames": nf, "file_bytes": nbytes, "read_s": t_read, "file_GB_per_s": nbytes / t_read / 1e9,
+                        "frames_per_s": nf / t_read, "h2d_s": t_h2d, "h2d_GB_per_s": arr / t_h2d / 1e9,
+                        "read_plus_h2d_panel_frames_per_s": nf * P / (t_read + t_h2d)}
+            log(f"[bench] ingest {key}: {nf} frames, {nbytes / 1e6:.1f} MB read in {t_read * 1e3:.1f} ms "
+                f"({nbytes / t_read / 1e9:.2f} GB/s), H2D {arr / t_h2d / 1e9:.1f} GB/s")
+            for k in range(nf):
+                os.remove(fileio.frame_path(d, k))
+            del dev, host
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +322,7 @@ def main():
                     help="short run for rocprofv3: 1 warmup + `--steps` FP32 steps, then a 1 GiB device copy "
                          "(the reference kernel for HBM byte counters); prints no JSON")
     ap.add_argument("--mode", default="f32", choices=["f32", "bf16"], help="mode of the profile run")
+    ap.add_argument("--ingest-only", action="store_true", help="only the file-ingestion measurement (JSON line)")
     ap.add_argument("--workload", default="dipole_sphere",
                     choices=["dipole_sphere", "airfoil_broadband", "general_motion"],
                     help="workload of the profile run")
@@ -290,6 +342,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     sync = torch.cuda.synchronize
+    if args.ingest_only:
+        print(json.dumps({"ingest": bench_ingest(sync)}), flush=True)
+        return
     if args.profile_run and args.workload == "general_motion":
         bench_general_motion(args.steps, sync, profile_only=True)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -428,6 +483,7 @@ def main():
         extra["airfoil_broadband"] = bench_airfoil(3, sync)
         extra["batched"] = bench_batch(5, sync)
         extra["general_motion"] = bench_general_motion(5, sync)
+        extra["ingest"] = bench_ingest(sync)
 
     out = {
         "metric": "FW-H panel-obs-samples/s (fwd, adjoint) vs FP64 plain at stated err; % HBM peak",

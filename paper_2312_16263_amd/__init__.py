@@ -32,6 +32,9 @@ EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fw
             "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_profile_enable",
             "fwh_gm_profile_read", "fwh_gm_destroy", "fwh_last_error",
             "fwh_version"]
+# names declared in include/fwh_io.h
+IO_EXPORTED = ["fwh_io_control_read", "fwh_io_geometry_read", "fwh_io_geometry_write", "fwh_io_observers_read",
+               "fwh_io_frame_path", "fwh_io_frames_read", "fwh_io_frame_write", "fwh_io_last_error"]
 STAGES = {"setup": 0, "source": 1, "gather": 2, "reduce": 3, "adj_gather": 4, "source_adj": 5}
 
 
@@ -124,6 +127,20 @@ def lib():
         L.fwh_last_error.restype = ctypes.c_char_p
         L.fwh_version.argtypes = []
         L.fwh_version.restype = ctypes.c_char_p
+        # host-side file readers, include/fwh_io.h
+        cs = ctypes.c_char_p
+        for name, args in (("fwh_io_control_read", [cs, vp, i32, ctypes.POINTER(i32)]),
+                           ("fwh_io_geometry_read", [cs, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp, vp,
+                                                     i64, i64]),
+                           ("fwh_io_geometry_write", [cs, i64, vp, vp, vp, vp]),
+                           ("fwh_io_observers_read", [cs, ctypes.POINTER(i64), vp, i64]),
+                           ("fwh_io_frame_path", [cs, i64, ctypes.c_char_p, i64]),
+                           ("fwh_io_frames_read", [cs, i64, i64, i64, i32, i64, vp, i32, vp, vp, vp, i32]),
+                           ("fwh_io_frame_write", [cs, i32, i64, vp, vp, vp, vp, vp, vp])):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = ctypes.c_int
+        L.fwh_io_last_error.argtypes = []
+        L.fwh_io_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 

@@ -11,6 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwh.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["fwh_api.hip", "fwh_setup.hip", "fwh_source.hip", "fwh_gather.hip", "fwh_post.hip", "fwh_gm.hip"]
+HOST_SOURCES = ["fwh_io.cpp"]  # host-only C++ (file readers), built with the host compiler
 ARCH = os.environ.get("FWH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          # no packed FP32 instructions anywhere in the device code
@@ -31,10 +32,20 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(r.stderr)
         return obj
 
+    def compile_host(src):
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        cmd = [os.environ.get("CXX", "g++"), "-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"host compile failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        host = [ex.submit(compile_host, s) for s in HOST_SOURCES]
+        objs = list(ex.map(compile_one, SOURCES)) + [h.result() for h in host]
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
-every function include/fwh.h declares, and fwh_plan_create / fwh_setup /
+every function include/fwh.h and include/fwh_io.h declare, and fwh_plan_create / fwh_setup /
 fwh_forward reject bad arguments with the documented codes before any HIP call."""
 import ctypes
 import os
@@ -14,8 +14,8 @@ from workloads import surfaces
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    text = open(os.path.join(ROOT, "include", "fwh.h")).read()
+def header_functions(name="fwh.h"):
+    text = open(os.path.join(ROOT, "include", name)).read()
     return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(fwh_\w+)\s*\(", text, flags=re.M)))
 
 
@@ -26,6 +26,18 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert "gfx950" in fwh.version()
+
+
+def test_library_exports_every_file_io_function():
+    L = fwh.lib()
+    names = header_functions("fwh_io.h")
+    assert set(names) == set(fwh.IO_EXPORTED), names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_headers_cover_every_include():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["fwh.h", "fwh_io.h"]
 
 
 def _args(**kw):

@@ -1,0 +1,345 @@
+"""Readers and writers of the OpenCFD-FWH files (Sec. III A, Appendix A;
+include/fwh_io.h).  CPU only.
+
+* A hand-written case (tests/golden/opencfd_case) read back to the values typed
+  here: namelist comments, case-folded keys, Fortran 'd' exponents, arrays,
+  logicals, quoted text holding '/' and '!'; two Faces; a blank observer line.
+* Independent codecs: dataset and geometry files written here with struct /
+  text formatting are read by the library bit for bit, and the library's
+  writers are decoded here bit for bit, in both formats.
+* Round trip of a whole case through save_case / load_case, FP32 reads equal
+  to the rounded doubles, thread counts, pinned outputs.
+* Error paths: missing files, truncated and mislabelled records, Face
+  dimensions that differ from the geometry, counts that disagree."""
+import os
+import shutil
+import struct
+
+import numpy as np
+import pytest
+
+from paper_2312_16263_amd import fileio
+from workloads import configs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "opencfd_case")
+
+
+def test_golden_control():
+    ent = fileio.read_control_entries(os.path.join(GOLDEN, "control.fwh"))
+    assert {g for g, _, _ in ent} == {"control_fwh"}
+    ctl = fileio.read_control(os.path.join(GOLDEN, "control.fwh"))
+    assert ctl["mach"] == 0.5 and isinstance(ctl["mach"], float)
+    assert ctl["aoa"] == 10.0 and ctl["dt"] == 2.0e-3
+    assert (ctl["kstep_start"], ctl["kstep_end"], ctl["delta_step"]) == (100, 120, 10)
+    assert ctl["fwh_data_format"] == 1 and ctl["number_of_observers"] == 3 and ctl["num_threads"] == 2
+    assert ctl["title"] == "Face / test ! kept"
+    assert ctl["probes"] == [1, 2, 3]
+    assert ctl["verbose"] is True
+    assert len(ent) == 12
+
+
+def test_golden_geometry_and_observers():
+    g = fileio.read_geometry(os.path.join(GOLDEN, "FWH_Surface_Geo.dat"))
+    np.testing.assert_array_equal(g.face_dims, [[2, 1, 1], [1, 1, 3]])
+    np.testing.assert_array_equal(g.face_id, [0, 0, 1, 1, 1])
+    np.testing.assert_array_equal(g.y, [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 2]])
+    np.testing.assert_array_equal(g.normal, [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1]])
+    np.testing.assert_array_equal(g.dS, [0.25, 0.5, 0.125, 0.15, 0.75])
+    x = fileio.read_observers(os.path.join(GOLDEN, "observers.dat"))
+    np.testing.assert_array_equal(x, [[10, 0, 0], [0, -20.5, 1], [-3, 4, 5]])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_golden_case(dtype):
+    c = fileio.load_case(GOLDEN, dtype=dtype)
+    assert (c.mach, c.aoa_deg, c.n_frames, c.fmt) == (0.5, 10.0, 3, fileio.ASCII)
+    assert c.dtau == pytest.approx(0.02, rel=1e-15) and c.tau0 == pytest.approx(0.2, rel=1e-15)
+    k = np.arange(3)[:, None]
+    rho = np.array([1.0, 1.1, 1.2, 1.3, 1.4])[None, :] + 0.01 * k
+    u1 = np.tile([0.1, 0.2, 0.3, 0.4, 0.5], (3, 1))
+    u2 = np.tile([0.0, 0.0, 0.01, 0.0, 0.0], (3, 1))
+    u3 = np.tile([0.0, 0.0, 0.0, -0.01, 0.0], (3, 1))
+    pp = np.array([[0.0, -0.0, 1e-3, 2e-3, -0.5e-3], [1e-3, -1e-3, 1e-3, 2e-3, -1.5e-3],
+                   [2e-3, -2e-3, 1e-3, 2e-3, -2.5e-3]])
+    want = [np.array([float(f"{v:.2f}") for v in rho.ravel()]).reshape(3, 5), np.stack([u1, u2, u3]), pp]
+    dt = np.float64 if dtype == "f64" else np.float32
+    for got, w in zip((c.rho, c.u, c.pp), want):
+        assert got.dtype == dt
+        np.testing.assert_array_equal(got, w.astype(dt))
+
+
+# ----------------------------------------------------------- independent codecs
+def _py_write_frame(path, fmt, dims, vals):
+    """vals [5][P] (rho, u1, u2, u3, p'); the layout of include/fwh_io.h."""
+    P0 = 0
+    if fmt == fileio.ASCII:
+        with open(path, "w") as f:
+            for d in dims:
+                m = int(np.prod(d))
+                f.write(" ".join(str(int(v)) for v in d) + "\n")
+                for q in range(P0, P0 + m):
+                    f.write(" ".join(repr(float(vals[v][q])) for v in range(5)) + "\n")
+                P0 += m
+        return
+    with open(path, "wb") as f:
+        for d in dims:
+            m = int(np.prod(d))
+            f.write(struct.pack("<I3iI", 12, *[int(v) for v in d], 12))
+            body = b"".join(struct.pack(f"<{m}d", *vals[v][P0:P0 + m]) for v in range(5))
+            f.write(struct.pack("<I", len(body)) + body + struct.pack("<I", len(body)))
+            P0 += m
+
+
+def _py_read_frame(path, fmt, dims):
+    P = int(sum(np.prod(d) for d in dims))
+    out = np.zeros((5, P))
+    P0 = 0
+    if fmt == fileio.ASCII:
+        lines = [ln.split() for ln in open(path).read().splitlines() if ln.strip()]
+        i = 0
+        for d in dims:
+            m = int(np.prod(d))
+            assert [int(v) for v in lines[i]] == [int(v) for v in d]
+            for q in range(m):
+                out[:, P0 + q] = [float(v) for v in lines[i + 1 + q]]
+            i += 1 + m
+            P0 += m
+        return out
+    b = open(path, "rb").read()
+    o = 0
+    for d in dims:
+        m = int(np.prod(d))
+        n0, a, bb, c, n1 = struct.unpack_from("<I3iI", b, o)
+        assert (n0, n1, a, bb, c) == (12, 12, *[int(v) for v in d])
+        o += 20
+        (n,) = struct.unpack_from("<I", b, o)
+        assert n == 40 * m
+        out[:, P0:P0 + m] = np.frombuffer(b, "<f8", 5 * m, o + 4).reshape(5, m)
+        assert struct.unpack_from("<I", b, o + 4 + n) == (n,)
+        o += 8 + n
+        P0 += m
+    assert o == len(b)
+    return out
+
+
+def _random_faces(rng, P_target=700):
+    dims = []
+    while sum(int(np.prod(d)) for d in dims) < P_target:
+        a, b = rng.integers(1, 17, 2)
+        d = [a, b]
+        d.insert(int(rng.integers(0, 3)), 1)
+        dims.append(d)
+    return np.array(dims, dtype=np.int64)
+
+
+def _awkward_values(rng, P):
+    """Values that stress text formatting: subnormals, huge, negative zero, exact binary fractions."""
+    v = rng.standard_normal((5, P)) * 10.0 ** rng.integers(-300, 300, (5, P))
+    v[0, :4] = [5e-324, -0.0, 1.7976931348623157e308, 0.1]
+    return v
+
+
+@pytest.mark.parametrize("fmt", [fileio.BINARY, fileio.ASCII])
+def test_library_reads_independently_written_frames(tmp_path, fmt):
+    rng = np.random.default_rng(7)
+    dims = _random_faces(rng)
+    P = int(np.prod(dims, axis=1).sum())
+    N = 5
+    vals = [_awkward_values(rng, P) for _ in range(N)]
+    for k in range(N):
+        _py_write_frame(fileio.frame_path(str(tmp_path), 40 + 3 * k), fmt, dims, vals[k])
+    rho, u, pp = fileio.read_frames(str(tmp_path), 40, 3, N, fmt, dims)
+    for k in range(N):
+        np.testing.assert_array_equal(rho[k], vals[k][0])
+        np.testing.assert_array_equal(u[:, k], vals[k][1:4])
+        np.testing.assert_array_equal(pp[k], vals[k][4])
+        assert np.signbit(rho[k][1])
+    r32, u32, p32 = fileio.read_frames(str(tmp_path), 40, 3, N, fmt, dims, dtype="f32")
+    with np.errstate(over="ignore"):
+        for k in range(N):
+            np.testing.assert_array_equal(r32[k], vals[k][0].astype(np.float32))
+            np.testing.assert_array_equal(u32[:, k], vals[k][1:4].astype(np.float32))
+            np.testing.assert_array_equal(p32[k], vals[k][4].astype(np.float32))
+
+
+@pytest.mark.parametrize("fmt", [fileio.BINARY, fileio.ASCII])
+def test_library_writes_independently_decodable_frames(tmp_path, fmt):
+    rng = np.random.default_rng(8)
+    dims = _random_faces(rng, 300)
+    P = int(np.prod(dims, axis=1).sum())
+    v = _awkward_values(rng, P)
+    path = str(tmp_path / "f.dat")
+    fileio.write_frame(path, fmt, dims, v[0], v[1:4], v[4])
+    np.testing.assert_array_equal(_py_read_frame(path, fmt, dims), v)
+
+
+def test_geometry_codecs(tmp_path):
+    rng = np.random.default_rng(9)
+    dims = _random_faces(rng, 400)
+    P = int(np.prod(dims, axis=1).sum())
+    y, nrm, dS = rng.standard_normal((P, 3)), rng.standard_normal((P, 3)), rng.random(P)
+    p1 = str(tmp_path / "g1.dat")
+    with open(p1, "w") as f:  # written here
+        f.write(f"variables=x,y,z,n1,n2,n3,dS\n {len(dims)}\n")
+        q = 0
+        for d in dims:
+            f.write("  %d  %d  %d\n" % tuple(d))
+            for _ in range(int(np.prod(d))):
+                f.write("\t".join(repr(float(a)) for a in (*y[q], *nrm[q], dS[q])) + "\n")
+                q += 1
+    g = fileio.read_geometry(p1)
+    np.testing.assert_array_equal(g.face_dims, dims)
+    for a, b in ((g.y, y), (g.normal, nrm), (g.dS, dS)):
+        np.testing.assert_array_equal(a, b)
+    p2 = str(tmp_path / "g2.dat")
+    fileio.write_geometry(p2, g)  # written by the library, decoded here
+    lines = open(p2).read().splitlines()
+    assert lines[0] == "variables=x,y,z,n1,n2,n3,dS" and int(lines[1]) == len(dims)
+    rows = np.array([[float(t) for t in ln.split()] for ln in lines[2:] if len(ln.split()) == 7])
+    np.testing.assert_array_equal(rows, np.hstack([y, nrm, dS[:, None]]))
+
+
+def _sphere_case(n_theta=8, n_phi=16, n_tau=40):
+    c = configs.dipole_sphere(n_theta=n_theta, n_phi=n_phi, n_tau=n_tau, n_obs=6)
+    rho, u, pp = c.data()
+    dims = np.array([[n_theta // 2, n_phi, 1], [1, n_theta // 2, n_phi]], dtype=np.int64)
+    geom = fileio.Geometry(dims, c.surface.y, c.surface.normal, c.surface.dS)
+    return c, geom, rho, u, pp
+
+
+@pytest.mark.parametrize("fmt", [fileio.BINARY, fileio.ASCII])
+def test_case_round_trip(tmp_path, fmt):
+    c, geom, rho, u, pp = _sphere_case()
+    d = str(tmp_path / "case")
+    fileio.save_case(d, c.mach, c.aoa_deg, c.dtau / 4, 1000, 4, geom, c.x_obs, rho, u, pp, fmt=fmt, threads=3)
+    back = fileio.load_case(d)
+    assert (back.mach, back.aoa_deg, back.n_frames, back.fmt) == (c.mach, c.aoa_deg, c.n_tau, fmt)
+    assert back.dtau == pytest.approx(c.dtau, rel=1e-15)
+    np.testing.assert_array_equal(back.geometry.y, c.surface.y)
+    np.testing.assert_array_equal(back.geometry.normal, c.surface.normal)
+    np.testing.assert_array_equal(back.geometry.dS, c.surface.dS)
+    np.testing.assert_array_equal(back.x_obs, c.x_obs)
+    for a, b in ((back.rho, rho), (back.u, u), (back.pp, pp)):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(back.geometry.face_id[:64], 0)
+    np.testing.assert_array_equal(back.geometry.face_id[64:], 1)
+
+
+def test_thread_counts_agree(tmp_path):
+    c, geom, rho, u, pp = _sphere_case(n_tau=37)
+    d = str(tmp_path / "case")
+    fileio.save_case(d, c.mach, c.aoa_deg, c.dtau, 0, 1, geom, c.x_obs, rho, u, pp)
+    ref = fileio.read_frames(d, 0, 1, 37, fileio.BINARY, geom.face_dims, threads=1)
+    for t in (2, 5, 8, 64, 0):
+        got = fileio.read_frames(d, 0, 1, 37, fileio.BINARY, geom.face_dims, threads=t)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_read_into_caller_buffers(tmp_path):
+    import torch
+    c, geom, rho, u, pp = _sphere_case(n_tau=12)
+    d = str(tmp_path / "case")
+    fileio.save_case(d, c.mach, c.aoa_deg, c.dtau, 0, 1, geom, c.x_obs, rho, u, pp)
+    out = (torch.empty(rho.shape, dtype=torch.float32), torch.empty(u.shape, dtype=torch.float32),
+           torch.empty(pp.shape, dtype=torch.float32))
+    fileio.read_frames(d, 0, 1, 12, fileio.BINARY, geom.face_dims, dtype="f32", out=out)
+    np.testing.assert_array_equal(out[1].numpy(), u.astype(np.float32))
+    with pytest.raises(ValueError):
+        fileio.read_frames(d, 0, 1, 12, fileio.BINARY, geom.face_dims, dtype="f64", out=out)
+    with pytest.raises(ValueError):
+        fileio.read_frames(d, 0, 1, 12, fileio.BINARY, geom.face_dims, out=(rho[:, ::2], u, pp))
+
+
+# ----------------------------------------------------------------- error paths
+def _copy_golden(tmp_path):
+    d = str(tmp_path / "case")
+    shutil.copytree(GOLDEN, d)
+    return d
+
+
+def _expect(code, fn, *a, match=None, **kw):
+    with pytest.raises(fileio.FwhIOError, match=match) as e:
+        fn(*a, **kw)
+    assert e.value.code == code
+    return e.value
+
+
+def test_missing_files(tmp_path):
+    d = _copy_golden(tmp_path)
+    os.remove(os.path.join(d, "FWH-00000110.dat"))
+    _expect(fileio.FWH_IO_EFILE, fileio.load_case, d, match="FWH-00000110.dat")
+    _expect(fileio.FWH_IO_EFILE, fileio.read_geometry, str(tmp_path / "none.dat"))
+    _expect(fileio.FWH_IO_EFILE, fileio.read_observers, str(tmp_path / "none.dat"))
+    _expect(fileio.FWH_IO_EFILE, fileio.read_control, str(tmp_path / "none.fwh"))
+
+
+def test_frame_format_errors(tmp_path):
+    dims = np.array([[2, 1, 1], [1, 1, 3]], dtype=np.int64)
+    v = np.arange(25, dtype=np.float64).reshape(5, 5)
+    d = str(tmp_path)
+    p = fileio.frame_path(d, 0)
+    fileio.write_frame(p, fileio.BINARY, dims, v[0], v[1:4], v[4])
+    good = open(p, "rb").read()
+    cases = {
+        "truncated": good[:-3],
+        "extra bytes": good + b"\0",
+        "record length": good[:20] + struct.pack("<I", 39 * 2) + good[24:],
+        "trailing length": good[:-4] + struct.pack("<I", 7),
+        "dimensions": struct.pack("<I3iI", 12, 1, 2, 1, 12) + good[20:],
+    }
+    for what, blob in cases.items():
+        open(p, "wb").write(blob)
+        _expect(fileio.FWH_IO_EFORMAT, fileio.read_frames, d, 0, 1, 1, fileio.BINARY, dims)
+    text = "2 1 1\n1 2 3 4 5\n1 2 3 4 5\n1 1 3\n1 2 3 4 5\n1 2 3 4 5\n1 2 3 4 5\n"
+    for what, t in {"short": text[:-4], "word": text.replace("3 4 5\n1 1", "3 x 5\n1 1"),
+                    "dims": text.replace("1 1 3", "1 3 1"), "extra": text + "9\n"}.items():
+        open(p, "w").write(t)
+        _expect(fileio.FWH_IO_EFORMAT, fileio.read_frames, d, 0, 1, 1, fileio.ASCII, dims)
+    open(p, "w").write(text)
+    fileio.read_frames(d, 0, 1, 1, fileio.ASCII, dims)
+    _expect(fileio.FWH_IO_EINVAL, fileio.read_frames, d, 0, 0, 1, fileio.ASCII, dims)
+    _expect(fileio.FWH_IO_EINVAL, fileio.read_frames, d, 0, 1, 1, 2, dims)
+    _expect(fileio.FWH_IO_EINVAL, fileio.read_frames, d, 99999999, 1, 2, fileio.ASCII, dims)
+    _expect(fileio.FWH_IO_EINVAL, fileio.frame_path, d, -1)
+
+
+def test_text_file_errors(tmp_path):
+    p = str(tmp_path / "f")
+    for body in ("variables=x,y,z,n1,n2,n3,dS\n", "variables\n1\n1 1 0\n",
+                 "variables\n1\n1 1 2\n1 2 3 4 5 6 7\n1 2 3 4 5 6\n"):
+        open(p, "w").write(body)
+        _expect(fileio.FWH_IO_EFORMAT, fileio.read_geometry, p)
+    open(p, "w").write("1 2 3\n4 5\n")
+    _expect(fileio.FWH_IO_EFORMAT, fileio.read_observers, p, match="line 2")
+    for body in ("&g\n a 1 /\n", "&g\n a = 'open\n/\n"):
+        open(p, "w").write(body)
+        _expect(fileio.FWH_IO_EFORMAT, fileio.read_control, p)
+    open(p, "w").write("&g\n a = '" + "x" * 300 + "'\n/\n")
+    _expect(fileio.FWH_IO_ESIZE, fileio.read_control, p)
+
+
+def test_namelist_forms(tmp_path):
+    p = str(tmp_path / "c.fwh")
+    open(p, "w").write("text before the group is ignored\n"
+                       "&first  A=1,B = -2.5d+1 ,C='it''s'\n d=.false. /\n"
+                       "$second\n  e = T, f = 1.0e-3\n  g = 'x = 1, y = 2'\n&end\n")
+    ent = fileio.read_control_entries(p)
+    assert [(g, k) for g, k, _ in ent] == [("first", "a"), ("first", "b"), ("first", "c"), ("first", "d"),
+                                          ("second", "e"), ("second", "f"), ("second", "g")]
+    ctl = fileio.read_control(p)
+    assert ctl["a"] == 1 and ctl["b"] == -25.0 and ctl["d"] is False and ctl["e"] is True
+    assert ctl["f"] == 1e-3 and ctl["g"] == "x = 1, y = 2" and ctl["c"] == "it's"
+
+
+def test_case_consistency_errors(tmp_path):
+    d = _copy_golden(tmp_path)
+    ctl = open(os.path.join(d, "control.fwh")).read()
+    open(os.path.join(d, "control.fwh"), "w").write(ctl.replace("number_of_observers = 3", "number_of_observers = 4"))
+    _expect(fileio.FWH_IO_EFORMAT, fileio.load_case, d, match="n_observers")
+    open(os.path.join(d, "control.fwh"), "w").write(ctl.replace("Kstep_end = 120", "Kstep_end = 125"))
+    _expect(fileio.FWH_IO_EFORMAT, fileio.load_case, d, match="whole frames")
+    open(os.path.join(d, "control.fwh"), "w").write(ctl.replace("Mach = 0.5d0", "Speed = 0.5d0"))
+    _expect(fileio.FWH_IO_EFORMAT, fileio.load_case, d, match="mach")
+    open(os.path.join(d, "control.fwh"), "w").write(ctl)
+    assert fileio.load_case(d, frames=False).rho is None

@@ -12,8 +12,9 @@
                    c_s/U0 (dtau = 1.2642e-3), 72 observers every 5 deg at R = 10 about
                    mid-chord; seeded broadband data, RMS 1 % of freestream, FP32.
 
-`scaled(name, ...)` shrinks a workload (panel grid, samples, observers) for
-parity tests that the FP64 oracle finishes in seconds.
+The constructors take the panel grid, samples and observers as arguments, so
+parity tests build the same workloads at sizes the FP64 oracle finishes in
+seconds.
 """
 from __future__ import annotations
 
