@@ -1,6 +1,6 @@
 """A case read from OpenCFD-FWH files (Appendix A layouts, include/fwh_io.h)
 runs through the HIP path exactly as the same arrays handed over directly:
-bit-identical output, and parity with the FP64 oracle on the original arrays
+bit-identical output, and parity with the FP64 oracle on the data as read
 (relative L2 1e-11 for the FP64 form, 1e-5 for FP32).  The frames are read
 into page-locked host tensors and copied to the device asynchronously."""
 import numpy as np
@@ -42,9 +42,11 @@ def test_case_from_files_matches_direct_arrays(tmp_path, fmt, mode):
     direct = plan.forward(*to_device((rho, u, pp), tdt))
     torch.cuda.synchronize()
     assert torch.equal(out_files, direct)
-    # the loaded tau0 = 500 * dtau/5 = 5.0 shifts every window start by 5.0
-    p_ref, ts_ref, nt_ref = oracle_forward(c, rho, u, pp)
-    np.testing.assert_allclose(plan.window.t_start, ts_ref + 5.0, rtol=1e-14, atol=0)
+    # frame 0 is solver step 500 at dt = dtau/5: tau0 = 1.0 shifts every window start by 1.0
+    assert fc.tau0 == pytest.approx(1.0, rel=1e-15)
+    # the oracle sees the data as stored (FP32 frames are the rounded doubles)
+    p_ref, ts_ref, nt_ref = oracle_forward(c, *(t.numpy().astype(np.float64) for t in (fc.rho, fc.u, fc.pp)))
+    np.testing.assert_allclose(plan.window.t_start, ts_ref + fc.tau0, rtol=1e-14, atol=0)
     assert np.array_equal(plan.window.n_t, nt_ref)
     p = out_files.double().cpu().numpy()
     m = valid_mask(nt_ref, p.shape[1])
