@@ -464,10 +464,12 @@ def main():
             pr, _, ntr = oracle.forward(c.surface, xs, c.mach, c.aoa_deg, c.dtau, c.tau0, rho, u, pp)
             oracle.adjoint(c.surface, xs, c.mach, c.aoa_deg, c.dtau, c.tau0, rho, u, pp, 2.0 * pr)
             return time.perf_counter() - t, int(c.n_panels * int(ntr.sum()))
-        # two probes separate the fixed cost (layout transposes, window) from the per-observer cost
+        # two probes separate the fixed cost (layout transposes, window) from the per-observer cost;
+        # a first call warms the thread pool and the allocations so that it does not inflate them
+        oracle_step(np.array([0]))
         t1o, _ = oracle_step(np.array([0]))
-        t2o, _ = oracle_step(np.array([0, c.n_obs // 2]))
-        per_obs = max(t2o - t1o, 1e-3)
+        t9o, _ = oracle_step(np.linspace(0, c.n_obs - 1, 9).round().astype(int))
+        per_obs = max((t9o - t1o) / 8.0, 1e-3)
         fixed = max(t1o - per_obs, 0.0)
         n_s = int(min(c.n_obs, max(1, round((args.cpu_seconds - fixed) / per_obs))))
         idx = np.unique(np.linspace(0, c.n_obs - 1, n_s).round().astype(int))
