@@ -324,20 +324,22 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
     nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > kLdsSub ? kLdsSub : nsub));
     // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows
-    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const QT *L0, const QT *L1, int lo, int q) {
+    // (Lq: the panel's first-group window shifted by lane - lo, so that one add per observer
+    // gives each lane's element; the second group follows NW elements later)
+    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const QT *Lq, int q) {
         constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
         for (int j = 0; j < NOBS; ++j) {
             const float4 *R = lrec + (q * kObsTile + j * kLdsWaves + wv) * 4;
             const float4 Ka = R[0], Kb = R[1], W = R[2];
-            const int off = __float_as_int(R[3].x) - lo;
+            const QT *P0 = Lq + __float_as_int(R[3].x);
+            const QT *P1 = P0 + NW;
 #pragma unroll
             for (int m = 0; m < NSUB; ++m) {
-                const int idx = off + m * kLdsLanesOut + lane;
                 float a[4], c[4];
-                Quad<TS>::unpack(L0[idx], a);
-                Quad<TS>::unpack(L1[idx], c);
+                Quad<TS>::unpack(P0[m * kLdsLanesOut], a);
+                Quad<TS>::unpack(P1[m * kLdsLanesOut], c);
                 float g = Ka.x * a[0];
                 g = fmaf(Ka.y, a[1], g);
                 g = fmaf(Ka.z, a[2], g);
@@ -358,61 +360,70 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             }
         }
     };
-    int cnt = 0;
-    int b = 0;
-    // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
-    auto load_lo = [&](int64_t ps) {
-        const int64_t q = ps + lane < pe ? ps + lane : pe - 1;
-        return twt[q].x;
-    };
-    int lo_cur = 0;
-    if (pb < pe) {
-        fill(pb, 0);
-        lo_cur = load_lo(pb);
-    }
-    for (int64_t ps = pb; ps < pe; ps += PT, b ^= 1) {
-        const int np = (int)(pe - ps < PT ? pe - ps : PT);
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
-        __syncthreads();                // ... and every wave's; the other buffer is free
-        const int lo_stage = lo_cur;
-        if (ps + PT < pe) {
-            fill(ps + PT, b ^ 1);
-            lo_cur = load_lo(ps + PT);
+    // The stage loop, compiled once per (observers, sub-rows) of the wave: both are fixed for the
+    // whole block, so the accumulators keep their registers across panels.  A wave without work
+    // (NOBS = 0) still issues its share of the copies and meets every barrier.
+    auto stage_loop = [&](auto nobs_c, auto nsub_c) {
+        constexpr int NOBS = decltype(nobs_c)::value;
+        constexpr int NSUB = decltype(nsub_c)::value;
+        int cnt = 0;
+        int b = 0;
+        // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
+        auto load_lo = [&](int64_t ps) {
+            const int64_t q = ps + lane < pe ? ps + lane : pe - 1;
+            return twt[q].x;
+        };
+        int lo_cur = 0;
+        if (pb < pe) {
+            fill(pb, 0);
+            lo_cur = load_lo(pb);
         }
-        const unsigned char *base = smem_raw + (size_t)b * buf_bytes;
-        const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
-        for (int q = 0; q < np; ++q) {
-            const int lo = __builtin_amdgcn_readlane(lo_stage, q);
-            const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
-            const QT *L1 = L0 + NW;
-            // every record slot of the tile holds a valid record (slots past the last
-            // observer repeat it); the wave skips the sub-rows past its observers' windows and
-            // the observer slots past its last valid one (3 valid slots run as 4)
-            auto by_sub = [&](auto nobs_c) {
-                switch (nsub) {
-                    case 0: break;
-                    case 1: panel_work(nobs_c, std::integral_constant<int, 1>{}, lrec, L0, L1, lo, q); break;
-                    case 2: panel_work(nobs_c, std::integral_constant<int, 2>{}, lrec, L0, L1, lo, q); break;
-                    case 3: panel_work(nobs_c, std::integral_constant<int, 3>{}, lrec, L0, L1, lo, q); break;
-                    default: panel_work(nobs_c, std::integral_constant<int, kLdsSub>{}, lrec, L0, L1, lo, q); break;
+        for (int64_t ps = pb; ps < pe; ps += PT, b ^= 1) {
+            const int np = (int)(pe - ps < PT ? pe - ps : PT);
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
+            __syncthreads();                // ... and every wave's; the other buffer is free
+            const int lo_stage = lo_cur;
+            if (ps + PT < pe) {
+                fill(ps + PT, b ^ 1);
+                lo_cur = load_lo(ps + PT);
+            }
+            const unsigned char *base = smem_raw + (size_t)b * buf_bytes;
+            const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
+            for (int q = 0; q < np; ++q) {
+                const int lo = __builtin_amdgcn_readlane(lo_stage, q);
+                const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
+                panel_work(nobs_c, nsub_c, lrec, L0 + (lane - lo), q);
+                if (++cnt == kChunk) {
+#pragma unroll
+                    for (int j = 0; j < NOBS; ++j)
+#pragma unroll
+                        for (int m = 0; m < NSUB; ++m) {
+                            accd[j][m] += (double)acc[j][m];
+                            acc[j][m] = 0.f;
+                        }
+                    cnt = 0;
                 }
-            };
-            switch (nobs) {
-                case 0: break;
-                case 1: by_sub(std::integral_constant<int, 1>{}); break;
-                case 2: by_sub(std::integral_constant<int, 2>{}); break;
-                default: by_sub(std::integral_constant<int, kObsPerWave>{}); break;
             }
-            if (++cnt == kChunk) {
-#pragma unroll
-                for (int j = 0; j < kObsPerWave; ++j)
-#pragma unroll
-                    for (int m = 0; m < kLdsSub; ++m) {
-                        accd[j][m] += (double)acc[j][m];
-                        acc[j][m] = 0.f;
-                    }
-                cnt = 0;
-            }
+        }
+    };
+    // every record slot of the tile holds a valid record (slots past the last observer repeat
+    // it); the wave skips the sub-rows past its observers' windows and the observer slots past its
+    // last valid one (3 valid slots run as 4)
+    auto by_sub = [&](auto nobs_c) {
+        switch (nsub) {
+            case 1: stage_loop(nobs_c, std::integral_constant<int, 1>{}); break;
+            case 2: stage_loop(nobs_c, std::integral_constant<int, 2>{}); break;
+            case 3: stage_loop(nobs_c, std::integral_constant<int, 3>{}); break;
+            default: stage_loop(nobs_c, std::integral_constant<int, kLdsSub>{}); break;
+        }
+    };
+    if (nobs == 0 || nsub == 0) {
+        stage_loop(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    } else {
+        switch (nobs) {
+            case 1: by_sub(std::integral_constant<int, 1>{}); break;
+            case 2: by_sub(std::integral_constant<int, 2>{}); break;
+            default: by_sub(std::integral_constant<int, kObsPerWave>{}); break;
         }
     }
     if (lane < kLdsLanesOut) {
