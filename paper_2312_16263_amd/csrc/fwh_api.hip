@@ -53,7 +53,7 @@ struct fwh_plan {
     bool ready = false;
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
-    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_tw = 0, off_wblk = 0;
+    size_t off_K64 = 0, off_W64 = 0, off_N0 = 0, off_rec_op = 0, off_rbf = 0, off_tw = 0, off_wblk = 0;
     size_t off_coef = 0, off_scr = SIZE_MAX, off_part = 0, off_gpad = 0, ws_bytes = 0;
     char *ws = nullptr;
     // optional per-stage event timing
@@ -63,6 +63,7 @@ struct fwh_plan {
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     void *scratch() const { return off_scr == SIZE_MAX ? nullptr : ws + off_scr; }
+    fwh::PairBf *rbf() const { return mode == FWH_MODE_BF16 ? at<fwh::PairBf>(off_rbf) : nullptr; }
 };
 
 namespace {
@@ -92,6 +93,7 @@ int layout(fwh_plan *pl) {
         pl->off_N0 = take(O * P * sizeof(int32_t));
     } else {
         pl->off_rec_op = take(O * P * sizeof(fwh::PairRec));
+        if (pl->mode == FWH_MODE_BF16) pl->off_rbf = take(O * P * sizeof(fwh::PairBf));
         pl->off_tw = take((O + fwh::kObsTile - 1) / fwh::kObsTile * P * sizeof(int2));
         pl->off_wblk = take((size_t)fwh::tile_window_blocks(pl->P, pl->O) * sizeof(int32_t));
     }
@@ -258,7 +260,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
                                 pl->at<double>(pl->off_x), pl->at<double>(pl->off_ts), pl->at<int32_t>(pl->off_nt), P,
                                 O, N, pl->flow, f64 ? pl->at<double>(pl->off_K64) : nullptr,
                                 f64 ? pl->at<double>(pl->off_W64) : nullptr, f64 ? pl->at<int32_t>(pl->off_N0) : nullptr,
-                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op), st)))
+                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(), st)))
         return hip_fail("fwh_setup: table kernel", e);
     if (!f64) {
         // per (observer tile, panel) windows of n0 and their largest width -> LDS staging geometry
@@ -277,8 +279,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         // window length per channel group: a multiple of 64 elements (whole wave-wide direct loads)
         const int nw = ((wmax + fwh::kLdsK + fwh::kLdsHalo + 63) / 64) * 64;
         // two stage buffers of PT panels: windows of both groups plus the tile's pair records
-        int64_t pt = (int64_t)(fwh::kLdsBudget /
-                               (2 * ((size_t)8 * nw * esz + fwh::kObsTile * sizeof(fwh::PairRec))));
+        int64_t pt = (int64_t)(fwh::kLdsBudget / (2 * fwh::gather_lds_panel_bytes(esz == sizeof(float) ? 1 : 2, nw)));
         if (pt > fwh::kMaxPanelsPerStage) pt = fwh::kMaxPanelsPerStage;
         pl->lds_nw = nw;
         pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit: the direct-load gather is used
@@ -338,7 +339,8 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
         {
             StageScope sc(pl, FWH_STAGE_GATHER, st);
             if (pl->lds_pt > 0)
-                e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int2>(pl->off_tw),
+                e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                           pl->at<int2>(pl->off_tw),
                                            pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O, pl->NS,
                                            pl->n_t_max, pl->splits, pl->lds_nw, pl->lds_pt,
                                            pl->at<double>(pl->off_part), st);
@@ -558,7 +560,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         fwh::BatchCase &d = desc[c];
         d.src = fwh::SrcFwdArgs{k.rho, k.u, k.p_prime, pl->at<double>(pl->off_n), P, N, NS, pl->flow,
                                 pl->at<double>(pl->off_cp), pl->scratch(), pl->ws + pl->off_coef};
-        d.gat = fwh::GatherArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int2>(pl->off_tw),
+        d.gat = fwh::GatherArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(), pl->at<int2>(pl->off_tw),
                                 pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, P, O, NS, ntm, p_chunk,
                                 pl->lds_nw, pl->lds_pt, (int)S, pl->at<double>(pl->off_part)};
         d.red = fwh::ReduceArgs{pl->at<double>(pl->off_part), (int)S, O * ntm, static_cast<float *>(k.p_out)};

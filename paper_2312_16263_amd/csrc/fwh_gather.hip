@@ -219,6 +219,12 @@ struct Stage<uint16_t> {
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// a.lo * b.lo + a.hi * b.hi + c for two bfloat16 pairs (v_dot2_f32_bf16)
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+
 // Direct global -> LDS copy of `count` units of Stage::kBytesPerLoad bytes from
 // src (byte address of unit u: src + u*bytes, clamped to unit `last`) to LDS at
 // dst (unit u at dst + u*bytes), wave w handling 64-unit chunks w, w + 8, ...
@@ -258,8 +264,10 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     double *__restrict__ partial = a.partial;
     using QT = typename Quad<TS>::T;
     constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels)
+    constexpr bool kBf = std::is_same<TS, uint16_t>::value;
     const size_t win_bytes = (size_t)2 * NW * EB;                    // one panel, both groups
-    const size_t buf_bytes = (size_t)PT * (win_bytes + kObsTile * sizeof(PairRec));
+    // stage buffer: PT windows, then PT x kObsTile records, then (BF16) PT x kObsTile split weights
+    const size_t buf_bytes = (size_t)PT * (win_bytes + kObsTile * (sizeof(PairRec) + (kBf ? sizeof(PairBf) : 0)));
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t k0 = kb * kLdsK;
@@ -298,6 +306,19 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const float4 *srec = reinterpret_cast<const float4 *>(rec + (t * kObsTile + jj) * P + ps + q) + (r & 3);
             __builtin_amdgcn_global_load_lds((const void *)srec, (lds_ptr_t)(rbase + ci * 64 * 16), 16, 0, 0);
         }
+        if constexpr (kBf) {
+            // split weights: for panel q, observer j of the tile -> 32 bytes at [q][j]
+            unsigned char *bbase = rbase + (size_t)PT * kObsTile * sizeof(PairRec);
+            const int bunits = np * kObsTile * 2;
+            for (int ci = wv; ci * 64 < bunits; ci += kLdsWaves) {
+                int u = ci * 64 + lane;
+                u = u < bunits ? u : bunits - 1;
+                const int q = u / (kObsTile * 2), r = u - q * (kObsTile * 2);
+                const int64_t jj = (r >> 1) < ot_last ? (r >> 1) : ot_last;
+                const uint4 *sb = reinterpret_cast<const uint4 *>(a.rbf + (t * kObsTile + jj) * P + ps + q) + (r & 1);
+                __builtin_amdgcn_global_load_lds((const void *)sb, (lds_ptr_t)(bbase + ci * 64 * 16), 16, 0, 0);
+            }
+        }
     };
 
     float acc[kObsPerWave][kLdsSub];
@@ -331,23 +352,49 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
         for (int j = 0; j < NOBS; ++j) {
-            const float4 *R = lrec + (q * kObsTile + j * kLdsWaves + wv) * 4;
-            const float4 Ka = R[0], Kb = R[1], W = R[2];
+            const int slot = q * kObsTile + j * kLdsWaves + wv;
+            const float4 *R = lrec + slot * 4;
+            const float4 W = R[2];
             const QT *P0 = Lq + __float_as_int(R[3].x);
             const QT *P1 = P0 + NW;
+            float4 Ka, Kb;
+            uint4 Kh, Kl;
+            if constexpr (kBf) {
+                const uint4 *B = reinterpret_cast<const uint4 *>(lrec + PT * kObsTile * 4) + slot * 2;
+                Kh = B[0];
+                Kl = B[1];
+            } else {
+                Ka = R[0];
+                Kb = R[1];
+            }
 #pragma unroll
             for (int m = 0; m < NSUB; ++m) {
-                float a[4], c[4];
-                Quad<TS>::unpack(P0[m * kLdsLanesOut], a);
-                Quad<TS>::unpack(P1[m * kLdsLanesOut], c);
-                float g = Ka.x * a[0];
-                g = fmaf(Ka.y, a[1], g);
-                g = fmaf(Ka.z, a[2], g);
-                g = fmaf(Ka.w, a[3], g);
-                g = fmaf(Kb.x, c[0], g);
-                g = fmaf(Kb.y, c[1], g);
-                g = fmaf(Kb.z, c[2], g);
-                g = fmaf(Kb.w, c[3], g);
+                float g;
+                if constexpr (kBf) {
+                    // packed bf16 dot products: channel pairs of the four-channel elements against the
+                    // high and low parts of their weights
+                    const uint2 e0 = P0[m * kLdsLanesOut], e1 = P1[m * kLdsLanesOut];
+                    g = dot2_bf16(Kh.x, e0.x, 0.f);
+                    g = dot2_bf16(Kh.y, e0.y, g);
+                    g = dot2_bf16(Kh.z, e1.x, g);
+                    g = dot2_bf16(Kh.w, e1.y, g);
+                    g = dot2_bf16(Kl.x, e0.x, g);
+                    g = dot2_bf16(Kl.y, e0.y, g);
+                    g = dot2_bf16(Kl.z, e1.x, g);
+                    g = dot2_bf16(Kl.w, e1.y, g);
+                } else {
+                    float a[4], c[4];
+                    Quad<TS>::unpack(P0[m * kLdsLanesOut], a);
+                    Quad<TS>::unpack(P1[m * kLdsLanesOut], c);
+                    g = Ka.x * a[0];
+                    g = fmaf(Ka.y, a[1], g);
+                    g = fmaf(Ka.z, a[2], g);
+                    g = fmaf(Ka.w, a[3], g);
+                    g = fmaf(Kb.x, c[0], g);
+                    g = fmaf(Kb.y, c[1], g);
+                    g = fmaf(Kb.z, c[2], g);
+                    g = fmaf(Kb.w, c[3], g);
+                }
                 const float g1 = from_next_lane(g);
                 const float g2 = from_next_lane(g1);
                 const float g3 = from_next_lane(g2);
@@ -653,11 +700,11 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
     return hipGetLastError();
 }
 
-hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *tw, const int32_t *nt, const void *coef,
-                             int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
-                             double *partial, hipStream_t stream) {
+hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
+                             const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
+                             int PT, double *partial, hipStream_t stream) {
     const int64_t p_chunk = (P + splits - 1) / splits;
-    const GatherArgs a{rec_op, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
+    const GatherArgs a{rec_op, rbf, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
     const int64_t tiles = (O + kObsTile - 1) / kObsTile, kblocks = (nt_max + kLdsK - 1) / kLdsK;
     const dim3 n1((unsigned)(tiles * kblocks * splits));
     const size_t shmem = gather_lds_shmem(coef_type, NW, PT);

@@ -22,6 +22,15 @@ struct alignas(64) PairRec {
 };
 static_assert(sizeof(PairRec) == 64, "PairRec must be 64 bytes");
 
+// BF16 mode: the 8 weights K_c of a pair as bfloat16 high and low parts
+// (K ~ hi + lo to 2^-17 relative), channels (2i, 2i + 1) in word i (even channel
+// in the low half), for the packed bf16 dot products of the forward gather.
+struct alignas(32) PairBf {
+    uint32_t hi[4];
+    uint32_t lo[4];
+};
+static_assert(sizeof(PairBf) == 32, "PairBf must be 32 bytes");
+
 // Geometry and flow constants passed by value to kernels.
 struct Flow {
     double M0, ca, sa, beta2, dtau, tau0;
@@ -72,6 +81,7 @@ struct SrcFwdArgs {
 
 struct GatherArgs {
     const PairRec *rec;
+    const PairBf *rbf;  // BF16 mode: [O][P] split weights (null in FP32 mode)
     const int2 *tw;
     const int32_t *nt;
     const void *coef;
@@ -164,7 +174,7 @@ hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hip
 // mode 0: FP64 tables (K64 [O][P][8], W64 [O][P][4], N0 [O][P]); mode 1/2: PairRec [O][P].
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, hipStream_t stream);
+                         int32_t *N0, PairRec *rec_op, PairBf *rbf, hipStream_t stream);
 
 // Per (observer tile t, panel p): lo/hi of n0 over the tile's observers -> tw[t][p];
 // per block of 256 (t, p) entries the largest hi - lo -> wblk[block].
@@ -227,13 +237,15 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
                                hipStream_t stream);
 // LDS-staged gather; NW = staged window length per channel group (multiple of 64, >= max
 // width + kLdsK + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
-inline size_t gather_lds_shmem(int coef_type, int NW, int PT) {
+// Per panel of a stage: both windows, the tile's records and, in BF16 mode, its split weights.
+inline size_t gather_lds_panel_bytes(int coef_type, int NW) {
     const size_t esz = coef_type == 1 ? 4 : 2;
-    return 2 * (size_t)PT * ((size_t)8 * NW * esz + (size_t)kObsTile * sizeof(PairRec));
+    return (size_t)8 * NW * esz + (size_t)kObsTile * (sizeof(PairRec) + (coef_type == 1 ? 0 : sizeof(PairBf)));
 }
-hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const int2 *tw, const int32_t *nt, const void *coef,
-                             int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW, int PT,
-                             double *partial, hipStream_t stream);
+inline size_t gather_lds_shmem(int coef_type, int NW, int PT) { return 2 * (size_t)PT * gather_lds_panel_bytes(coef_type, NW); }
+hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
+                             const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
+                             int PT, double *partial, hipStream_t stream);
 // out[i] = sum over splits of partial[z][i], fixed order, rounded to float.
 hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream);
 

@@ -78,14 +78,15 @@ __global__ __launch_bounds__(256) void minmax_kernel(const double *__restrict__ 
 // Eqs. (pT_WT_nd) + (pL_WT_nd), dS/(4 pi) included:
 //   Qdot:   1/(R om^2)                 Q:   (M_R - M0^2)/(M0 R^2 om^3)
 //   Ldot_i: M0 Rhat_i/(R om^2)         L_i: (Rhat_i - M_i)/(R^2 om^2) + Rhat_i (M_R - M0^2)/(R^2 om^3)
-// with om = 1 - M_R (the L_M term is L . M, Eq. (LM)).
+// with om = 1 - M_R (the L_M term is L . M, Eq. (LM)).  With rbf (BF16 mode)
+// the weights are also stored split into bfloat16 high and low parts.
 __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__restrict__ y,
                                                      const double *__restrict__ dS, const double *__restrict__ x_obs,
                                                      const double *__restrict__ t_start,
                                                      const int32_t *__restrict__ nt, int64_t P, int64_t O,
                                                      int64_t N, Flow f, double *__restrict__ K64,
                                                      double *__restrict__ W64, int32_t *__restrict__ N0,
-                                                     PairRec *__restrict__ rec_op) {
+                                                     PairRec *__restrict__ rec_op, PairBf *__restrict__ rbf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P * O) return;
     const int64_t o = i / P, p = i - o * P;
@@ -133,6 +134,24 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
         r.n0 = n0;
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
         rec_op[i] = r;
+        if (rbf) {
+            // bfloat16 by round-to-nearest-even of the FP32 value (weights are finite)
+            auto bf16 = [](double v) {
+                const uint32_t b = __float_as_uint((float)v);
+                return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+            };
+            PairBf q;
+            for (int c = 0; c < 4; ++c) {
+                uint32_t h[2], l[2];
+                for (int e = 0; e < 2; ++e) {
+                    h[e] = bf16(K[2 * c + e]);
+                    l[e] = bf16(K[2 * c + e] - (double)__uint_as_float(h[e] << 16));
+                }
+                q.hi[c] = h[0] | (h[1] << 16);
+                q.lo[c] = l[0] | (l[1] << 16);
+            }
+            rbf[i] = q;
+        }
     }
 }
 
@@ -189,10 +208,10 @@ hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hip
 
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, hipStream_t stream) {
+                         int32_t *N0, PairRec *rec_op, PairBf *rbf, hipStream_t stream) {
     const int64_t n = P * O;
     tables_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(mode, y, dS, x_obs, t_start, nt, P, O, N,
-                                                                            f, K64, W64, N0, rec_op);
+                                                                            f, K64, W64, N0, rec_op, rbf);
     return hipGetLastError();
 }
 
