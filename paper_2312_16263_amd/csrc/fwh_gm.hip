@@ -292,8 +292,16 @@ struct GmTraj {
     }
 };
 
+// Rows GA .. GMSQ (the 16 channels of the integrand) are staged per wave in LDS
+// over the wave's tap span: kGmSpan positions per row.
+constexpr int kGmStaged = GMSQ + 1;
+constexpr int kGmSpan = 96;
+typedef __attribute__((address_space(3))) void *gm_lds_ptr_t;
+
 __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
+    __shared__ double stage[4][kGmStaged][kGmSpan];
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nkb = a.nkb, O = a.O;
     if (wave >= (int64_t)a.splits * O * nkb) return;
@@ -303,6 +311,9 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int64_t k = (rem - o * nkb) * 64 + lane;
     const int64_t nt = a.n_t[o];
     const bool active = k < nt;
+    // last lane of the wave inside the window (the wave has none when it is negative: then every
+    // lane is ignored and lane 0's span is as good as any)
+    const int last_active = __builtin_amdgcn_readfirstlane((int)max((int64_t)0, min((int64_t)63, nt - 1 - (k - lane))));
     const double x0 = a.x_obs[3 * o], x1 = a.x_obs[3 * o + 1], x2 = a.x_obs[3 * o + 2];
     const double t = a.t_start[o] + (double)k * a.dtau;
     const int64_t N = a.N, NS = a.NS;
@@ -374,7 +385,35 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const int64_t j = gm_locate(tau, tau0, dtau, N, u);
         double w[4], dw[4];
         bspline_w(u, w, dw);
-        // next panel's guess and first Newton taps (issued with the channel taps)
+        // The active lanes' intervals do not decrease with the sample (subsonic motion), so their
+        // taps of one row span j(lane 0) .. j(last active lane) + 3 (lanes past the window keep an
+        // extrapolated guess and are ignored).  When that span fits kGmSpan positions,
+        // each of the 16 integrand rows is copied once into this wave's LDS rows by direct
+        // global -> LDS loads (16 bytes, two positions, per lane) instead of every lane loading its
+        // own four taps: a quarter of the vector-memory bytes.  (A copy may read one position past
+        // the row end: the next row, a trajectory row for the last one.)
+        const int jb = __builtin_amdgcn_readfirstlane((int)j);
+        const int span = __builtin_amdgcn_readlane((int)j, last_active) - jb + 4;
+        double cv[kGmStaged];
+        if (span <= kGmSpan) {
+            if (2 * lane < span) {
+#pragma unroll
+                for (int c = 0; c < kGmStaged; ++c)
+                    __builtin_amdgcn_global_load_lds((const void *)(cf + c * NS + jb + 2 * lane),
+                                                     (gm_lds_ptr_t)&stage[wv][c][0], 16, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed (each wave reads only its rows)
+            const int sl = active ? (int)j - jb : 0;
+#pragma unroll
+            for (int c = 0; c < kGmStaged; ++c) {
+                const double *q = &stage[wv][c][sl];
+                cv[c] = w[0] * q[0] + w[1] * q[1] + w[2] * q[2] + w[3] * q[3];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kGmStaged; ++c) cv[c] = gm_tap(cf + c * NS, j, w);
+        }
+        // next panel's guess and first Newton taps
         const double tau_next = p == pb ? tau : fmin(fmax(2.0 * tau - tau_prev, tau0), tmax);
         tau_prev = tau;
         if (p + 1 < pe) {
@@ -386,7 +425,7 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
         const double ir = 1.0 / r;
         const double h0 = r0 * ir, h1 = r1 * ir, h2 = r2 * ir;
-        auto ch = [&](int c) { return gm_tap(cf + c * NS, j, w); };
+        auto ch = [&](int c) { return cv[c]; };
         const double Mr = ch(GM1) * h0 + ch(GM2) * h1 + ch(GM3) * h2;
         const double Mdr = ch(GMD1) * h0 + ch(GMD2) * h1 + ch(GMD3) * h2;
         const double Lr = ch(GL1) * h0 + ch(GL2) * h1 + ch(GL3) * h2;
