@@ -32,13 +32,14 @@ FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: non-packed FP32 FMA 
 FP32_PACKED_PEAK = 157.3e12       # published FP32 vector peak (needs packed FP32 FMA)
 FLOP_PER_UNIT = 24                # 8 FMA channel combine + 4 FMA taps per (panel, observer, sample)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_dipole32768_f32.md")
+GM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_general_motion_orbit8192_f64.md")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, path=TRAFFIC_PROFILE):
     """HBM bytes per launch of `kernel` (read + written, copy-calibrated) from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             for line in f:
                 cells = [c.strip() for c in line.strip().strip("|").split("|")]
                 if len(cells) == 5 and cells[0].strip("`") == kernel:
@@ -46,6 +47,13 @@ def measured_traffic(kernel):
     except (OSError, ValueError):
         return None
     return None
+
+
+def gm_traffic():
+    """HBM bytes of one general-motion gather launch (gather + panel-range sum), or None."""
+    g = measured_traffic("gm_gather_kernel", GM_TRAFFIC_PROFILE)
+    r = measured_traffic("gm_reduce_kernel", GM_TRAFFIC_PROFILE)
+    return None if g is None or r is None else g + r
 
 
 def log(*a):
@@ -189,7 +197,8 @@ def bench_general_motion(steps, sync, profile_only=False):
            "roofline": {"bound": "alu", "kernel": "gm_gather_kernel + gm_reduce_kernel", "achieved": achieved,
                         "peak": 78.6432, "unit": "TFLOP/s", "frac": achieved / 78.6432,
                         "flop_per_unit": GM_FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": gat_ms,
-                        "traffic": None}}
+                        "traffic": gm_traffic(),
+                        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}}
     log(f"[bench] general motion: {ms:.2f} ms/forward (source {src_ms:.2f}, gather {gat_ms:.2f}), "
         f"{U / (ms * 1e-3):.3e} units/s, err vs oracle {err:.2e}, vs closed form {err_exact:.2e}")
     del plan, data, p
