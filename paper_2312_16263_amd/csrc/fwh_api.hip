@@ -832,7 +832,7 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     if (!pl) return fail(FWH_EINVAL, "fwh_gm_forward: null plan");
     if (!pl->ready) return fail(FWH_ESTATE, "fwh_gm_forward: no window computed");
     if (!rho || !u || !pp || !p_out) return fail(FWH_EINVAL, "fwh_gm_forward: null data pointer");
-    if ((int64_t)pl->splits * pl->a.n_obs * ((pl->n_t_max + 63) / 64) / 4 + 1 > (int64_t)INT32_MAX)
+    if ((int64_t)pl->splits * ((pl->a.n_obs + 3) / 4) * ((pl->n_t_max + 63) / 64) > (int64_t)INT32_MAX)
         return fail(FWH_ESIZE, "fwh_gm_forward: %lld observers x %lld samples exceed one launch",
                     (long long)pl->a.n_obs, (long long)pl->n_t_max);
     hipStream_t st = as_stream(stream_);

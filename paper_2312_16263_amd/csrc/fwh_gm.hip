@@ -31,6 +31,8 @@
 //     with the four B-spline taps (two contiguous 16-byte loads per channel and
 //     lane) and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi) in FP64.
 //     Panel ranges (splits) are summed by gm_reduce_kernel in fixed order.
+#include <climits>
+
 #include "fwh_internal.h"
 
 namespace fwh {
@@ -292,28 +294,34 @@ struct GmTraj {
     }
 };
 
-// Rows GA .. GMSQ (the 16 channels of the integrand) are staged per wave in LDS
-// over the wave's tap span: kGmSpan positions per row.
+// Rows GA .. GMSQ (the 16 channels of the integrand) are staged per block in LDS
+// over the block's tap span: kGmSpanB positions per row, two buffers.
 constexpr int kGmStaged = GMSQ + 1;
-constexpr int kGmSpan = 96;
+constexpr int kGmSpanB = 152;  // two buffers of 16 rows: 38 KB, four blocks per compute unit
 typedef __attribute__((address_space(3))) void *gm_lds_ptr_t;
 
+// Block = 4 waves = observers 4 og .. 4 og + 3 (wave wv: observer 4 og + wv), the same 64 samples
+// k0 .. k0 + 63 and panel range; logical blocks run with the observer group fastest, regrouped per XCD.
 __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
-    __shared__ double stage[4][kGmStaged][kGmSpan];
+    __shared__ double stage[2][kGmStaged][kGmSpanB];
+    __shared__ int span_lo[4], span_hi[4];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nkb = a.nkb, O = a.O;
-    if (wave >= (int64_t)a.splits * O * nkb) return;
-    const int64_t z = wave / (O * nkb);
-    const int64_t rem = wave - z * O * nkb;
-    const int64_t o = rem / nkb;
-    const int64_t k = (rem - o * nkb) * 64 + lane;
-    const int64_t nt = a.n_t[o];
+    const int64_t ngrp = (O + 3) / 4;
+    const int64_t L = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t og = L % ngrp, rest = L / ngrp;
+    const int64_t kb = rest % nkb, z = rest / nkb;
+    // a wave past the last observer runs along (it meets every barrier) on observer O - 1 with
+    // every lane outside the window, and writes nothing
+    const bool obs_ok = og * 4 + wv < O;
+    const int64_t o = obs_ok ? og * 4 + wv : O - 1;
+    const int64_t k = kb * 64 + lane;
+    const int64_t nt = obs_ok ? a.n_t[o] : 0;
     const bool active = k < nt;
-    // last lane of the wave inside the window (the wave has none when it is negative: then every
-    // lane is ignored and lane 0's span is as good as any)
-    const int last_active = __builtin_amdgcn_readfirstlane((int)max((int64_t)0, min((int64_t)63, nt - 1 - (k - lane))));
+    const bool wave_active = nt > kb * 64;
+    // last lane of the wave inside the window
+    const int last_active = __builtin_amdgcn_readfirstlane((int)max((int64_t)0, min((int64_t)63, nt - 1 - kb * 64)));
     const double x0 = a.x_obs[3 * o], x1 = a.x_obs[3 * o + 1], x2 = a.x_obs[3 * o + 2];
     const double t = a.t_start[o] + (double)k * a.dtau;
     const int64_t N = a.N, NS = a.NS;
@@ -323,8 +331,8 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
     const int64_t pb = z * a.p_chunk;
     const int64_t pe = min(pb + a.p_chunk, a.P);
     double acc = 0.0;
-    if (pb >= pe) {
-        if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = 0.0;
+    if (pb >= pe) {  // block-uniform
+        if (obs_ok && k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = 0.0;
         return;
     }
     // first panel of the range: start from the emission time of frame 0's position
@@ -335,7 +343,7 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         tau = fmin(fmax(t - M0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2), tau0), tmax);
     }
     // taps of the current panel at the current guess (loaded ahead: for the next panel they are
-    // fetched together with this panel's channel taps); the guess for the next panel extrapolates
+    // fetched after this panel's channel taps); the guess for the next panel extrapolates
     // the retarded times of the last two panels (neighbouring panels are visited in order)
     double tau_prev = 0.0;
     GmTraj tr;
@@ -345,7 +353,8 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const double *cf = a.coef + pb * kGmRows * NS;
         tr.load(cf + GY1 * NS, cf + GY2 * NS, cf + GY3 * NS, j);
     }
-    for (int64_t p = pb; p < pe; ++p) {
+    int buf = 0;
+    for (int64_t p = pb; p < pe; ++p, buf ^= 1) {
         const double *cf = a.coef + p * kGmRows * NS;
         const double *ry0 = cf + GY1 * NS, *ry1 = cf + GY2 * NS, *ry2 = cf + GY3 * NS;
         // Newton on g(tau) = tau + M0 |x - Y(tau)| - t, g' = 1 - M0 rhat . Y'(tau); the first step
@@ -385,28 +394,42 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         const int64_t j = gm_locate(tau, tau0, dtau, N, u);
         double w[4], dw[4];
         bspline_w(u, w, dw);
-        // The active lanes' intervals do not decrease with the sample (subsonic motion), so their
-        // taps of one row span j(lane 0) .. j(last active lane) + 3 (lanes past the window keep an
-        // extrapolated guess and are ignored).  When that span fits kGmSpan positions,
-        // each of the 16 integrand rows is copied once into this wave's LDS rows by direct
-        // global -> LDS loads (16 bytes, two positions, per lane) instead of every lane loading its
-        // own four taps: a quarter of the vector-memory bytes.  (A copy may read one position past
-        // the row end: the next row, a trajectory row for the last one.)
-        const int jb = __builtin_amdgcn_readfirstlane((int)j);
-        const int span = __builtin_amdgcn_readlane((int)j, last_active) - jb + 4;
+        // The active lanes' intervals do not decrease with the sample (subsonic motion), so a wave's
+        // taps of one row span j(lane 0) .. j(last active lane) + 3, and the block's observers, a few
+        // degrees apart, have overlapping spans.  When the block's span fits kGmSpanB positions, each
+        // of the 16 integrand rows is copied once for the block into LDS by direct global -> LDS loads
+        // (16 bytes, two positions, per lane; wave wv copies rows wv, wv + 4, ...) instead of every lane
+        // loading its own four taps.  (A copy may read one position past the row end: the next row,
+        // a trajectory row for the last one.)  The copies of the next panel go to the other buffer:
+        // every wave has read this one before it reaches the next panel's first barrier.
+        if (lane == 0) {
+            span_lo[wv] = wave_active ? (int)j : INT_MAX;
+            span_hi[wv] = wave_active ? __builtin_amdgcn_readlane((int)j, last_active) : INT_MIN;
+        }
+        __syncthreads();
+        int lo = min(min(span_lo[0], span_lo[1]), min(span_lo[2], span_lo[3]));
+        int hi = max(max(span_hi[0], span_hi[1]), max(span_hi[2], span_hi[3]));
+        if (lo > hi) lo = hi = 0;  // no lane of the block is inside its window
+        const int span = hi - lo + 4;
         double cv[kGmStaged];
-        if (span <= kGmSpan) {
-            if (2 * lane < span) {
+        if (span <= kGmSpanB) {  // block-uniform
 #pragma unroll
-                for (int c = 0; c < kGmStaged; ++c)
-                    __builtin_amdgcn_global_load_lds((const void *)(cf + c * NS + jb + 2 * lane),
-                                                     (gm_lds_ptr_t)&stage[wv][c][0], 16, 0, 0);
+            for (int rr = 0; rr < kGmStaged / 4; ++rr) {
+                const int c = wv + 4 * rr;
+                const double *row = cf + c * NS + lo;
+                if (2 * lane < span)
+                    __builtin_amdgcn_global_load_lds((const void *)(row + 2 * lane), (gm_lds_ptr_t)&stage[buf][c][0], 16,
+                                                     0, 0);
+                if (2 * lane + 128 < span)
+                    __builtin_amdgcn_global_load_lds((const void *)(row + 128 + 2 * lane),
+                                                     (gm_lds_ptr_t)&stage[buf][c][128], 16, 0, 0);
             }
-            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed (each wave reads only its rows)
-            const int sl = active ? (int)j - jb : 0;
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed ...
+            __syncthreads();                // ... and every wave's
+            const int sl = active ? (int)j - lo : 0;
 #pragma unroll
             for (int c = 0; c < kGmStaged; ++c) {
-                const double *q = &stage[wv][c][sl];
+                const double *q = &stage[buf][c][sl];
                 cv[c] = w[0] * q[0] + w[1] * q[1] + w[2] * q[2] + w[3] * q[3];
             }
         } else {
@@ -438,7 +461,7 @@ __global__ __launch_bounds__(256) void gm_gather_kernel(GmGatherArgs a) {
         if (active) acc += F * a.dS[p];
         tau = tau_next;
     }
-    if (k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = active ? acc * (1.0 / (4.0 * kPiD)) : 0.0;
+    if (obs_ok && k < a.nt_stride) a.part[(z * O + o) * a.nt_stride + k] = active ? acc * (1.0 / (4.0 * kPiD)) : 0.0;
 }
 
 __global__ __launch_bounds__(256) void gm_reduce_kernel(const double *__restrict__ part, int splits, int64_t n,
@@ -469,8 +492,8 @@ hipError_t launch_gm_window(const GmWinArgs &a, hipStream_t stream) {
 }
 
 hipError_t launch_gm_gather(const GmGatherArgs &a, double *out, hipStream_t stream) {
-    const int64_t waves = (int64_t)a.splits * a.O * a.nkb;
-    gm_gather_kernel<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream>>>(a);
+    const int64_t blocks = (int64_t)a.splits * a.nkb * ((a.O + 3) / 4);
+    gm_gather_kernel<<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = a.O * a.nt_stride;

@@ -66,6 +66,16 @@ constexpr int kMaxPanelsPerStage = 8;
 
 
 // ------------------------------------------------------- per-stage arguments
+// Workgroups are dispatched round-robin over the 8 XCDs (block h to XCD h mod 8),
+// each with its own L2.  xcd_block(h, n) renumbers them so that XCD x runs the
+// consecutive logical blocks [start(x), start(x) + count(x)): neighbouring
+// logical blocks, which read the same panels' data, share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t h, int64_t n) {
+    const int64_t x = h % kXcds, s = h / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // Every stage kernel is a body taking one of these; the single-case kernels
 // pass them by value, the batched kernels pick them from a per-case array.
 
