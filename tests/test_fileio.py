@@ -343,3 +343,58 @@ def test_case_consistency_errors(tmp_path):
     _expect(fileio.FWH_IO_EFORMAT, fileio.load_case, d, match="mach")
     open(os.path.join(d, "control.fwh"), "w").write(ctl)
     assert fileio.load_case(d, frames=False).rho is None
+
+
+def test_every_truncation_and_length_corruption_is_an_error(tmp_path):
+    """Every prefix of a valid binary frame, and the frame with any one byte of
+    a record length changed, is rejected with FWH_IO_EFORMAT (never a crash or
+    a silent read)."""
+    dims = np.array([[2, 1, 1], [1, 1, 3]], dtype=np.int64)
+    v = np.arange(25, dtype=np.float64).reshape(5, 5) + 0.5
+    d = str(tmp_path)
+    p = fileio.frame_path(d, 0)
+    fileio.write_frame(p, fileio.BINARY, dims, v[0], v[1:4], v[4])
+    good = open(p, "rb").read()
+    for n in range(len(good)):
+        open(p, "wb").write(good[:n])
+        _expect(fileio.FWH_IO_EFORMAT, fileio.read_frames, d, 0, 1, 1, fileio.BINARY, dims)
+    # record length words: 4 per Face (head and tail of the dimension and value records)
+    offsets, o = [], 0
+    for face in dims:
+        m = int(np.prod(face))
+        offsets += [o, o + 16, o + 20, o + 24 + 40 * m]
+        o += 28 + 40 * m
+    assert o == len(good)
+    for off in offsets:
+        for byte in range(4):
+            bad = bytearray(good)
+            bad[off + byte] ^= 0x41
+            open(p, "wb").write(bytes(bad))
+            _expect(fileio.FWH_IO_EFORMAT, fileio.read_frames, d, 0, 1, 1, fileio.BINARY, dims)
+    open(p, "wb").write(good)
+    rho, u, pp = fileio.read_frames(d, 0, 1, 1, fileio.BINARY, dims)
+    np.testing.assert_array_equal(pp[0], v[4])
+
+
+def test_every_truncation_of_text_files_is_an_error_or_a_prefix(tmp_path):
+    """Cutting the geometry file anywhere inside its numbers gives FWH_IO_EFORMAT;
+    cutting an observer file at a line end reads the lines before it."""
+    g = os.path.join(GOLDEN, "FWH_Surface_Geo.dat")
+    text = open(g).read()
+    p = str(tmp_path / "g.dat")
+    end_of_data = len(text.rstrip())
+    for n in range(len(text.split("\n", 1)[0]) + 1, end_of_data):
+        open(p, "w").write(text[:n])
+        try:
+            geom = fileio.read_geometry(p)
+        except fileio.FwhIOError as e:
+            assert e.code == fileio.FWH_IO_EFORMAT
+        else:
+            # a cut inside the last number still parses a shorter number: the count must be complete
+            assert geom.n_panels == 5 and n > len(text) - 12
+    obs = open(os.path.join(GOLDEN, "observers.dat")).read()
+    q = str(tmp_path / "o.dat")
+    for n in [i + 1 for i, ch in enumerate(obs) if ch == "\n"]:
+        open(q, "w").write(obs[:n])
+        x = fileio.read_observers(q)
+        assert x.shape[0] == sum(1 for ln in obs[:n].splitlines() if ln.strip())
