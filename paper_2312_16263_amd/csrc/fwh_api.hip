@@ -277,7 +277,9 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         for (int32_t w : wblk) wmax = w > wmax ? w : wmax;
         const size_t esz = pl->mode == FWH_MODE_F32 ? sizeof(float) : sizeof(uint16_t);
         // window length per channel group: a multiple of 64 elements (whole wave-wide direct loads)
-        const int nw = ((wmax + fwh::kLdsK + fwh::kLdsHalo + 63) / 64) * 64;
+        // (BF16: a multiple of 128, two elements per 16-byte copy unit)
+        const int nwq = pl->mode == FWH_MODE_F32 ? 64 : 128;
+        const int nw = ((wmax + fwh::kLdsK + fwh::kLdsHalo + nwq - 1) / nwq) * nwq;
         // two stage buffers of PT panels: windows of both groups plus the tile's pair records
         int64_t pt = (int64_t)(fwh::kLdsBudget / (2 * fwh::gather_lds_panel_bytes(esz == sizeof(float) ? 1 : 2, nw)));
         if (pt > fwh::kMaxPanelsPerStage) pt = fwh::kMaxPanelsPerStage;

@@ -193,18 +193,17 @@ struct Quad<uint16_t> {
 
 // Element of a staged window: the 4 channels of one group at one time index
 // (16 bytes in FP32, 8 bytes in BF16); copied to LDS by direct global->LDS loads
-// of 16 bytes (FP32) or 4 bytes (BF16) per lane.
+// of 16 bytes per lane: one element (FP32) or two (BF16; the staged window
+// length is then a multiple of 128 elements, so a group is whole 64-lane copies).
 template <typename TS>
 struct Stage;
 template <>
 struct Stage<float> {
-    static constexpr int kBytesPerLoad = 16;  // one element per lane
-    static constexpr int kElemPerLoad = 1;
+    static constexpr int kElemPerUnit = 1;
 };
 template <>
 struct Stage<uint16_t> {
-    static constexpr int kBytesPerLoad = 4;   // half an element per lane
-    static constexpr int kElemPerLoad = 2;
+    static constexpr int kElemPerUnit = 2;
 };
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
@@ -276,13 +275,16 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         for (int q = 0; q < np; ++q) {
             const int64_t p = ps + q;
             const int64_t start = (int64_t)twt[p].x + k0;
-            const int units = NW * Stage<TS>::kElemPerLoad;
+            constexpr int EU = Stage<TS>::kElemPerUnit;
+            const int units = NW / EU;
             for (int g = 0; g < 2; ++g) {
                 const unsigned char *src =
                     reinterpret_cast<const unsigned char *>(coef + ((p * 2 + g) * NS + start) * 4);
-                // units past the row end are clamped to its last unit (never read by valid outputs)
-                const int64_t last = (NS - start) * Stage<TS>::kElemPerLoad - 1;
-                copy_to_lds<Stage<TS>::kBytesPerLoad>(src, last, base + q * win_bytes + g * NW * EB, units, wv, lane);
+                // units past the row end are clamped to its last unit (never read by valid outputs; in
+                // BF16 a last unit may take one element of the next row, or of the region after the
+                // coefficients, which are never read either)
+                const int64_t last = (NS - start + EU - 1) / EU - 1;
+                copy_to_lds<16>(src, last, base + q * win_bytes + g * NW * EB, units, wv, lane);
             }
         }
         // records: for panel q, observer j of the tile -> 64 bytes at [q][j]
