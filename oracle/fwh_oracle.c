@@ -18,7 +18,7 @@
  *                       at the observer times
  *   surface sum      -> sum over panels.
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent:
  *   - the surface Mach vector in the Garrick frame is M = -M0*U0hat (the surface
  *     moves against the mean flow), so M^2 = M0^2 and L_M = -M0 L.U0hat;
  *   - rho and u are full values, the pressure input is the pulsation p - p0;
