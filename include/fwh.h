@@ -44,8 +44,9 @@
  * untouched by the caller until fwh_destroy.
  *
  * Streams.  `stream` is a hipStream_t (0 = legacy default stream); all work is
- * enqueued on it.  fwh_setup synchronises `stream` once (it reads two doubles
- * per observer back to size the observer window).  fwh_forward and
+ * enqueued on it.  fwh_setup synchronises `stream`: it reads two doubles per
+ * observer back to size the observer window and, in the FP32/BF16 modes, the
+ * per-tile window widths to size the gather's LDS staging.  fwh_forward and
  * fwh_adjoint do not synchronise.  Forward and adjoint calls on one plan share
  * workspace regions (coefficients and scratch), so the caller must order all
  * calls on one plan (one stream, or events between streams); plans with
