@@ -313,6 +313,21 @@ def bench_ingest(sync, n_frames=256, n_ascii=8, threads=16):
                         "read_plus_h2d_panel_frames_per_s": nf * P / (t_read + t_h2d)}
             log(f"[bench] ingest {key}: {nf} frames, {nbytes / 1e6:.1f} MB read in {t_read * 1e3:.1f} ms "
                 f"({nbytes / t_read / 1e9:.2f} GB/s), H2D {arr / t_h2d / 1e9:.1f} GB/s")
+            if fmt == fileio.BINARY:
+                # files -> device in blocks of 128 frames, parsing overlapped with the copies
+                fileio.read_frames_to_device(d, 0, 1, nf, fmt, dims, dtype="f64", block=128, threads=threads)
+                sync()
+                t0 = time.perf_counter()
+                dv = fileio.read_frames_to_device(d, 0, 1, nf, fmt, dims, dtype="f64", block=128, threads=threads)
+                sync()
+                t_st = time.perf_counter() - t0
+                assert torch.equal(dv[0].cpu(), host[0])
+                out[key]["streamed_to_device_s"] = t_st
+                out[key]["streamed_panel_frames_per_s"] = nf * P / t_st
+                out[key]["streamed_file_GB_per_s"] = nbytes / t_st / 1e9
+                log(f"[bench] ingest {key} streamed to HBM (blocks of 128 frames): {t_st * 1e3:.1f} ms "
+                    f"({nbytes / t_st / 1e9:.2f} GB/s of file)")
+                del dv
             for k in range(nf):
                 os.remove(fileio.frame_path(d, k))
             del dev, host

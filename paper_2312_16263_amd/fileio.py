@@ -277,6 +277,53 @@ def read_frames(directory, kstep_start: int, delta_step: int, n_frames: int, fmt
     return rho, u, pp
 
 
+def read_frames_to_device(directory, kstep_start: int, delta_step: int, n_frames: int, fmt: int, face_dims,
+                          dtype: str = "f32", device="cuda", block: int = 128, threads: int = 0):
+    """Reads n_frames dataset files straight into time-major device tensors
+    (rho [N][P], u [3][N][P], pp [N][P]) in blocks of `block` frames: each block
+    is parsed by the library's reader threads into one of two page-locked
+    buffers while the previous block is copied to the device on a side stream.
+    Host memory stays at two blocks whatever the record length, for records
+    larger than the host can pin.  Returns after the copies are ordered before
+    later work on the current stream."""
+    import torch
+    dims = np.ascontiguousarray(face_dims, dtype=np.int64)
+    P = int(np.prod(dims, axis=1).sum())
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dtype]
+    dev = torch.device(device)
+    rho = torch.empty((n_frames, P), dtype=tdt, device=dev)
+    u = torch.empty((3, n_frames, P), dtype=tdt, device=dev)
+    pp = torch.empty((n_frames, P), dtype=tdt, device=dev)
+    block = max(1, min(block, n_frames))
+    bufs = [(torch.empty(block * P, dtype=tdt, pin_memory=True), torch.empty(3 * block * P, dtype=tdt, pin_memory=True),
+             torch.empty(block * P, dtype=tdt, pin_memory=True)) for _ in range(2)]
+    done = [None, None]
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))  # the outputs' allocation is ordered before the copies
+    for bi, k0 in enumerate(range(0, n_frames, block)):
+        nb = min(block, n_frames - k0)
+        rb, ub, pb = bufs[bi % 2]
+        if done[bi % 2] is not None:
+            done[bi % 2].synchronize()  # this buffer's previous copy has finished
+        views = (rb[:nb * P].view(nb, P), ub[:3 * nb * P].view(3, nb, P), pb[:nb * P].view(nb, P))
+        read_frames(directory, kstep_start + k0 * delta_step, delta_step, nb, fmt, dims, dtype=dtype, out=views,
+                    threads=threads)
+        with torch.cuda.stream(side):
+            rho[k0:k0 + nb].copy_(views[0], non_blocking=True)
+            for c in range(3):
+                u[c, k0:k0 + nb].copy_(views[1][c], non_blocking=True)
+            pp[k0:k0 + nb].copy_(views[2], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(side)
+        done[bi % 2] = ev
+    torch.cuda.current_stream(dev).wait_stream(side)
+    # the pinned buffers must outlive their copies
+    for ev in done:
+        if ev is not None:
+            ev.synchronize()
+    return rho, u, pp
+
+
 # ----------------------------------------------------------------- whole case
 @dataclass
 class Case:
@@ -315,10 +362,12 @@ class Case:
                     mode=mode, device=device)
 
 
-def load_case(directory, dtype: str = "f64", threads=None, pinned: bool = False, frames: bool = True) -> Case:
+def load_case(directory, dtype: str = "f64", threads=None, pinned: bool = False, frames: bool = True,
+              device=None) -> Case:
     """Reads control.fwh, FWH_Surface_Geo.dat, observers.dat and the dataset
     files of `directory`.  pinned=True reads the frames into page-locked torch
-    host tensors (ready for an asynchronous copy to the device)."""
+    host tensors (ready for an asynchronous copy to the device); device="cuda"
+    streams them into device tensors (read_frames_to_device)."""
     ctl = read_control(os.path.join(directory, CONTROL_FILE))
 
     def need(name):
@@ -344,6 +393,11 @@ def load_case(directory, dtype: str = "f64", threads=None, pinned: bool = False,
     if frames:
         if threads is None:
             threads = int(control_value(ctl, "threads", 0))
+        if device is not None:
+            case.rho, case.u, case.pp = read_frames_to_device(directory, case.kstep_start, case.delta_step,
+                                                              case.n_frames, case.fmt, geom.face_dims, dtype=dtype,
+                                                              device=device, threads=threads)
+            return case
         out = None
         if pinned:
             import torch

@@ -53,3 +53,26 @@ def test_case_from_files_matches_direct_arrays(tmp_path, fmt, mode):
     err = rel_l2(p, p_ref, m)
     print(f"    rel L2 vs oracle = {err:.3e} (tol {TOL[mode]:.0e})", flush=True)
     assert err <= TOL[mode], err
+
+
+@pytest.mark.parametrize("fmt,block", [(fileio.BINARY, 7), (fileio.ASCII, 64)])
+def test_frames_streamed_to_device(tmp_path, fmt, block):
+    """Blocks of frames parsed into two page-locked buffers while the previous
+    block is copied: the device tensors equal the host read, bit for bit
+    (ragged last block with block = 7)."""
+    import torch
+    c = _case()
+    rho, u, pp = c.data()
+    dims = np.array([[6, 24, 1], [1, 3, 24], [3, 1, 24]], dtype=np.int64)
+    geom = fileio.Geometry(dims, c.surface.y, c.surface.normal, c.surface.dS)
+    d = str(tmp_path / "case")
+    fileio.save_case(d, c.mach, c.aoa_deg, c.dtau, 0, 1, geom, c.x_obs, rho, u, pp, fmt=fmt)
+    for dtype in ("f64", "f32"):
+        fc = fileio.load_case(d, dtype=dtype, device="cuda", threads=3)
+        torch.cuda.synchronize()
+        ref = fileio.load_case(d, dtype=dtype)
+        for dev_t, host in zip((fc.rho, fc.u, fc.pp), (ref.rho, ref.u, ref.pp)):
+            assert dev_t.is_cuda
+            np.testing.assert_array_equal(dev_t.cpu().numpy(), host)
+        out = fileio.read_frames_to_device(d, 0, 1, c.n_tau, fmt, dims, dtype=dtype, block=block)
+        np.testing.assert_array_equal(out[1].cpu().numpy(), ref.u)
