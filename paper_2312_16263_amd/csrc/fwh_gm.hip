@@ -22,15 +22,18 @@
 //     M0 |x - y_p(tau_0)|], t_end = min_p [tau_{N-1} + M0 |x - y_p(tau_{N-1})|],
 //     N_t = floor((t_end - t_start)/dtau + 1e-9) + 1 (-1 for an empty window).
 //  4. gm_gather_kernel: a wave owns (observer, 64 consecutive samples, panel
-//     range); per panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton
-//     steps on the splined trajectory (started from the linear extrapolation of
-//     its solutions for the two previous panels; a step below 1e-6 dtau is accepted without a further
-//     check, the iteration being quadratic, and the position at tau_ret is the
-//     last evaluation advanced by that step; the next panel's first taps are
-//     fetched together with this panel's channel taps), evaluates the channels at tau_ret
-//     with the four B-spline taps (two contiguous 16-byte loads per channel and
-//     lane) and adds the integrand of Eqs. (pT) + (pL) times dS/(4 pi) in FP64.
-//     Panel ranges (splits) are summed by gm_reduce_kernel in fixed order.
+//     range), a block four neighbouring observers at the same samples; per
+//     panel each lane solves tau + M0 |x - Y(tau)| = t_k by Newton steps on the
+//     splined trajectory (started from the linear extrapolation of its
+//     solutions for the two previous panels; a step below 1e-6 dtau is accepted
+//     without a further check, the iteration being quadratic, and the position
+//     at tau_ret is the last evaluation advanced by that step; the next panel's
+//     first taps are fetched after this panel's channel taps), evaluates the 16
+//     integrand channels at tau_ret with the four B-spline taps, read from rows
+//     the block copies once into LDS over its joint tap span (each lane loads
+//     its own taps when the span is too wide), and adds the integrand of
+//     Eqs. (pT) + (pL) times dS/(4 pi) in FP64.  Panel ranges (splits) are
+//     summed by gm_reduce_kernel in fixed order.
 #include <climits>
 
 #include "fwh_internal.h"
