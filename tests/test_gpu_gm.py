@@ -135,3 +135,32 @@ def test_gm_fullsize_sampled():
     got = p[so, sk]
     err = np.abs(got - ref).max() / np.abs(ref).max()
     assert err < TOL, err
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gm_random_cases(seed):
+    """Seeded random motions (translation up to surface Mach 0.6, orbit, oscillation with spin),
+    sphere sizes, record lengths, tau0 and observer placements."""
+    rng = np.random.default_rng(500 + seed)
+    nt_ = int(rng.integers(3, 9))
+    body = surfaces.sphere(float(rng.uniform(0.6, 1.4)), nt_, 2 * nt_, center=tuple(rng.uniform(-0.3, 0.3, 3)))
+    M0 = float(rng.uniform(0.1, 0.5))
+    dtau = float(rng.choice([1 / 32, 1 / 64, 1 / 100]))
+    N = int(rng.integers(150, 400))
+    tau0 = float(rng.uniform(-1.0, 1.0))
+    kind = ["translate", "orbit", "oscillate"][seed % 3]
+    kw = {"translate": dict(velocity=tuple(rng.uniform(-1.0, 1.0, 3) * 0.6 / M0 / np.sqrt(3))),
+          "orbit": dict(spin=float(rng.uniform(0.2, 1.0))),
+          "oscillate": dict(spin=float(rng.uniform(0.0, 0.6)), amplitude=float(rng.uniform(0.1, 0.4)),
+                            omega_m=float(rng.uniform(0.5, 3.0)))}[kind]
+    ms = motion.moving_surface(body, kind, N, dtau, tau0, **kw)
+    rho, u, pp = motion.quiescent_monopole_series(ms, M0, 4 * math.pi * 1e-3, float(rng.uniform(1.0, 8.0)), dtau,
+                                                  tau0, source=tuple(rng.uniform(-0.1, 0.1, 3)))
+    O = int(rng.integers(1, 10))
+    x = rng.normal(size=(O, 3))
+    x *= (rng.uniform(8.0, 30.0, O) / np.linalg.norm(x, axis=1))[:, None]
+    print(f"[gm random] seed={seed} {kind} P={ms.n_panels} N={N} O={O} M0={M0:.2f}", flush=True)
+    plan, p = _run_gpu(ms, x, M0, dtau, tau0, rho, u, pp)
+    ref, ts, nt = oracle.gm_forward(ms, x, M0, dtau, tau0, rho, u, pp)
+    np.testing.assert_array_equal(plan.window.n_t, nt)
+    assert np.abs(p - ref).max() / np.abs(ref).max() < TOL
