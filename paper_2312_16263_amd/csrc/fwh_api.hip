@@ -288,17 +288,25 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         const char *force = std::getenv("FWH_FORCE_DIRECT_GATHER");  // test hook: exercise the direct-load gather
         if (force && force[0] == '1') pl->lds_pt = 0;
     }
-    // panel splits of the tuned gathers: enough workgroups to fill 256 CUs a few times over
+    // panel splits of the tuned gathers.  A split's block takes P/s panels, so a launch of B*s blocks
+    // on R resident blocks (2 per CU) lasts about ceil(B*s/R)/s block-times of the unsplit work.  Among
+    // the s (at most kMaxPanelSplits, at least 256 panels per split) within 3 % of its minimum, take
+    // the largest that keeps B*s within 8 rounds: whole rounds (no last round that leaves most CUs
+    // idle), and enough of them that blocks of unequal work even out
     int64_t blocks;
     if (pl->lds_pt > 0)
         blocks = ((O + fwh::kObsTile - 1) / fwh::kObsTile) * ((pl->n_t_max + fwh::kLdsK - 1) / fwh::kLdsK);
     else
         blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
                  ((pl->n_t_max + fwh::kGatherK - 1) / fwh::kGatherK);
-    int64_t s = (2048 + blocks - 1) / blocks;
-    if (s > fwh::kMaxPanelSplits) s = fwh::kMaxPanelSplits;
-    if (s > (P + 255) / 256) s = (P + 255) / 256;
-    if (s < 1) s = 1;
+    const int64_t resident = 2 * 256;
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + 255) / 256));
+    auto rounds = [&](int64_t c) { return (double)((blocks * c + resident - 1) / resident) / (double)c; };
+    double best = 1e300;
+    for (int64_t c = 1; c <= smax; ++c) best = std::min(best, rounds(c));
+    int64_t s = 1;
+    for (int64_t c = 1; c <= smax; ++c)
+        if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 8 * resident)) s = c;
     pl->splits = (int)s;
     pl->ready = true;
     return FWH_OK;
