@@ -754,11 +754,20 @@ int fwh_gm_plan_create(const fwh_gm_args *a, fwh_gm_plan **out, size_t *workspac
         c = 1.0 / (4.0 - c);
         pl->inv_beta[n] = c;
     }
-    // panel splits: about 16384 waves of (observer, 64 samples, panel range)
+    // panel splits: blocks of 4 observers x 64 samples x panel range (the record length stands in for
+    // the window), 4 resident per CU.  As for the wind-tunnel gather, among the split counts within
+    // 3 % of the fewest rounds per unit of work take the largest that keeps the launch within 8
+    // rounds (at most 1024 splits, at least 16 panels each)
     const int64_t nkb = (N + 63) / 64;
-    int64_t sp = (16384 + O * nkb - 1) / (O * nkb);
-    sp = std::max<int64_t>(1, std::min<int64_t>(sp, std::max<int64_t>(1, P / 16)));
-    pl->splits = (int)std::min<int64_t>(sp, 1024);
+    const int64_t gblocks = nkb * ((O + 3) / 4), gres = 4 * 256;
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(1024, P / 16));
+    auto grounds = [&](int64_t c) { return (double)((gblocks * c + gres - 1) / gres) / (double)c; };
+    double gbest = 1e300;
+    for (int64_t c = 1; c <= smax; ++c) gbest = std::min(gbest, grounds(c));
+    int64_t sp = 1;
+    for (int64_t c = 1; c <= smax; ++c)
+        if (grounds(c) <= gbest * 1.03 && (c == 1 || gblocks * c <= 8 * gres)) sp = c;
+    pl->splits = (int)sp;
     pl->p_chunk = (P + pl->splits - 1) / pl->splits;
     size_t off = 0;
     auto take = [&](size_t bytes) {
