@@ -280,16 +280,25 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         // (BF16: a multiple of 128, two elements per 16-byte copy unit)
         const int nwq = pl->mode == FWH_MODE_F32 ? 64 : 128;
         const int nw = ((wmax + fwh::kLdsK + fwh::kLdsHalo + nwq - 1) / nwq) * nwq;
-        // two stage buffers of PT panels: windows of both groups plus the tile's pair records
-        int64_t pt = (int64_t)(fwh::kLdsBudget / (2 * fwh::gather_lds_panel_bytes(esz == sizeof(float) ? 1 : 2, nw)));
+        // two stage buffers of PT panels: windows of both groups plus the tile's pair records (and,
+        // in BF16, split weights), at most kLdsBudget; the largest PT that keeps as many blocks per CU
+        // resident as a one-panel stage (more waves in flight hide the staging latency better than
+        // longer stages)
+        const int ctype = esz == sizeof(float) ? 1 : 2;
+        int64_t pt = (int64_t)(fwh::kLdsBudget / (2 * fwh::gather_lds_panel_bytes(ctype, nw)));
         if (pt > fwh::kMaxPanelsPerStage) pt = fwh::kMaxPanelsPerStage;
+        if (pt > 1) {
+            const int occ1 = fwh::gather_lds_blocks_per_cu(ctype, nw, 1);
+            while (pt > 1 && fwh::gather_lds_blocks_per_cu(ctype, nw, (int)pt) < occ1) --pt;
+        }
         pl->lds_nw = nw;
         pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit: the direct-load gather is used
         const char *force = std::getenv("FWH_FORCE_DIRECT_GATHER");  // test hook: exercise the direct-load gather
         if (force && force[0] == '1') pl->lds_pt = 0;
     }
     // panel splits of the tuned gathers.  A split's block takes P/s panels, so a launch of B*s blocks
-    // on R resident blocks (2 per CU) lasts about ceil(B*s/R)/s block-times of the unsplit work.  Among
+    // on R resident blocks (the LDS gather's occupancy at its staging size times the CU count; 2 per
+    // CU for the direct-load gather) lasts about ceil(B*s/R)/s block-times of the unsplit work.  Among
     // the s (at most kMaxPanelSplits, at least 256 panels per split) within 3 % of its minimum, take
     // the largest that keeps B*s within 8 rounds: whole rounds (no last round that leaves most CUs
     // idle), and enough of them that blocks of unequal work even out
@@ -299,7 +308,13 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     else
         blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
                  ((pl->n_t_max + fwh::kGatherK - 1) / fwh::kGatherK);
-    const int64_t resident = 2 * 256;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
+        return hip_fail("fwh_setup: device query", e);
+    const int64_t resident =
+        (int64_t)cus * (pl->lds_pt > 0 ? fwh::gather_lds_blocks_per_cu(pl->mode == FWH_MODE_F32 ? 1 : 2, pl->lds_nw,
+                                                                       pl->lds_pt)
+                                       : 2);
     const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + 255) / 256));
     auto rounds = [&](int64_t c) { return (double)((blocks * c + resident - 1) / resident) / (double)c; };
     double best = 1e300;

@@ -92,6 +92,9 @@ __device__ __forceinline__ float from_next_lane(float x) {
 }
 
 constexpr int kChunk = 64;  // panels summed in FP32 before adding into the FP64 accumulator
+// the LDS-staged gather keeps no FP64 accumulators in registers: it adds its FP32 sums over
+// kLdsChunk panels into the FP64 outputs in memory, so it flushes less often
+constexpr int kLdsChunk = 256;
 
 // A wave owns one observer and 252 consecutive samples k0 + 4*lane + m (m = 0..3,
 // lanes 0..62; lane 63 only computes the combined values its left neighbour
@@ -313,15 +316,19 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         }
     };
 
+    // FP32 sums over kLdsChunk panels, added in FP64 into the wave's own outputs (no other wave writes
+    // them), so no FP64 accumulators occupy registers
     float acc[kObsPerWave][kLdsSub];
-    double accd[kObsPerWave][kLdsSub];
 #pragma unroll
     for (int j = 0; j < kObsPerWave; ++j)
 #pragma unroll
-        for (int m = 0; m < kLdsSub; ++m) {
-            acc[j][m] = 0.f;
-            accd[j][m] = 0.0;
-        }
+        for (int m = 0; m < kLdsSub; ++m) acc[j][m] = 0.f;
+    // this wave's output element of observer slot j, sub-row m (null outside the output)
+    auto out_ptr = [&](int j, int m) -> double * {
+        const int64_t o = tbase + j * kLdsWaves + wv;
+        const int64_t k = k0 + m * kLdsLanesOut + lane;
+        return (lane < kLdsLanesOut && o < O && k < nt_max) ? partial + (z * O + o) * nt_max + k : nullptr;
+    };
     // this wave's valid observers (a prefix j < nobs) and the sub-rows of 61 samples below the
     // largest of their windows (0: nothing to do)
     int nt_wave = 0, nobs = 0;
@@ -407,6 +414,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NSUB = decltype(nsub_c)::value;
         int cnt = 0;
         int b = 0;
+        bool flushed = false;  // some chunk sum is already in the outputs
         // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
         auto load_lo = [&](int64_t ps) {
             const int64_t q = ps + lane < pe ? ps + lane : pe - 1;
@@ -432,15 +440,32 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                 const int lo = __builtin_amdgcn_readlane(lo_stage, q);
                 const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
                 panel_work(nobs_c, nsub_c, lrec, L0 + (lane - lo), q);
-                if (++cnt == kChunk) {
+                if (++cnt == kLdsChunk) {
 #pragma unroll
                     for (int j = 0; j < NOBS; ++j)
 #pragma unroll
                         for (int m = 0; m < NSUB; ++m) {
-                            accd[j][m] += (double)acc[j][m];
+                            double *dst = out_ptr(j, m);
+                            if (dst) *dst = (flushed ? *dst : 0.0) + (double)acc[j][m];
                             acc[j][m] = 0.f;
                         }
+                    flushed = true;
                     cnt = 0;
+                }
+            }
+        }
+        // final sums; outputs past an observer's window are zero
+#pragma unroll
+        for (int j = 0; j < kObsPerWave; ++j) {
+            const int64_t o = tbase + j * kLdsWaves + wv;
+            const int64_t ntl = o < O ? nt[o] : 0;
+#pragma unroll
+            for (int m = 0; m < kLdsSub; ++m) {
+                double *dst = out_ptr(j, m);
+                if (dst) {
+                    const int64_t k = k0 + m * kLdsLanesOut + lane;
+                    const double prev = (j < NOBS && m < NSUB && flushed) ? *dst : 0.0;
+                    *dst = k < ntl ? prev + (double)acc[j][m] : 0.0;
                 }
             }
         }
@@ -463,21 +488,6 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             case 1: by_sub(std::integral_constant<int, 1>{}); break;
             case 2: by_sub(std::integral_constant<int, 2>{}); break;
             default: by_sub(std::integral_constant<int, kObsPerWave>{}); break;
-        }
-    }
-    if (lane < kLdsLanesOut) {
-#pragma unroll
-        for (int j = 0; j < kObsPerWave; ++j) {
-            const int64_t o = tbase + j * kLdsWaves + wv;
-            if (o < O) {
-                const int64_t ntl = nt[o];
-#pragma unroll
-                for (int m = 0; m < kLdsSub; ++m) {
-                    const int64_t k = k0 + m * kLdsLanesOut + lane;
-                    if (k < nt_max)
-                        partial[(z * O + o) * nt_max + k] = (k < ntl) ? accd[j][m] + (double)acc[j][m] : 0.0;
-                }
-            }
         }
     }
 }
@@ -705,6 +715,16 @@ hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf 
     else
         gather_lds_kernel<uint16_t><<<n1, dim3(kLdsWaves * 64), shmem, stream>>>(a, tiles, kblocks);
     return hipGetLastError();
+}
+
+int gather_lds_blocks_per_cu(int coef_type, int NW, int PT) {
+    const size_t shmem = gather_lds_shmem(coef_type, NW, PT);
+    int n = 0;
+    const hipError_t e =
+        coef_type == 1
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_lds_kernel<float>, kLdsWaves * 64, shmem)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_lds_kernel<uint16_t>, kLdsWaves * 64, shmem);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream) {

@@ -253,6 +253,8 @@ inline size_t gather_lds_panel_bytes(int coef_type, int NW) {
     return (size_t)8 * NW * esz + (size_t)kObsTile * (sizeof(PairRec) + (coef_type == 1 ? 0 : sizeof(PairBf)));
 }
 inline size_t gather_lds_shmem(int coef_type, int NW, int PT) { return 2 * (size_t)PT * gather_lds_panel_bytes(coef_type, NW); }
+// blocks of the LDS-staged gather resident per CU at this staging size (registers and LDS)
+int gather_lds_blocks_per_cu(int coef_type, int NW, int PT);
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
                              const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
                              int PT, double *partial, hipStream_t stream);
