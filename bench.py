@@ -223,7 +223,7 @@ def bench_batch(replays, sync):
     plans = [fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
                       c.n_tau, mode="bf16") for c in cases]
     batch = fwh.Batch(plans, inputs)
-    iu, bpc, table = fwh.autotune(batch, candidates=[(1e6, 2), (4e6, 2), (16e6, 2), (4e6, 1)], reps=2)
+    iu, bpc, table = fwh.autotune(batch, candidates=[(1e6, 2), (4e6, 2), (16e6, 2), (1e6, 3), (4e6, 3)], reps=2)
     info = batch.info()
     graph = batch.capture()
     graph.replay()

@@ -129,3 +129,30 @@ def test_batch_autotune_keeps_results(tmp_path):
     # cached choice is reused
     iu2, bpc2, _ = fwh.autotune(batch, cache_path=str(tmp_path / "tune.json"))
     assert (iu2, bpc2) == (iu, bpc)
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_batch_blocks_per_cu_same_results(mode):
+    """The persistent gather's grid (1 to 4 resident blocks per CU) only changes
+    which block takes which work item: the outputs are bit-identical."""
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    data = _case_data(CASES)
+    plans = [make_plan(c, mode) for c in CASES]
+    inputs = [to_device(d[:3]) for d in data]
+    batch = fwh.Batch(plans, inputs)
+    ref = None
+    for bpc in (2, 1, 3, 4):
+        print(f"[batch grid] mode={mode} blocks_per_cu={bpc}", flush=True)
+        batch.tune(1e6, bpc)
+        p = [t.clone() for t in batch.forward()]
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = p
+            for i, d in enumerate(data):
+                m = valid_mask(d[4], d[3].shape[1])
+                assert rel_l2(p[i].double().cpu().numpy(), d[3], m) <= TOL[mode]
+        else:
+            for a, b in zip(p, ref):
+                assert torch.equal(a, b), bpc
