@@ -300,7 +300,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     // on R resident blocks (the LDS gather's occupancy at its staging size times the CU count; 2 per
     // CU for the direct-load gather) lasts about ceil(B*s/R)/s block-times of the unsplit work.  Among
     // the s (at most kMaxPanelSplits, at least 256 panels per split) within 3 % of its minimum, take
-    // the largest that keeps B*s within 8 rounds: whole rounds (no last round that leaves most CUs
+    // the largest that keeps B*s within 16 rounds: whole rounds (no last round that leaves most CUs
     // idle), and enough of them that blocks of unequal work even out
     int64_t blocks;
     if (pl->lds_pt > 0)
@@ -321,7 +321,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     for (int64_t c = 1; c <= smax; ++c) best = std::min(best, rounds(c));
     int64_t s = 1;
     for (int64_t c = 1; c <= smax; ++c)
-        if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 8 * resident)) s = c;
+        if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 16 * resident)) s = c;
     pl->splits = (int)s;
     pl->ready = true;
     return FWH_OK;
