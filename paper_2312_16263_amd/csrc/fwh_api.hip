@@ -104,7 +104,10 @@ int layout(fwh_plan *pl) {
     // (the chunked FP32/BF16 stages need none)
     if (pl->mode == FWH_MODE_F64) pl->off_scr = take(8 * N * P * real_sz);
     if (pl->mode != FWH_MODE_F64) {
-        pl->off_part = take((size_t)fwh::kMaxPanelSplits * O * N * sizeof(double));
+        // partial signals of the panel splits: at most kMaxPanelSplits, and never more than one per 64
+        // panels (the single-case selection keeps at least 256 panels per split, the batched one 64)
+        const int64_t max_splits = std::min<int64_t>(fwh::kMaxPanelSplits, std::max<int64_t>(1, (P + 63) / 64));
+        pl->off_part = take((size_t)max_splits * O * N * sizeof(double));
         pl->off_gpad = take((size_t)O * fwh::adj_pad_row(pl->N, pl->NS) * sizeof(float));
     }
     pl->ws_bytes = off;
