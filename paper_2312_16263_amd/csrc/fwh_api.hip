@@ -105,7 +105,7 @@ int layout(fwh_plan *pl) {
     if (pl->mode == FWH_MODE_F64) pl->off_scr = take(8 * N * P * real_sz);
     if (pl->mode != FWH_MODE_F64) {
         // partial signals of the panel splits: at most kMaxPanelSplits, and never more than one per 64
-        // panels (the single-case selection keeps at least 256 panels per split, the batched one 64)
+        // panels (the single-case selection keeps at least 128 panels per split, the batched one 64)
         const int64_t max_splits = std::min<int64_t>(fwh::kMaxPanelSplits, std::max<int64_t>(1, (P + 63) / 64));
         pl->off_part = take((size_t)max_splits * O * N * sizeof(double));
         pl->off_gpad = take((size_t)O * fwh::adj_pad_row(pl->N, pl->NS) * sizeof(float));
@@ -302,8 +302,8 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     // panel splits of the tuned gathers.  A split's block takes P/s panels, so a launch of B*s blocks
     // on R resident blocks (the LDS gather's occupancy at its staging size times the CU count; 2 per
     // CU for the direct-load gather) lasts about ceil(B*s/R)/s block-times of the unsplit work.  Among
-    // the s (at most kMaxPanelSplits, at least 256 panels per split) within 3 % of its minimum, take
-    // the largest that keeps B*s within 16 rounds: whole rounds (no last round that leaves most CUs
+    // the s (at most kMaxPanelSplits, at least 128 panels per split) within 3 % of its minimum, take
+    // the largest that keeps B*s within 32 rounds: whole rounds (no last round that leaves most CUs
     // idle), and enough of them that blocks of unequal work even out
     int64_t blocks;
     if (pl->lds_pt > 0)
@@ -318,13 +318,13 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         (int64_t)cus * (pl->lds_pt > 0 ? fwh::gather_lds_blocks_per_cu(pl->mode == FWH_MODE_F32 ? 1 : 2, pl->lds_nw,
                                                                        pl->lds_pt)
                                        : 2);
-    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + 255) / 256));
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + 127) / 128));
     auto rounds = [&](int64_t c) { return (double)((blocks * c + resident - 1) / resident) / (double)c; };
     double best = 1e300;
     for (int64_t c = 1; c <= smax; ++c) best = std::min(best, rounds(c));
     int64_t s = 1;
     for (int64_t c = 1; c <= smax; ++c)
-        if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 16 * resident)) s = c;
+        if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 32 * resident)) s = c;
     pl->splits = (int)s;
     pl->ready = true;
     return FWH_OK;

@@ -47,7 +47,7 @@ constexpr int kGatherLanesOut = 63;
 constexpr int kGatherKT = 4;
 constexpr int kGatherK = kGatherLanesOut * kGatherKT;  // 252
 constexpr int kGatherObsPerBlock = 4;                   // one observer per wave
-constexpr int kMaxPanelSplits = 128;
+constexpr int kMaxPanelSplits = 256;
 
 // LDS-staged gather: a block of kLdsWaves waves owns kObsTile consecutive
 // observers (kObsPerWave per wave) and kLdsK consecutive samples (kLdsSub
