@@ -774,7 +774,7 @@ int fwh_gm_plan_create(const fwh_gm_args *a, fwh_gm_plan **out, size_t *workspac
     }
     // panel splits: blocks of 4 observers x 64 samples x panel range (the record length stands in for
     // the window), 4 resident per CU.  As for the wind-tunnel gather, among the split counts within
-    // 3 % of the fewest rounds per unit of work take the largest that keeps the launch within 8
+    // 3 % of the fewest rounds per unit of work take the largest that keeps the launch within 32
     // rounds (at most 1024 splits, at least 16 panels each)
     const int64_t nkb = (N + 63) / 64;
     const int64_t gblocks = nkb * ((O + 3) / 4), gres = 4 * 256;
@@ -784,7 +784,7 @@ int fwh_gm_plan_create(const fwh_gm_args *a, fwh_gm_plan **out, size_t *workspac
     for (int64_t c = 1; c <= smax; ++c) gbest = std::min(gbest, grounds(c));
     int64_t sp = 1;
     for (int64_t c = 1; c <= smax; ++c)
-        if (grounds(c) <= gbest * 1.03 && (c == 1 || gblocks * c <= 8 * gres)) sp = c;
+        if (grounds(c) <= gbest * 1.03 && (c == 1 || gblocks * c <= 32 * gres)) sp = c;
     pl->splits = (int)sp;
     pl->p_chunk = (P + pl->splits - 1) / pl->splits;
     size_t off = 0;
