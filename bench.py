@@ -28,11 +28,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12                 # B/s, MI355X HBM3E
-FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: non-packed FP32 FMA (packed FP32 is not used)
-FP32_PACKED_PEAK = 157.3e12       # published FP32 vector peak (needs packed FP32 FMA)
+FP32_PEAK = 157.3e12              # published FP32 vector peak of MI355X (reached only with packed FP32 FMA)
+FP32_NONPACKED_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: FP32 FMA without packing (packed FP32 is not used)
 FLOP_PER_UNIT = 24                # 8 FMA channel combine + 4 FMA taps per (panel, observer, sample)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_dipole32768_f32.md")
 GM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_general_motion_orbit8192_f64.md")
+LOWO_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_dipole32768_obs8.md")
 
 
 def measured_traffic(kernel, path=TRAFFIC_PROFILE):
@@ -60,10 +61,65 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def rel_l2(a, b, mask):
     a = np.asarray(a, dtype=np.float64) * mask
     b = np.asarray(b, dtype=np.float64) * mask
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
+
+
+def bench_low_obs(c_full, d, steps, sync, n_obs=8):
+    """The dipole sphere's surface and data with 8 observers (every 45 deg at r =
+    100): 8 coefficient channels of 4 (FP32) or 2 (BF16) bytes per sample serve
+    only 8 observers, so the forward gather reads about 4 (2) bytes per unit
+    against 24 flop and is bound by HBM.  Reports the gather's algorithmic bytes
+    (coefficients read once, 52 B of pair table per pair, the output) over its
+    HIP-event time against the 8 TB/s peak."""
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    from workloads import configs
+    c = configs.dipole_sphere(n_obs=n_obs)
+    out = {"workload": f"dipole sphere (32768 panels, N=2048, M0=0.5, AoA 10 deg) with {n_obs} observers every "
+                       f"{360 // n_obs} deg at r=100; forward only"}
+    for mode, esz in (("f32", 4), ("bf16", 2)):
+        plan = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
+                        c.n_tau, mode=mode)
+        U = int(c.n_panels * int(plan.window.n_t.sum()))
+        p = plan.forward(*d)
+        sync()
+        plan.profile(True)
+        for _ in range(steps):
+            plan.forward(*d, out=p)
+        sync()
+        st = plan.profile_read()
+        g_ms = st["gather"][0] / st["gather"][1]
+        r_ms = st["reduce"][0] / st["reduce"][1]
+        s_ms = st["source"][0] / st["source"][1]
+        alg = 8 * esz * (c.n_tau + 3) * c.n_panels + 52 * n_obs * c.n_panels + 4 * int(plan.window.n_t.sum())
+        gbs = alg / (g_ms * 1e-3)
+        kern = "gather_lds_kernel<float>" if mode == "f32" else "gather_lds_kernel<unsigned short>"
+        out[mode] = {"units": U, "gather_ms": g_ms, "reduce_ms": r_ms, "source_ms": s_ms,
+                     "gather_units_per_s": U / (g_ms * 1e-3),
+                     "roofline": {"bound": "hbm", "kernel": kern, "achieved": gbs / 1e9, "peak": HBM_PEAK / 1e9,
+                                  "unit": "GB/s", "frac": gbs / HBM_PEAK, "algorithmic_bytes": alg,
+                                  "traffic": measured_traffic(kern, LOWO_TRAFFIC_PROFILE)},
+                     "gather": plan.info()}
+        log(f"[bench] {n_obs} observers {mode}: gather {g_ms:.3f} ms ({gbs / 1e9:.0f} GB/s algorithmic, "
+            f"{gbs / HBM_PEAK:.2f} of HBM peak), reduce {r_ms:.3f} ms, source {s_ms:.3f} ms, {plan.info()}")
+        del plan, p
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_steps(plan, d, steps, sync):
@@ -208,22 +264,29 @@ def bench_general_motion(steps, sync, profile_only=False):
 
 def bench_batch(replays, sync):
     """64 seeded uneven cases (spheres with analytic sources, extruded contours
-    with broadband data; P 2048-32768, N 512-2048, O 8-360, M0 0.1-0.5, AoA
-    0-10 deg), BF16 storage, one step (forward, dJ/dp', adjoint) of all cases
-    as one HIP-graph replay, against 64 separate plain FP64 steps."""
+    with broadband data; P 2048-65536, N 512-4096, O 8-360, M0 0.1-0.5, AoA
+    0-10 deg), BF16 storage, FP32 inputs: one step (forward, dJ/dp', adjoint)
+    of all cases as one HIP-graph replay, tiles tuned per class of case sizes,
+    against 64 separate plain FP64 steps."""
     import torch
 
     import paper_2312_16263_amd as fwh
     from workloads import configs
-    cases = configs.batched_cases(p_range=(2048, 32768), n_range=(512, 2048))
+    cases = configs.batched_cases()
     t0 = time.time()
     inputs = [c.data_device("cuda") for c in cases]
     sync()
-    log(f"[bench] batch: {len(cases)} cases generated ({time.time() - t0:.1f} s)")
+    log(f"[bench] batch: {len(cases)} cases generated on the device ({time.time() - t0:.1f} s), "
+        f"{torch.cuda.memory_allocated() / 1e9:.1f} GB")
     plans = [fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
                       c.n_tau, mode="bf16") for c in cases]
     batch = fwh.Batch(plans, inputs)
-    iu, bpc, table = fwh.autotune(batch, candidates=[(1e6, 2), (4e6, 2), (16e6, 2), (1e6, 3), (4e6, 3)], reps=2)
+    log(f"[bench] batch: plans and batch bound, {torch.cuda.memory_allocated() / 1e9:.1f} GB; gather {batch.gather}")
+    t0 = time.time()
+    tune = fwh.autotune(batch, reps=1)
+    log(f"[bench] batch: autotune {time.time() - t0:.1f} s: " +
+        "; ".join(f"{k} ({v['cases']}) -> rows {v['choice'][0]}, {v['choice'][1]:.0e}" for k, v in tune["classes"].items())
+        + f"; {tune['blocks_per_cu']} blocks/CU")
     info = batch.info()
     graph = batch.capture()
     graph.replay()
@@ -233,6 +296,15 @@ def bench_batch(replays, sync):
         graph.replay()
     sync()
     ms = (time.perf_counter() - t0) * 1e3 / replays
+    # forward and adjoint apart (eager, HIP events around each)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    batch.forward()
+    ev[1].record()
+    batch.adjoint()
+    ev[2].record()
+    sync()
+    fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     p_b = [t.double().cpu().numpy() for t in batch.p_out]
     del graph, batch
     del plans
@@ -253,14 +325,17 @@ def bench_batch(replays, sync):
         del plan
         torch.cuda.empty_cache()
     U = info["units"]
-    out = {"workload": "64 seeded uneven cases (sphere monopole/dipole and extruded-contour broadband; P 2048-32768, "
-                       "N 512-2048, O 8-360, M0 0.1-0.5, AoA 0-10 deg), BF16 storage, FP32 inputs",
+    out = {"workload": "64 seeded uneven cases (sphere monopole/dipole and extruded-contour broadband; P 2048-65536, "
+                       "N 512-4096, O 8-360, M0 0.1-0.5, AoA 0-10 deg), BF16 storage, FP32 inputs",
+           "panels": [c.n_panels for c in cases], "samples": [c.n_tau for c in cases],
+           "observers": [c.n_obs for c in cases],
            "units_per_step": U, "ms_per_step": ms, "value": U / (ms * 1e-3),
+           "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
            "plain_f64_64_launches": {"ms_per_step": t_plain * 1e3, "value": U / t_plain},
            "speedup_vs_plain_f64": t_plain * 1e3 / ms, "max_rel_l2_vs_plain_f64": max(errs),
-           "work_items": info["items"], "grid": info["grid"], "autotune": {"choice": [iu, bpc], "table": table}}
-    log(f"[bench] batch: {ms:.2f} ms/step ({U / (ms * 1e-3):.3e} units/s) vs 64 plain FP64 steps "
-        f"{t_plain * 1e3:.1f} ms; max rel L2 vs FP64 {max(errs):.3e}")
+           "work_items": info["items"], "grid": info["grid"], "autotune": tune}
+    log(f"[bench] batch: {ms:.2f} ms/step ({U / (ms * 1e-3):.3e} units/s; forward {fwd_ms:.1f} ms, adjoint "
+        f"{adj_ms:.1f} ms) vs 64 plain FP64 steps {t_plain * 1e3:.1f} ms; max rel L2 vs FP64 {max(errs):.3e}")
     del inputs
     torch.cuda.empty_cache()
     return out
@@ -415,7 +490,8 @@ def main():
     stages = plan.profile_read()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = U / (ms_per_step * 1e-3)
-    log(f"[bench] f32: {ms_per_step:.3f} ms/step, {value:.3e} units/s")
+    plan_info = plan.info()
+    log(f"[bench] f32: {ms_per_step:.3f} ms/step, {value:.3e} units/s; forward gather {plan_info}")
     avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     per_launch = {k: (v[0] / v[1] if v[1] else None) for k, v in stages.items()}
 
@@ -430,6 +506,10 @@ def main():
     mask = (np.arange(p_ref.shape[1])[None, :] < nt_ref[sample_obs][:, None]).astype(float)
     err32 = rel_l2(p32[sample_obs], p_ref, mask)
     log(f"[bench] f32 rel L2 vs FP64 oracle on observers {sample_obs.tolist()}: {err32:.3e}")
+    # and against the closed-form convected dipole (Sec. IV B) on all observers
+    t_obs = plan.window.t_start[:, None] + c.dtau * np.arange(p32.shape[1])[None, :]
+    err32_exact = rel_l2(p32, c.exact(t_obs), (np.arange(p32.shape[1])[None, :] < nt[:, None]).astype(float))
+    log(f"[bench] f32 rel L2 vs the closed-form dipole, all observers: {err32_exact:.3e}")
 
     # BF16 coefficient storage
     plan_b = fwh.Plan(c.surface.y, c.surface.normal, c.surface.dS, c.x_obs, c.mach, c.aoa_deg, c.dtau, c.tau0,
@@ -441,6 +521,7 @@ def main():
     errb = rel_l2(plan_b.forward(*d).double().cpu().numpy()[sample_obs], p_ref, mask)
     del plan_b
     log(f"[bench] bf16: {ms_b:.3f} ms/step, err {errb:.3e}")
+    low_obs = bench_low_obs(c, d, max(5, args.steps // 2), sync)
 
     plain = None
     if not args.no_plain:
@@ -466,12 +547,16 @@ def main():
     # algorithmic bytes per launch: coefficients (8 channels FP32 over NS) + pair records + output/input signal
     NSd = ((c.n_tau + 12 + 63) // 64) * 64
     alg_bytes = 8 * 4 * c.n_panels * NSd + 64 * c.n_obs * c.n_panels + 4 * c.n_obs * int(nt.max())
-    roofline = {"bound": "alu", "kernel": dom_kernel, "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": measured_traffic(dom_kernel),
+    roofline = {"bound": "alu", "kernel": dom_kernel, "achieved": achieved, "peak": FP32_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved * 1e12 / FP32_PEAK, "traffic": measured_traffic(dom_kernel),
                 "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes": alg_bytes,
-                "frac_of_packed_fp32_peak": achieved * 1e12 / FP32_PACKED_PEAK,
-                "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom]}
+                "frac_of_nonpacked_fp32_peak": achieved * 1e12 / FP32_NONPACKED_PEAK,
+                "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom],
+                "other_gather": {"kernel": "adj_gather_dpp_kernel" if dom == "gather" else "gather_lds_kernel<float>",
+                                 "avg_launch_ms": avg["adj_gather" if dom == "gather" else "gather"],
+                                 "frac": FLOP_PER_UNIT * U / (avg["adj_gather" if dom == "gather" else "gather"]
+                                                              * 1e-3) / FP32_PEAK}}
     # source stage: HBM-bound streaming (inputs read once, coefficients written once)
     NS = ((c.n_tau + 12 + 63) // 64) * 64
     src_bytes = 5 * 8 * c.n_panels * c.n_tau + 8 * 4 * c.n_panels * NS
@@ -481,7 +566,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        # oracle forward + adjoint (the same step) on a bounded observer sample
+        # oracle forward + adjoint (the same step) on a bounded observer sample, built for this host
+        flags = oracle.use_native()
+        n_threads = oracle.num_threads()
+
         def oracle_step(idx):
             xs = c.x_obs[idx]
             t = time.perf_counter()
@@ -498,11 +586,19 @@ def main():
         n_s = int(min(c.n_obs, max(1, round((args.cpu_seconds - fixed) / per_obs))))
         idx = np.unique(np.linspace(0, c.n_obs - 1, n_s).round().astype(int))
         t_cpu, u_cpu = oracle_step(idx)
-        cpu = {"value": u_cpu / t_cpu, "unit": "panel-obs-samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+        # the same on one thread, on one observer
+        oracle.set_num_threads(1)
+        t_1, u_1 = oracle_step(np.array([c.n_obs // 2]))
+        oracle.set_num_threads(n_threads)
+        cpu = {"value": u_cpu / t_cpu, "unit": "panel-obs-samples/s", "cores": n_threads, "kind": "oracle",
                "sample": f"forward + adjoint of the FP64 oracle on {len(idx)} of {c.n_obs} observers (all "
                          f"{c.n_panels} panels, {c.n_tau} samples): {u_cpu:.3e} units in {t_cpu:.1f} s; "
-                         f"excludes input generation", "seconds": t_cpu}
-        log(f"[bench] cpu oracle: {cpu['value']:.3e} units/s on {cpu['cores']} threads")
+                         f"excludes input generation", "seconds": t_cpu,
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+               "compile_flags": flags,
+               "value_1thread": u_1 / t_1, "sample_1thread": f"one observer, {u_1:.3e} units in {t_1:.1f} s"}
+        log(f"[bench] cpu oracle: {cpu['value']:.3e} units/s on {cpu['cores']} threads, {u_1 / t_1:.3e} on one "
+            f"({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     extra = {}
     if not args.no_extra:
@@ -525,11 +621,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_oracle": err32,
+        "err_vs_closed_form": err32_exact,
         "stage_ms_per_launch": per_launch,
         "fwd_units_per_s": U / ((avg["source"] + avg["gather"] + avg["reduce"]) * 1e-3),
         "adj_units_per_s": U / ((avg["adj_gather"] + avg["source_adj"]) * 1e-3),
         "source_roofline": src,
         "bf16_storage": {"value": U / (ms_b * 1e-3), "ms_per_step": ms_b, "err_vs_oracle": errb},
+        "hbm_bound_8_observers": low_obs,
+        "gather": plan_info,
         "plain_f64": plain,
         "speedup_vs_plain_f64": (value / plain["value"]) if plain else None,
         "oracle_sampled_forward_s": t_o,

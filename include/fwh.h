@@ -116,6 +116,31 @@ int fwh_plan_create(const fwh_setup_args *args, fwh_plan **out, size_t *workspac
  * `stream`.  FWH_EWINDOW if a window is empty. */
 int fwh_setup(fwh_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Launch choices of the FP32/BF16 forward gather, for tests and measurements
+ * (the defaults pick by themselves).  gather: FWH_GATHER_AUTO (the first of the
+ * following that applies), FWH_GATHER_MFMA (channel combine on the matrix
+ * cores for 32 observers x 16 samples at a time, then the taps; needs a tile's
+ * delay-index spread below about 260 samples), FWH_GATHER_LDS (coefficient
+ * windows staged in LDS; needs one panel's window over a tile to fit) or
+ * FWH_GATHER_DIRECT (direct loads); MFMA and LDS make fwh_setup fail with
+ * FWH_EINVAL when they do not apply.
+ * splits: number of panel ranges summed separately and then added in fixed
+ * order (0: chosen by fwh_setup to fill whole rounds of resident workgroups;
+ * else 1 .. min(256, ceil(P/128)), FWH_ESIZE beyond).  Every choice gives the
+ * same sums up to FP32 rounding order.  Host only; takes effect at the next
+ * fwh_setup, which must follow (until it does, forward and adjoint calls fail
+ * with FWH_ESTATE).  FWH_EINVAL for an unknown variant, or for any choice but
+ * (AUTO, 0) in FWH_MODE_F64. */
+#define FWH_GATHER_AUTO    0
+#define FWH_GATHER_LDS     1
+#define FWH_GATHER_DIRECT  2
+#define FWH_GATHER_MFMA    3
+int fwh_plan_tune(fwh_plan *plan, int32_t gather, int32_t splits);
+/* The gather kernel and panel-split count fwh_setup chose (FWH_GATHER_MFMA,
+ * _LDS or _DIRECT; FWH_GATHER_AUTO and 1 in FWH_MODE_F64).  FWH_ESTATE before
+ * fwh_setup.  Either pointer may be NULL. */
+int fwh_plan_info(const fwh_plan *plan, int32_t *gather, int32_t *splits);
+
 /* Observer window of a set-up plan (host values): t_start [O], n_t [O]
  * (samples per observer) and their maximum (row length of p_out).  Any
  * output pointer may be NULL. */
@@ -181,6 +206,16 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n_cases, int32_t in_dt
  * (panel-observer-samples; <= 0 keeps the default) and resident blocks per
  * compute unit of the persistent gather (1..4). */
 int fwh_batch_tune(fwh_batch *batch, double item_units, int32_t blocks_per_cu);
+/* Host only: tiles of one case for the next fwh_batch_bind: target work per
+ * forward item (<= 0 keeps the batch's) and rows of 61 samples per block of
+ * the matrix-core gather (2..4; 4 only when the batch uses the LDS-staged
+ * gather).  Shorter blocks waste fewer rows past short windows and cost more
+ * window overlap; the autotuner of the Python binding picks both per class of
+ * case sizes. */
+int fwh_batch_tune_case(fwh_batch *batch, int32_t case_index, double item_units, int32_t rows);
+/* The forward gather the batch runs for all its cases: FWH_GATHER_MFMA when
+ * every case's windows fit it, else FWH_GATHER_LDS. */
+int fwh_batch_gather(const fwh_batch *batch, int32_t *gather);
 /* Build the work list and upload descriptors and list into the workspace
  * (>= workspace_bytes, 256-byte aligned) on `stream`; synchronises `stream`. */
 int fwh_batch_bind(fwh_batch *batch, void *workspace, size_t workspace_bytes, void *stream);

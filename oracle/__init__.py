@@ -24,26 +24,49 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fwh_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+# FP64 throughout: no contraction of a*b+c into fused multiply-adds, no fast-math
+BASE_FLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
+NATIVE_FLAGS = BASE_FLAGS + ["-march=native"]
 
 _lib = None
+_lib_path = _LIB
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, -ffp-contract=off, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", _SRC, "-o", _LIB + ".tmp", "-lm"]
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, -ffp-contract=off, no fast-math).
+    native=True builds a copy tuned for the host CPU (-march=native) under
+    another name: it is only for timing on the machine that built it, the
+    portable build is the one the tests load."""
+    path = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(path):
+        cmd = ["gcc", *(NATIVE_FLAGS if native else BASE_FLAGS), _SRC, "-o", path + ".tmp", "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(path + ".tmp", path)
+    return path
+
+
+def use_native() -> str:
+    """Build the -march=native copy on this host and load it in place of the
+    portable one for the calls that follow; returns the compile flags."""
+    global _lib, _lib_path
+    build(force=True, native=True)
+    _lib, _lib_path = None, _LIB_NATIVE
+    _load()
+    return " ".join(NATIVE_FLAGS)
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        _lib = ctypes.CDLL(_LIB)
+        if not os.path.exists(_lib_path):
+            build(force=True, native=_lib_path == _LIB_NATIVE)
+        _lib = ctypes.CDLL(_lib_path)
         D = ctypes.POINTER(ctypes.c_double)
         I = ctypes.POINTER(ctypes.c_int64)
         i64, f64 = ctypes.c_int64, ctypes.c_double
@@ -79,6 +102,8 @@ def _load():
         _lib.orc_gm_channels.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+        _lib.orc_set_num_threads.restype = None
     return _lib
 
 

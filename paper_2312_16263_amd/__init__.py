@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libfwh.so")
 
 FWH_OK, FWH_EINVAL, FWH_EDOMAIN, FWH_EWINDOW, FWH_ESIZE, FWH_EWORKSPACE, FWH_EHIP, FWH_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 FWH_F64, FWH_F32 = 0, 1
+GATHER_AUTO, GATHER_LDS, GATHER_DIRECT, GATHER_MFMA = 0, 1, 2, 3
+GATHERS = {"auto": GATHER_AUTO, "lds": GATHER_LDS, "direct": GATHER_DIRECT, "mfma": GATHER_MFMA}
 MODE_F64, MODE_F32, MODE_BF16 = 0, 1, 2
 MODES = {"f64": MODE_F64, "f32": MODE_F32, "bf16": MODE_BF16}
 ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW: "FWH_EWINDOW",
@@ -26,8 +28,8 @@ ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW
                FWH_ESTATE: "FWH_ESTATE"}
 
 # names declared in include/fwh.h
-EXPORTED = ["fwh_plan_create", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_post", "fwh_profile_enable",
-            "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_bind", "fwh_batch_forward",
+EXPORTED = ["fwh_plan_create", "fwh_plan_tune", "fwh_plan_info", "fwh_setup", "fwh_obs_window", "fwh_forward", "fwh_adjoint", "fwh_post", "fwh_profile_enable",
+            "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_tune_case", "fwh_batch_gather", "fwh_batch_bind", "fwh_batch_forward",
             "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_gm_plan_create",
             "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_profile_enable",
             "fwh_gm_profile_read", "fwh_gm_destroy", "fwh_last_error",
@@ -79,6 +81,10 @@ def lib():
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.fwh_plan_create.argtypes = [ctypes.POINTER(SetupArgs), ctypes.POINTER(vp), ctypes.POINTER(sz)]
         L.fwh_plan_create.restype = ctypes.c_int
+        L.fwh_plan_tune.argtypes = [vp, i32, i32]
+        L.fwh_plan_tune.restype = ctypes.c_int
+        L.fwh_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.fwh_plan_info.restype = ctypes.c_int
         L.fwh_setup.argtypes = [vp, vp, sz, vp]
         L.fwh_setup.restype = ctypes.c_int
         L.fwh_obs_window.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -97,6 +103,10 @@ def lib():
         L.fwh_batch_create.restype = ctypes.c_int
         L.fwh_batch_tune.argtypes = [vp, ctypes.c_double, i32]
         L.fwh_batch_tune.restype = ctypes.c_int
+        L.fwh_batch_tune_case.argtypes = [vp, i32, ctypes.c_double, i32]
+        L.fwh_batch_tune_case.restype = ctypes.c_int
+        L.fwh_batch_gather.argtypes = [vp, ctypes.POINTER(i32)]
+        L.fwh_batch_gather.restype = ctypes.c_int
         L.fwh_batch_bind.argtypes = [vp, vp, sz, vp]
         L.fwh_batch_bind.restype = ctypes.c_int
         L.fwh_batch_forward.argtypes = [vp, vp]
@@ -165,10 +175,13 @@ class Plan:
     """A set-up FW-H plan on the current CUDA(HIP) device.
 
     y, normal [P,3], dS [P], x_obs [O,3]: geometry (host arrays);
-    mach, aoa_deg, dtau, tau0, n_tau: flow and time grid; mode: 'f64' | 'f32' | 'bf16'.
+    mach, aoa_deg, dtau, tau0, n_tau: flow and time grid; mode: 'f64' | 'f32' | 'bf16';
+    gather: forward gather kernel of the FP32/BF16 modes, 'auto' | 'mfma' | 'lds' | 'direct';
+    splits: panel splits of that gather (0: chosen at setup).
     """
 
-    def __init__(self, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0, n_tau, mode="f32", device=None):
+    def __init__(self, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0, n_tau, mode="f32", device=None,
+                 gather="auto", splits=0):
         import torch
         L = lib()
         self._keep = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (y, normal, dS, x_obs)]
@@ -180,6 +193,8 @@ class Plan:
         nbytes = ctypes.c_size_t()
         _check(L.fwh_plan_create(ctypes.byref(args), ctypes.byref(h), ctypes.byref(nbytes)))
         self._h = h
+        if gather != "auto" or splits:
+            _check(L.fwh_plan_tune(h, GATHERS[gather], int(splits)))
         self.P, self.O, self.N = yy.shape[0], xx.shape[0], int(n_tau)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workspace_bytes = int(nbytes.value)
@@ -200,6 +215,12 @@ class Plan:
         _check(L.fwh_obs_window(self._h, _dptr(ts), nt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 ctypes.byref(ntm)))
         self.window = Window(ts, nt, int(ntm.value))
+
+    def info(self):
+        """(gather kernel, panel splits) chosen at setup: ('mfma' | 'lds' | 'direct' | 'f64', splits)."""
+        g, s = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fwh_plan_info(self._h, ctypes.byref(g), ctypes.byref(s)))
+        return {GATHER_LDS: "lds", GATHER_DIRECT: "direct", GATHER_MFMA: "mfma"}.get(g.value, "f64"), int(s.value)
 
     def profile(self, enable: bool = True):
         """Bracket every stage of this plan with HIP events on its stream."""
@@ -293,9 +314,9 @@ def _stream():
 class Batch:
     """Many set-up plans (FP32 or BF16 mode) run as one batch: forward and
     adjoint of every case are each a fixed sequence of batched launches (the
-    forward gather persistent over a longest-first work list), so
-    `capture()` records a whole step (forward, dJ/dp' = 2 p', adjoint) in one
-    HIP graph.  `inputs` holds (rho, u, p) device tensors per plan, one dtype."""
+    gathers persistent over longest-first work lists), so `capture()` records a
+    whole step (forward, dJ/dp' = 2 p', adjoint) in one HIP graph.  `inputs`
+    holds (rho, u, p) device tensors per plan, one dtype."""
 
     def __init__(self, plans, inputs, item_units=None, blocks_per_cu=2):
         import torch
@@ -323,14 +344,32 @@ class Batch:
         _check(L.fwh_batch_create(arr, len(self.plans), self.in_dtype, ctypes.byref(h), ctypes.byref(nb)))
         self._h = h
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.plans[0].device)
+        self.blocks_per_cu = blocks_per_cu
         self.tune(item_units, blocks_per_cu)
 
-    def tune(self, item_units=None, blocks_per_cu=2):
-        L = lib()
-        _check(L.fwh_batch_tune(self._h, float(item_units or 0.0), int(blocks_per_cu)))
-        _check(L.fwh_batch_bind(self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
-                                _stream()))
-        self.item_units, self.blocks_per_cu = item_units, blocks_per_cu
+    @property
+    def gather(self):
+        """'mfma' or 'lds': the forward gather of every case."""
+        g = ctypes.c_int32()
+        _check(lib().fwh_batch_gather(self._h, ctypes.byref(g)))
+        return {GATHER_MFMA: "mfma", GATHER_LDS: "lds"}[g.value]
+
+    def tune(self, item_units=None, blocks_per_cu=None):
+        """Batch-wide work granularity (None keeps each case's) and resident blocks per CU; rebinds."""
+        bpc = self.blocks_per_cu if blocks_per_cu is None else blocks_per_cu
+        _check(lib().fwh_batch_tune(self._h, float(item_units or 0.0), int(bpc)))
+        self.blocks_per_cu = bpc
+        self.bind()
+
+    def tune_case(self, i, item_units=None, rows=4, bind=True):
+        """Tiles of case i: forward work per item and rows of 61 samples per block (2..4)."""
+        _check(lib().fwh_batch_tune_case(self._h, int(i), float(item_units or 0.0), int(rows)))
+        if bind:
+            self.bind()
+
+    def bind(self):
+        _check(lib().fwh_batch_bind(self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                    _stream()))
 
     def info(self):
         n_items, units, grid = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -374,7 +413,9 @@ class Batch:
             self._h = None
 
 
-DEFAULT_TUNING_CANDIDATES = [(1e6, 2), (2e6, 2), (4e6, 2), (8e6, 2), (16e6, 2), (4e6, 1), (4e6, 3)]
+# per-class candidates: (rows of 61 samples per block, target panel-observer-samples per forward item)
+DEFAULT_CASE_CANDIDATES = [(4, 1e6), (4, 4e6), (4, 16e6), (2, 1e6), (2, 4e6), (2, 16e6)]
+DEFAULT_BPC_CANDIDATES = (2, 3)
 
 
 def batch_signature(batch: "Batch") -> str:
@@ -383,40 +424,81 @@ def batch_signature(batch: "Batch") -> str:
     return "|".join(parts)
 
 
-def autotune(batch: "Batch", candidates=None, reps=3, cache_path=None):
-    """Pick the work granularity (target panel-observer-samples per work item)
-    and the resident blocks per CU of the persistent forward gather by timing
-    each candidate with HIP events; cache the choice per batch signature in
-    `cache_path` (JSON) when given.  Returns (item_units, blocks_per_cu, table)."""
+def size_class(plan) -> str:
+    """Tuning class of a case: mode, panels (nearest power of two), observers
+    (<= 32, <= 96, <= 192, more) and record length (<= 1024, <= 2048, more)."""
+    import math
+    ob = 0 if plan.O <= 32 else 1 if plan.O <= 96 else 2 if plan.O <= 192 else 3
+    nb = 0 if plan.N <= 1024 else 1 if plan.N <= 2048 else 2
+    return f"m{plan.mode}|P2^{int(round(math.log2(plan.P)))}|O{ob}|N{nb}"
+
+
+def _time_forward(batch, reps):
+    import torch
+    batch.forward()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        batch.forward()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def autotune(batch: "Batch", candidates=None, bpc_candidates=None, reps=2, cache_path=None):
+    """Tile choice per class of case sizes (size_class): the cases of one class
+    run alone as a batch under each (rows, item_units) candidate, timed with HIP
+    events over the batched forward; the fastest is applied to those cases.
+    Then the resident blocks per CU of the persistent gathers are timed on the
+    whole batch.  Choices are cached in `cache_path` (JSON) per class and, for
+    the grid, per batch signature.  Returns {"classes": {class: {"choice": [rows,
+    item_units], "table": [[rows, item_units, ms], ...]}}, "blocks_per_cu": b,
+    "grid_table": [[b, ms], ...]}."""
     import json
     import os
-    import torch
-    key = batch_signature(batch)
-    if cache_path and os.path.exists(cache_path):
-        cache = json.load(open(cache_path))
+    cands = list(candidates or DEFAULT_CASE_CANDIDATES)
+    if batch.gather != "mfma":
+        cands = sorted({(4, iu) for _, iu in cands})
+    cache = json.load(open(cache_path)) if cache_path and os.path.exists(cache_path) else {}
+    groups = {}
+    for i, pl in enumerate(batch.plans):
+        groups.setdefault(size_class(pl), []).append(i)
+    out = {"classes": {}}
+    for key, idx in groups.items():
         if key in cache:
-            iu, bpc = cache[key]["choice"]
-            batch.tune(iu, bpc)
-            return iu, bpc, cache[key]["table"]
-    table = []
-    for iu, bpc in (candidates or DEFAULT_TUNING_CANDIDATES):
-        batch.tune(iu, bpc)
-        batch.forward()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            batch.forward()
-        b.record()
-        b.synchronize()
-        table.append((iu, bpc, a.elapsed_time(b) / reps))
-    iu, bpc, _ = min(table, key=lambda r: r[2])
-    batch.tune(iu, bpc)
+            rows, iu = cache[key]["choice"]
+            table = cache[key]["table"]
+        else:
+            sub = Batch([batch.plans[i] for i in idx], [batch.inputs[i] for i in idx],
+                        blocks_per_cu=batch.blocks_per_cu)
+            table = []
+            for rows, iu in cands:
+                for j in range(len(idx)):
+                    sub.tune_case(j, iu, rows, bind=False)
+                sub.bind()
+                table.append([rows, iu, _time_forward(sub, reps)])
+            del sub
+            rows, iu, _ = min(table, key=lambda r: r[2])
+            cache[key] = {"choice": [rows, iu], "table": table}
+        for i in idx:
+            batch.tune_case(i, iu, rows, bind=False)
+        out["classes"][key] = {"choice": [rows, iu], "table": table, "cases": len(idx)}
+    sig = batch_signature(batch)
+    if sig in cache:
+        bpc, gtable = cache[sig]["choice"], cache[sig]["table"]
+    else:
+        gtable = []
+        for bpc in (bpc_candidates or DEFAULT_BPC_CANDIDATES):
+            batch.tune(None, bpc)
+            gtable.append([bpc, _time_forward(batch, reps)])
+        bpc = min(gtable, key=lambda r: r[1])[0]
+        cache[sig] = {"choice": bpc, "table": gtable}
+    batch.tune(None, bpc)
+    out["blocks_per_cu"], out["grid_table"] = bpc, gtable
     if cache_path:
-        cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
-        cache[key] = {"choice": [iu, bpc], "table": table}
         json.dump(cache, open(cache_path, "w"))
-    return iu, bpc, table
+    return out
 
 
 def _autograd_function():

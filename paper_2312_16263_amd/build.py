@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwh.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fwh_api.hip", "fwh_setup.hip", "fwh_source.hip", "fwh_gather.hip", "fwh_post.hip", "fwh_gm.hip"]
+SOURCES = ["fwh_api.hip", "fwh_setup.hip", "fwh_source.hip", "fwh_gather.hip", "fwh_gather_mfma.hip", "fwh_post.hip",
+           "fwh_gm.hip"]
 HOST_SOURCES = ["fwh_io.cpp"]  # host-only C++ (file readers), built with the host compiler
 ARCH = os.environ.get("FWH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",

@@ -33,6 +33,7 @@ int fail(int code, const char *fmt, ...) {
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 
+
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 }  // namespace
@@ -49,7 +50,12 @@ struct fwh_plan {
     std::vector<int32_t> n_t32;
     int64_t n_t_max = 0;
     int splits = 1;
+    int max_splits = 1;          // panel splits the partial-signal region holds
+    int gather_variant = FWH_GATHER_AUTO, forced_splits = 0;  // fwh_plan_tune
+    int gather_kind = FWH_GATHER_AUTO;  // kernel chosen by fwh_setup (FP32/BF16 modes)
     int lds_nw = 0, lds_pt = 0;  // staged window length and panels per stage of the LDS gather (0: not usable)
+    int wmax = 0;                // widest delay-index window over a tile of observers
+    int mfma_bpc = 0;            // resident blocks per CU of the matrix-core gather (0: not usable)
     bool ready = false;
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
@@ -70,6 +76,13 @@ namespace {
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+// Largest number of panel splits of the FP32/BF16 gathers (single-case and batched): at most
+// kMaxPanelSplits and at least kMinSplitPanels panels per split.  The partial-signal region is sized for it.
+constexpr int64_t kMinSplitPanels = 128;
+int64_t split_cap(int64_t P) {
+    return std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + kMinSplitPanels - 1) / kMinSplitPanels));
+}
+
 int layout(fwh_plan *pl) {
     const size_t P = (size_t)pl->P, O = (size_t)pl->O, N = (size_t)pl->N, NS = (size_t)pl->NS;
     size_t off = 0;
@@ -82,7 +95,6 @@ int layout(fwh_plan *pl) {
     pl->off_n = take(P * 3 * sizeof(double));
     pl->off_dS = take(P * sizeof(double));
     pl->off_x = take(O * 3 * sizeof(double));
-    pl->off_D = take(O * P * sizeof(double));
     pl->off_dmm = take(O * 2 * sizeof(double));
     pl->off_ts = take(O * sizeof(double));
     pl->off_nt = take(O * sizeof(int32_t));
@@ -97,17 +109,19 @@ int layout(fwh_plan *pl) {
         pl->off_tw = take((O + fwh::kObsTile - 1) / fwh::kObsTile * P * sizeof(int2));
         pl->off_wblk = take((size_t)fwh::tile_window_blocks(pl->P, pl->O) * sizeof(int32_t));
     }
-    // coefficient channels (forward) and coefficient adjoints (adjoint) share one region
+    // coefficient channels (forward) and coefficient adjoints (adjoint) share one region; the pair
+    // delays [O][P], needed only between the delay kernel and the window reduction of fwh_setup, live
+    // in it too when they fit (the forward writes the coefficients after the setup)
     const size_t real_sz = pl->mode == FWH_MODE_F64 ? sizeof(double) : sizeof(float);
     pl->off_coef = take(8 * P * NS * real_sz);
+    pl->off_D = O * P * sizeof(double) <= 8 * P * NS * real_sz ? pl->off_coef : take(O * P * sizeof(double));
     // time-major scratch of the sequential FP64 source stage, forward and adjoint
     // (the chunked FP32/BF16 stages need none)
     if (pl->mode == FWH_MODE_F64) pl->off_scr = take(8 * N * P * real_sz);
     if (pl->mode != FWH_MODE_F64) {
-        // partial signals of the panel splits: at most kMaxPanelSplits, and never more than one per 64
-        // panels (the single-case selection keeps at least 128 panels per split, the batched one 64)
-        const int64_t max_splits = std::min<int64_t>(fwh::kMaxPanelSplits, std::max<int64_t>(1, (P + 63) / 64));
-        pl->off_part = take((size_t)max_splits * O * N * sizeof(double));
+        // FP32 partial signals of the panel splits, [max_splits][O][n_t_max <= N]
+        pl->max_splits = (int)split_cap(pl->P);
+        pl->off_part = take((size_t)pl->max_splits * O * N * sizeof(float));
         pl->off_gpad = take((size_t)O * fwh::adj_pad_row(pl->N, pl->NS) * sizeof(float));
     }
     pl->ws_bytes = off;
@@ -295,9 +309,28 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
             while (pt > 1 && fwh::gather_lds_blocks_per_cu(ctype, nw, (int)pt) < occ1) --pt;
         }
         pl->lds_nw = nw;
-        pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit: the direct-load gather is used
-        const char *force = std::getenv("FWH_FORCE_DIRECT_GATHER");  // test hook: exercise the direct-load gather
-        if (force && force[0] == '1') pl->lds_pt = 0;
+        pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit
+        pl->wmax = wmax;
+        pl->mfma_bpc = fwh::gather_mfma_blocks_per_cu(ctype, wmax);
+        // kernel: the matrix-core gather when its Y tile fits, else the LDS-staged one, else direct loads
+        switch (pl->gather_variant) {
+            case FWH_GATHER_MFMA:
+                if (pl->mfma_bpc <= 0)
+                    return fail(FWH_EINVAL, "fwh_setup: the delay windows (%d samples) are too wide for the "
+                                            "matrix-core gather", wmax);
+                pl->gather_kind = FWH_GATHER_MFMA;
+                break;
+            case FWH_GATHER_LDS:
+                if (pl->lds_pt <= 0)
+                    return fail(FWH_EINVAL, "fwh_setup: the delay windows (%d samples) are too wide for the "
+                                            "LDS-staged gather", wmax);
+                pl->gather_kind = FWH_GATHER_LDS;
+                break;
+            case FWH_GATHER_DIRECT: pl->gather_kind = FWH_GATHER_DIRECT; break;
+            default:
+                pl->gather_kind = pl->mfma_bpc > 0 ? FWH_GATHER_MFMA
+                                                   : (pl->lds_pt > 0 ? FWH_GATHER_LDS : FWH_GATHER_DIRECT);
+        }
     }
     // panel splits of the tuned gathers.  A split's block takes P/s panels, so a launch of B*s blocks
     // on R resident blocks (the LDS gather's occupancy at its staging size times the CU count; 2 per
@@ -306,7 +339,8 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     // the largest that keeps B*s within 32 rounds: whole rounds (no last round that leaves most CUs
     // idle), and enough of them that blocks of unequal work even out
     int64_t blocks;
-    if (pl->lds_pt > 0)
+    const bool tiled = !f64 && pl->gather_kind != FWH_GATHER_DIRECT;  // 32-observer x 244-sample blocks
+    if (tiled)
         blocks = ((O + fwh::kObsTile - 1) / fwh::kObsTile) * ((pl->n_t_max + fwh::kLdsK - 1) / fwh::kLdsK);
     else
         blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
@@ -314,19 +348,56 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
         return hip_fail("fwh_setup: device query", e);
+    const int ctype_s = pl->mode == FWH_MODE_F32 ? 1 : 2;
     const int64_t resident =
-        (int64_t)cus * (pl->lds_pt > 0 ? fwh::gather_lds_blocks_per_cu(pl->mode == FWH_MODE_F32 ? 1 : 2, pl->lds_nw,
-                                                                       pl->lds_pt)
-                                       : 2);
-    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + 127) / 128));
+        (int64_t)cus * (pl->gather_kind == FWH_GATHER_MFMA  ? pl->mfma_bpc
+                        : pl->gather_kind == FWH_GATHER_LDS ? fwh::gather_lds_blocks_per_cu(ctype_s, pl->lds_nw,
+                                                                                            pl->lds_pt)
+                                                            : 2);
+    const int64_t smax = split_cap(P);
     auto rounds = [&](int64_t c) { return (double)((blocks * c + resident - 1) / resident) / (double)c; };
     double best = 1e300;
     for (int64_t c = 1; c <= smax; ++c) best = std::min(best, rounds(c));
     int64_t s = 1;
     for (int64_t c = 1; c <= smax; ++c)
         if (rounds(c) <= best * 1.03 && (c == 1 || blocks * c <= 32 * resident)) s = c;
+    if (pl->forced_splits > 0) s = pl->forced_splits;
     pl->splits = (int)s;
+    if (!f64) {
+        // one launch: a 1-D grid of at most 2^32 work-items
+        const int64_t threads = blocks * s * (tiled ? (int64_t)fwh::kLdsWaves * 64 : 256);
+        if (blocks * s > INT32_MAX || threads >= ((int64_t)1 << 32))
+            return fail(FWH_ESIZE, "fwh_setup: %lld observers x %lld samples x %lld panel splits exceed one gather launch",
+                        (long long)O, (long long)pl->n_t_max, (long long)s);
+    }
     pl->ready = true;
+    return FWH_OK;
+}
+
+int fwh_plan_tune(fwh_plan *pl, int32_t gather, int32_t splits) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_plan_tune: null plan");
+    if (gather != FWH_GATHER_AUTO && gather != FWH_GATHER_LDS && gather != FWH_GATHER_DIRECT &&
+        gather != FWH_GATHER_MFMA)
+        return fail(FWH_EINVAL, "fwh_plan_tune: unknown gather variant %d", (int)gather);
+    if (pl->mode == FWH_MODE_F64 && (gather != FWH_GATHER_AUTO || splits != 0))
+        return fail(FWH_EINVAL, "fwh_plan_tune: the plain FP64 form has one gather and no panel splits");
+    if (splits < 0 || splits > pl->max_splits)
+        return fail(FWH_ESIZE, "fwh_plan_tune: splits must be in 0 .. %d for %lld panels (got %d)", pl->max_splits,
+                    (long long)pl->P, (int)splits);
+    pl->gather_variant = gather;
+    pl->forced_splits = splits;
+    pl->ready = false;
+    return FWH_OK;
+}
+
+int fwh_plan_info(const fwh_plan *pl, int32_t *gather, int32_t *splits) {
+    g_last_error.clear();
+    if (!pl) return fail(FWH_EINVAL, "fwh_plan_info: null plan");
+    if (!pl->ready) return fail(FWH_ESTATE, "fwh_plan_info: plan is not set up");
+    if (gather)
+        *gather = pl->mode == FWH_MODE_F64 ? FWH_GATHER_AUTO : pl->gather_kind;
+    if (splits) *splits = pl->mode == FWH_MODE_F64 ? 1 : pl->splits;
     return FWH_OK;
 }
 
@@ -366,20 +437,25 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
     } else {
         {
             StageScope sc(pl, FWH_STAGE_GATHER, st);
-            if (pl->lds_pt > 0)
+            if (pl->gather_kind == FWH_GATHER_MFMA)
+                e = fwh::launch_gather_mfma(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                            pl->at<int2>(pl->off_tw), pl->at<int32_t>(pl->off_nt),
+                                            pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
+                                            pl->wmax, pl->at<float>(pl->off_part), st);
+            else if (pl->gather_kind == FWH_GATHER_LDS)
                 e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
                                            pl->at<int2>(pl->off_tw),
                                            pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O, pl->NS,
                                            pl->n_t_max, pl->splits, pl->lds_nw, pl->lds_pt,
-                                           pl->at<double>(pl->off_part), st);
+                                           pl->at<float>(pl->off_part), st);
             else
                 e = fwh::launch_gather_tuned(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op),
                                              pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O,
-                                             pl->NS, pl->n_t_max, pl->splits, pl->at<double>(pl->off_part), st);
+                                             pl->NS, pl->n_t_max, pl->splits, pl->at<float>(pl->off_part), st);
         }
         if (!e) {
             StageScope sc(pl, FWH_STAGE_REDUCE, st);
-            e = fwh::launch_reduce_splits(pl->at<double>(pl->off_part), pl->splits, pl->O * pl->n_t_max,
+            e = fwh::launch_reduce_splits(pl->at<float>(pl->off_part), pl->splits, pl->O * pl->n_t_max,
                                           static_cast<float *>(p_out), st);
         }
     }
@@ -479,11 +555,16 @@ struct fwh_batch {
     int in_dtype = 0, mode = 0, n = 0;
     double item_units = 4.0e6;
     int blocks_per_cu = 2;
+    int kind = FWH_GATHER_MFMA;        // forward gather of every case (matrix-core or LDS-staged)
+    int umax = 0;                      // matrix units per wave the persistent kernel is compiled for
+    std::vector<double> case_units;    // per case: target panel-observer-samples per forward item
+    std::vector<int> case_rows;        // per case: rows of 61 samples per block (matrix-core gather)
     int64_t max_items = 0, n_items = 0, units = 0, grid = 0;
+    int64_t max_adj_items = 0, n_adj_items = 0, grid_adj = 0;
     int64_t blocks_src = 0, blocks_srcg = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_sadj = 0,
             blocks_sadjg = 0;
     size_t shmem = 0;
-    size_t off_cases = 0, off_idx = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
+    size_t off_cases = 0, off_idx = 0, off_items = 0, off_adj_items = 0, off_counter = 0, ws_bytes = 0;
     char *ws = nullptr;
     bool bound = false;
     template <typename T>
@@ -505,7 +586,7 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
     if (!cases || !out || n < 1) return fail(FWH_EINVAL, "fwh_batch_create: need cases, out and n_cases >= 1");
     if (in_dtype != FWH_F64 && in_dtype != FWH_F32) return fail(FWH_EINVAL, "fwh_batch_create: bad in_dtype");
     int mode = -1;
-    int64_t max_items = 0;
+    int64_t max_items = 0, max_adj_items = 0;
     for (int c = 0; c < n; ++c) {
         const fwh_batch_case &k = cases[c];
         if (!k.plan || !k.rho || !k.u || !k.p_prime || !k.p_out || !k.grad_p || !k.g_rho || !k.g_u || !k.g_p)
@@ -515,11 +596,16 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
             return fail(FWH_EINVAL, "fwh_batch_create: case %d uses the plain FP64 mode (batches run FP32/BF16)", c);
         if (mode < 0) mode = k.plan->mode;
         if (k.plan->mode != mode) return fail(FWH_EINVAL, "fwh_batch_create: cases mix FP32 and BF16 modes");
-        if (k.plan->lds_pt <= 0)
-            return fail(FWH_EINVAL, "fwh_batch_create: case %d has delay windows too wide for the LDS gather", c);
-        const int64_t tiles = ceil_div(k.plan->O, fwh::kObsTile), kbs = ceil_div(k.plan->n_t_max, fwh::kLdsK);
-        max_items += tiles * kbs * fwh::kMaxPanelSplits;
+        if (k.plan->lds_pt <= 0 && k.plan->mfma_bpc <= 0)
+            return fail(FWH_EINVAL, "fwh_batch_create: case %d has delay windows too wide for the batched gathers", c);
+        // k blocks of at least 2 rows (matrix-core gather), 4 rows (LDS-staged gather)
+        const int64_t tiles = ceil_div(k.plan->O, fwh::kObsTile),
+                      kbs = ceil_div(k.plan->n_t_max, 2 * fwh::kLdsLanesOut);
+        max_items += tiles * kbs * k.plan->max_splits;
+        const int64_t nib = ceil_div(k.plan->NS, fwh::kAdjSub * fwh::kLdsLanesOut);
+        max_adj_items += ceil_div(ceil_div(k.plan->P * nib, 4), fwh::kAdjItemGroups);
     }
+    if (max_adj_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many adjoint work items");
     if (max_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many work items");
     fwh_batch *b = new (std::nothrow) fwh_batch();
     if (!b) return fail(FWH_EINVAL, "fwh_batch_create: out of host memory");
@@ -528,6 +614,21 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
     b->in_dtype = in_dtype;
     b->mode = mode;
     b->max_items = max_items;
+    b->max_adj_items = max_adj_items;
+    // the matrix-core gather when every case can take it, else the LDS-staged one
+    bool all_mfma = true, all_lds = true;
+    for (int c = 0; c < n; ++c) {
+        all_mfma = all_mfma && cases[c].plan->mfma_bpc > 0;
+        all_lds = all_lds && cases[c].plan->lds_pt > 0;
+        b->umax = std::max(b->umax, fwh::gather_mfma_umax(cases[c].plan->wmax));
+    }
+    if (!all_mfma && !all_lds) {
+        delete b;
+        return fail(FWH_EINVAL, "fwh_batch_create: no batched gather takes the delay windows of every case");
+    }
+    b->kind = all_mfma ? FWH_GATHER_MFMA : FWH_GATHER_LDS;
+    b->case_units.assign((size_t)n, b->item_units);
+    b->case_rows.assign((size_t)n, fwh::kLdsSub);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -537,7 +638,8 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
     b->off_cases = take((size_t)n * sizeof(fwh::BatchCase));
     b->off_idx = take((size_t)7 * (n + 1) * sizeof(int64_t));
     b->off_items = take((size_t)max_items * sizeof(int4));
-    b->off_counter = take(sizeof(int));
+    b->off_adj_items = take((size_t)max_adj_items * sizeof(int2));
+    b->off_counter = take(2 * sizeof(int));  // forward and adjoint work-list counters
     b->ws_bytes = off;
     *out = b;
     if (workspace_bytes) *workspace_bytes = off;
@@ -548,9 +650,32 @@ int fwh_batch_tune(fwh_batch *b, double item_units, int32_t blocks_per_cu) {
     g_last_error.clear();
     if (!b) return fail(FWH_EINVAL, "fwh_batch_tune: null batch");
     if (blocks_per_cu < 1 || blocks_per_cu > 4) return fail(FWH_EINVAL, "fwh_batch_tune: blocks_per_cu in 1..4");
-    if (item_units > 0.0) b->item_units = item_units;
+    if (item_units > 0.0) {
+        b->item_units = item_units;
+        b->case_units.assign((size_t)b->n, item_units);
+    }
     b->blocks_per_cu = blocks_per_cu;
     b->bound = false;
+    return FWH_OK;
+}
+
+int fwh_batch_tune_case(fwh_batch *b, int32_t c, double item_units, int32_t rows) {
+    g_last_error.clear();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_tune_case: null batch");
+    if (c < 0 || c >= b->n) return fail(FWH_EINVAL, "fwh_batch_tune_case: case %d not in 0..%d", (int)c, b->n - 1);
+    if (rows < 2 || rows > fwh::kLdsSub || (b->kind != FWH_GATHER_MFMA && rows != fwh::kLdsSub))
+        return fail(FWH_EINVAL, "fwh_batch_tune_case: rows must be 2..%d (%d with the LDS-staged gather)",
+                    fwh::kLdsSub, fwh::kLdsSub);
+    if (item_units > 0.0) b->case_units[(size_t)c] = item_units;
+    b->case_rows[(size_t)c] = rows;
+    b->bound = false;
+    return FWH_OK;
+}
+
+int fwh_batch_gather(const fwh_batch *b, int32_t *gather) {
+    g_last_error.clear();
+    if (!b) return fail(FWH_EINVAL, "fwh_batch_gather: null batch");
+    if (gather) *gather = b->kind;
     return FWH_OK;
 }
 
@@ -571,17 +696,25 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         int4 w;
     };
     std::vector<Item> items;
+    struct AdjItem {
+        double cost;
+        int2 w;
+    };
+    std::vector<AdjItem> adj_items;
     b->units = 0;
     b->shmem = 0;
     for (int c = 0; c < n; ++c) {
         const fwh_batch_case &k = b->cases[c];
         fwh_plan *pl = k.plan;
         const int64_t P = pl->P, O = pl->O, N = pl->N, NS = pl->NS, ntm = pl->n_t_max;
-        const int64_t tiles = ceil_div(O, fwh::kObsTile), kbs = ceil_div(ntm, fwh::kLdsK);
-        // panel splits: work per item close to item_units
-        const double tile_units = (double)P * std::min<int64_t>(O, fwh::kObsTile) * std::min<int64_t>(ntm, fwh::kLdsK);
-        int64_t S = (int64_t)std::ceil(tile_units / b->item_units);
-        S = std::max<int64_t>(1, std::min<int64_t>({S, (int64_t)fwh::kMaxPanelSplits, ceil_div(P, 64)}));
+        const bool mfma = b->kind == FWH_GATHER_MFMA;
+        const int rows = mfma ? b->case_rows[(size_t)c] : fwh::kLdsSub;
+        const int64_t kstep = (int64_t)fwh::kLdsLanesOut * rows;
+        const int64_t tiles = ceil_div(O, fwh::kObsTile), kbs = ceil_div(ntm, kstep);
+        // panel splits: work per item close to the case's target
+        const double tile_units = (double)P * std::min<int64_t>(O, fwh::kObsTile) * std::min<int64_t>(ntm, kstep);
+        int64_t S = (int64_t)std::ceil(tile_units / b->case_units[(size_t)c]);
+        S = std::max<int64_t>(1, std::min<int64_t>(S, pl->max_splits));
         const int64_t p_chunk = ceil_div(P, S);
         const int64_t LR = fwh::adj_pad_row(N, NS), padlo = fwh::adj_pad_lo(N);
         const int64_t nib = ceil_div(NS, fwh::kAdjSub * fwh::kLdsLanesOut);
@@ -590,8 +723,9 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
                                 pl->at<double>(pl->off_cp), pl->scratch(), pl->ws + pl->off_coef};
         d.gat = fwh::GatherArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(), pl->at<int2>(pl->off_tw),
                                 pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, P, O, NS, ntm, p_chunk,
-                                pl->lds_nw, pl->lds_pt, (int)S, pl->at<double>(pl->off_part)};
-        d.red = fwh::ReduceArgs{pl->at<double>(pl->off_part), (int)S, O * ntm, static_cast<float *>(k.p_out)};
+                                mfma ? fwh::gather_mfma_y_row(pl->wmax) : pl->lds_nw, pl->lds_pt, (int)S,
+                                pl->at<float>(pl->off_part), rows};
+        d.red = fwh::ReduceArgs{pl->at<float>(pl->off_part), (int)S, O * ntm, static_cast<float *>(k.p_out)};
         d.pad = fwh::PadArgs{static_cast<const float *>(k.grad_p), pl->at<int32_t>(pl->off_nt), O, ntm, LR, padlo,
                              pl->at<float>(pl->off_gpad)};
         d.adj = fwh::AdjArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<float>(pl->off_gpad), P, O, NS, LR, padlo,
@@ -607,24 +741,37 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         const int64_t adj_int = fwh::adj_interior_chunks(N);
         s_sadj[c + 1] = s_sadj[c] + ceil_div(P, fwh::kSrcPanels) * adj_int;
         s_sadjg[c + 1] = s_sadjg[c] + ceil_div(P, fwh::kSrcPanels) * (fwh::adj_chunks(N) - adj_int);
-        b->shmem = std::max(b->shmem, fwh::gather_lds_shmem(coef_type, pl->lds_nw, pl->lds_pt));
+        b->shmem = std::max(b->shmem, mfma ? fwh::gather_mfma_shmem(pl->wmax)
+                                           : fwh::gather_lds_shmem(coef_type, pl->lds_nw, pl->lds_pt));
         for (int64_t t = 0; t < tiles; ++t)
             for (int64_t kb = 0; kb < kbs; ++kb)
                 for (int64_t z = 0; z < S; ++z) {
                     const int64_t np = std::max<int64_t>(0, std::min(P, (z + 1) * p_chunk) - z * p_chunk);
                     const int64_t no = std::min<int64_t>(fwh::kObsTile, O - t * fwh::kObsTile);
-                    const int64_t nk = std::min<int64_t>(fwh::kLdsK, ntm - kb * fwh::kLdsK);
+                    const int64_t nk = std::min<int64_t>(kstep, ntm - kb * kstep);
                     items.push_back({(double)np * no * nk, make_int4(c, (int)t, (int)kb, (int)z)});
                 }
+        // transposed gather: items of kAdjItemGroups groups of 4 (panel, index block) waves, each wave
+        // costing O x 244 panel-observer-samples (the last item of a case may be partly empty)
+        const int64_t groups = ceil_div(P * nib, 4), n_adj = ceil_div(groups, fwh::kAdjItemGroups);
+        for (int64_t g = 0; g < n_adj; ++g) {
+            const int64_t waves = std::min<int64_t>(4 * fwh::kAdjItemGroups, P * nib - 4 * fwh::kAdjItemGroups * g);
+            adj_items.push_back({(double)waves * O, make_int2(c, (int)g)});
+        }
         int64_t sum_nt = 0;
         for (int64_t o = 0; o < O; ++o) sum_nt += pl->n_t[o];
         b->units += P * sum_nt;
     }
     // longest first (the paper's greedy partition by size), ties in case order
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    std::stable_sort(adj_items.begin(), adj_items.end(),
+                     [](const AdjItem &x, const AdjItem &y) { return x.cost > y.cost; });
     std::vector<int4> wl(items.size());
     for (size_t i = 0; i < items.size(); ++i) wl[i] = items[i].w;
+    std::vector<int2> wla(adj_items.size());
+    for (size_t i = 0; i < adj_items.size(); ++i) wla[i] = adj_items[i].w;
     b->n_items = (int64_t)wl.size();
+    b->n_adj_items = (int64_t)wla.size();
     b->blocks_src = s_src[n];
     b->blocks_srcg = s_srcg[n];
     b->blocks_red = s_red[n];
@@ -637,6 +784,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
         return hip_fail("fwh_batch_bind: device query", e);
     b->grid = (int64_t)cus * b->blocks_per_cu;
+    b->grid_adj = (int64_t)cus * fwh::adj_gather_blocks_per_cu();
     b->ws = static_cast<char *>(workspace);
     if ((e = hipMemcpyAsync(b->at<fwh::BatchCase>(b->off_cases), desc.data(), desc.size() * sizeof(fwh::BatchCase),
                             hipMemcpyHostToDevice, st)) ||
@@ -644,6 +792,8 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
                             hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(b->at<int4>(b->off_items), wl.data(), wl.size() * sizeof(int4), hipMemcpyHostToDevice,
                             st)) ||
+        (e = hipMemcpyAsync(b->at<int2>(b->off_adj_items), wla.data(), wla.size() * sizeof(int2),
+                            hipMemcpyHostToDevice, st)) ||
         (e = hipStreamSynchronize(st)))
         return hip_fail("fwh_batch_bind: upload", e);
     b->bound = true;
@@ -661,6 +811,7 @@ int fwh_batch_forward(fwh_batch *b, void *stream_) {
     g_last_error.clear();
     if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_forward: batch is not bound");
     hipError_t e = fwh::launch_batch_forward(b->in_dtype == FWH_F64 ? 0 : 1, b->mode == FWH_MODE_F32 ? 1 : 2,
+                                             b->kind == FWH_GATHER_MFMA ? b->umax : 0,
                                              b->at<fwh::BatchCase>(b->off_cases), batch_index(b),
                                              b->at<int4>(b->off_items), (int)b->n_items, b->at<int>(b->off_counter),
                                              (int)b->grid, b->shmem, b->blocks_src, b->blocks_srcg, b->blocks_red,
@@ -673,8 +824,9 @@ int fwh_batch_adjoint(fwh_batch *b, void *stream_) {
     g_last_error.clear();
     if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_adjoint: batch is not bound");
     hipError_t e = fwh::launch_batch_adjoint(b->in_dtype == FWH_F64 ? 0 : 1, b->at<fwh::BatchCase>(b->off_cases),
-                                             batch_index(b), b->blocks_pad, b->waves_adj, b->blocks_sadj,
-                                             b->blocks_sadjg, as_stream(stream_));
+                                             batch_index(b), b->blocks_pad, b->at<int2>(b->off_adj_items),
+                                             (int)b->n_adj_items, b->at<int>(b->off_counter) + 1, (int)b->grid_adj,
+                                             b->blocks_sadj, b->blocks_sadjg, as_stream(stream_));
     if (e) return hip_fail("fwh_batch_adjoint", e);
     return FWH_OK;
 }
@@ -869,9 +1021,10 @@ int fwh_gm_forward(fwh_gm_plan *pl, const double *rho, const double *u, const do
     if (!pl) return fail(FWH_EINVAL, "fwh_gm_forward: null plan");
     if (!pl->ready) return fail(FWH_ESTATE, "fwh_gm_forward: no window computed");
     if (!rho || !u || !pp || !p_out) return fail(FWH_EINVAL, "fwh_gm_forward: null data pointer");
-    if ((int64_t)pl->splits * ((pl->a.n_obs + 3) / 4) * ((pl->n_t_max + 63) / 64) > (int64_t)INT32_MAX)
-        return fail(FWH_ESIZE, "fwh_gm_forward: %lld observers x %lld samples exceed one launch",
-                    (long long)pl->a.n_obs, (long long)pl->n_t_max);
+    // one launch of 256-thread blocks: at most 2^32 work-items
+    if ((int64_t)pl->splits * ((pl->a.n_obs + 3) / 4) * ((pl->n_t_max + 63) / 64) * 256 >= ((int64_t)1 << 32))
+        return fail(FWH_ESIZE, "fwh_gm_forward: %lld observers x %lld samples x %d panel ranges exceed one launch",
+                    (long long)pl->a.n_obs, (long long)pl->n_t_max, pl->splits);
     hipStream_t st = as_stream(stream_);
     fwh::GmChanArgs c{};
     c.y = pl->a.y;
@@ -958,6 +1111,7 @@ void fwh_gm_destroy(fwh_gm_plan *pl) {
 }
 
 const char *fwh_last_error(void) { return g_last_error.c_str(); }
+
 
 const char *fwh_version(void) { return "fwh-mi355x 0.1 (gfx950)"; }
 

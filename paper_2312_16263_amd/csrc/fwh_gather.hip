@@ -92,8 +92,9 @@ __device__ __forceinline__ float from_next_lane(float x) {
 }
 
 constexpr int kChunk = 64;  // panels summed in FP32 before adding into the FP64 accumulator
-// the LDS-staged gather keeps no FP64 accumulators in registers: it adds its FP32 sums over
-// kLdsChunk panels into the FP64 outputs in memory, so it flushes less often
+// the LDS-staged gather keeps no accumulators beyond one FP32 sum per output in registers: it adds
+// its sums over kLdsChunk panels into the split's partial signal in memory (a split of at most
+// kLdsChunk panels is one FP32 sum; the splits are added in FP64 by the reduction)
 constexpr int kLdsChunk = 256;
 
 // A wave owns one observer and 252 consecutive samples k0 + 4*lane + m (m = 0..3,
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
                                                            const int32_t *__restrict__ nt,
                                                            const TS *__restrict__ coef, int64_t P, int64_t O,
                                                            int64_t NS, int64_t nt_max, int64_t p_chunk,
-                                                           double *__restrict__ partial) {
+                                                           float *__restrict__ partial) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t o = (int64_t)blockIdx.x * kGatherObsPerBlock + wv;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void gather_tuned_kernel(const PairRec *__rest
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int64_t k = kl + m;
-            if (k < nt_max) partial[(z * O + o) * nt_max + k] = (k < ntl) ? accd[m] + (double)acc[m] : 0.0;
+            if (k < nt_max) partial[(z * O + o) * nt_max + k] = (k < ntl) ? (float)(accd[m] + (double)acc[m]) : 0.f;
         }
     }
 }
@@ -253,7 +254,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     const TS *__restrict__ coef = static_cast<const TS *>(a.coef);
     const int64_t P = a.P, O = a.O, NS = a.NS, nt_max = a.nt_max, p_chunk = a.p_chunk;
     const int NW = a.NW, PT = a.PT;
-    double *__restrict__ partial = a.partial;
+    float *__restrict__ partial = a.partial;
     using QT = typename Quad<TS>::T;
     constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels)
     constexpr bool kBf = std::is_same<TS, uint16_t>::value;
@@ -316,15 +317,15 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         }
     };
 
-    // FP32 sums over kLdsChunk panels, added in FP64 into the wave's own outputs (no other wave writes
-    // them), so no FP64 accumulators occupy registers
+    // FP32 sums over kLdsChunk panels, added into the wave's own outputs of the split's partial signal
+    // (no other wave writes them)
     float acc[kObsPerWave][kLdsSub];
 #pragma unroll
     for (int j = 0; j < kObsPerWave; ++j)
 #pragma unroll
         for (int m = 0; m < kLdsSub; ++m) acc[j][m] = 0.f;
     // this wave's output element of observer slot j, sub-row m (null outside the output)
-    auto out_ptr = [&](int j, int m) -> double * {
+    auto out_ptr = [&](int j, int m) -> float * {
         const int64_t o = tbase + j * kLdsWaves + wv;
         const int64_t k = k0 + m * kLdsLanesOut + lane;
         return (lane < kLdsLanesOut && o < O && k < nt_max) ? partial + (z * O + o) * nt_max + k : nullptr;
@@ -445,8 +446,8 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                     for (int j = 0; j < NOBS; ++j)
 #pragma unroll
                         for (int m = 0; m < NSUB; ++m) {
-                            double *dst = out_ptr(j, m);
-                            if (dst) *dst = (flushed ? *dst : 0.0) + (double)acc[j][m];
+                            float *dst = out_ptr(j, m);
+                            if (dst) *dst = (flushed ? *dst : 0.f) + acc[j][m];
                             acc[j][m] = 0.f;
                         }
                     flushed = true;
@@ -461,11 +462,11 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const int64_t ntl = o < O ? nt[o] : 0;
 #pragma unroll
             for (int m = 0; m < kLdsSub; ++m) {
-                double *dst = out_ptr(j, m);
+                float *dst = out_ptr(j, m);
                 if (dst) {
                     const int64_t k = k0 + m * kLdsLanesOut + lane;
-                    const double prev = (j < NOBS && m < NSUB && flushed) ? *dst : 0.0;
-                    *dst = k < ntl ? prev + (double)acc[j][m] : 0.0;
+                    const float prev = (j < NOBS && m < NSUB && flushed) ? *dst : 0.f;
+                    *dst = k < ntl ? prev + acc[j][m] : 0.f;
                 }
             }
         }
@@ -646,18 +647,34 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
     adj_gather_dpp_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
-__global__ __launch_bounds__(256) void adj_gather_dpp_batched(const BatchCase *__restrict__ cases,
-                                                              const int64_t *__restrict__ start, int n) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c = find_case(start, n, w);
-    adj_gather_dpp_body(cases[c].adj, w - start[c]);
+// Persistent batched transposed gather: blocks of 4 waves pull items in list
+// order (longest first: the paper's greedy partition by size) through an atomic
+// counter until the list is exhausted.  Item (case c, g) covers the waves
+// [4 kAdjItemGroups g, 4 kAdjItemGroups (g + 1)) of case c, wave w being
+// (panel w / nib, index block w % nib); waves past the case's P * nib return at once.
+__global__ __launch_bounds__(256) void adj_gather_persistent(const BatchCase *__restrict__ cases,
+                                                             const int2 *__restrict__ items, int n_items,
+                                                             int *__restrict__ counter) {
+    __shared__ int cur;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (;;) {
+        __syncthreads();  // every wave has read the previous item
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(cur);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const int c = __builtin_amdgcn_readfirstlane(w.x);
+        const int64_t g0 = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * kAdjItemGroups;
+        for (int g = 0; g < kAdjItemGroups; ++g) adj_gather_dpp_body(cases[c].adj, (g0 + g) * 4 + wv);
+    }
 }
 
 // out[o][k] = sum_z partial[z][o][k] in fixed order.
 __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int64_t i) {
     if (i >= a.total) return;
     double s = 0.0;
-    for (int z = 0; z < a.splits; ++z) s += a.partial[(int64_t)z * a.total + i];
+    for (int z = 0; z < a.splits; ++z) s += (double)a.partial[(int64_t)z * a.total + i];
     a.out[i] = (float)s;
 }
 
@@ -667,12 +684,12 @@ __global__ __launch_bounds__(256) void reduce_batched(const BatchCase *__restric
     reduce_body(cases[c].red, ((int64_t)blockIdx.x - start[c]) * 256 + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__restrict__ partial, int splits,
+__global__ __launch_bounds__(256) void reduce_splits_kernel(const float *__restrict__ partial, int splits,
                                                             int64_t total, float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * total + i];
+    for (int z = 0; z < splits; ++z) s += (double)partial[(int64_t)z * total + i];
     out[i] = (float)s;
 }
 
@@ -688,7 +705,7 @@ hipError_t launch_gather_f64(const double *K64, const double *W64, const int32_t
 }
 
 hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32_t *nt, const void *coef, int64_t P,
-                               int64_t O, int64_t NS, int64_t nt_max, int splits, double *partial,
+                               int64_t O, int64_t NS, int64_t nt_max, int splits, float *partial,
                                hipStream_t stream) {
     const int64_t p_chunk = (P + splits - 1) / splits;
     dim3 grid((unsigned)((O + kGatherObsPerBlock - 1) / kGatherObsPerBlock),
@@ -704,7 +721,7 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
 
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
                              const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
-                             int PT, double *partial, hipStream_t stream) {
+                             int PT, float *partial, hipStream_t stream) {
     const int64_t p_chunk = (P + splits - 1) / splits;
     const GatherArgs a{rec_op, rbf, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
     const int64_t tiles = (O + kObsTile - 1) / kObsTile, kblocks = (nt_max + kLdsK - 1) / kLdsK;
@@ -727,7 +744,7 @@ int gather_lds_blocks_per_cu(int coef_type, int NW, int PT) {
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream) {
+hipError_t launch_reduce_splits(const float *partial, int splits, int64_t total, float *out, hipStream_t stream) {
     reduce_splits_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(partial, splits, total, out);
     return hipGetLastError();
 }
@@ -754,7 +771,7 @@ hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const flo
     return hipGetLastError();
 }
 
-hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
+hipError_t launch_batch_forward(int in_dtype, int coef_type, int umax, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
                                 int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream) {
     hipError_t e =
@@ -762,7 +779,9 @@ hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *ca
     if (e != hipSuccess) return e;
     reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (coef_type == 1)
+    if (umax > 0)
+        e = launch_gather_mfma_persistent(coef_type, umax, cases, items, n_items, counter, grid, shmem, stream);
+    else if (coef_type == 1)
         gather_lds_persistent<float><<<dim3((unsigned)grid), dim3(kLdsWaves * 64), shmem, stream>>>(cases, items,
                                                                                                    n_items, counter);
     else
@@ -773,12 +792,21 @@ hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *ca
     return hipGetLastError();
 }
 
+int adj_gather_blocks_per_cu() {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_gather_persistent, 256, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                int64_t waves_adj, int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream) {
+                                const int2 *adj_items, int n_adj_items, int *counter, int grid_adj,
+                                int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream) {
     pad_grad_batched<<<dim3((unsigned)blocks_pad), dim3(256), 0, stream>>>(cases, idx.pad, idx.n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    adj_gather_dpp_batched<<<dim3((unsigned)((waves_adj + 3) / 4)), dim3(256), 0, stream>>>(cases, idx.adj, idx.n);
+    reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    adj_gather_persistent<<<dim3((unsigned)grid_adj), dim3(256), 0, stream>>>(cases, adj_items, n_adj_items, counter);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_batch_source_adjoint(in_dtype, cases, idx.sadj, idx.sadjg, idx.n, blocks_sadj, blocks_sadjg, stream);
 }

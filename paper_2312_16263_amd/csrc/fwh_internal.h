@@ -97,11 +97,12 @@ struct GatherArgs {
     const void *coef;
     int64_t P, O, NS, nt_max, p_chunk;
     int NW, PT, splits;
-    double *partial;
+    float *partial;  // [splits][O][nt_max] partial signals of the panel splits
+    int rows;        // matrix-core gather: rows of kLdsLanesOut samples per block (1..kLdsSub)
 };
 
 struct ReduceArgs {
-    const double *partial;
+    const float *partial;
     int splits;
     int64_t total;
     float *out;
@@ -241,9 +242,9 @@ hipError_t launch_source(int in_dtype, int coef_type, const void *rho, const voi
 hipError_t launch_gather_f64(const double *K64, const double *W64, const int32_t *N0, const int32_t *nt,
                              const double *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, double *out,
                              hipStream_t stream);
-// coef_type 1 = float, 2 = bf16.  partial: [splits][O][nt_max] doubles.
+// coef_type 1 = float, 2 = bf16.  partial: [splits][O][nt_max] floats.
 hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32_t *nt, const void *coef, int64_t P,
-                               int64_t O, int64_t NS, int64_t nt_max, int splits, double *partial,
+                               int64_t O, int64_t NS, int64_t nt_max, int splits, float *partial,
                                hipStream_t stream);
 // LDS-staged gather; NW = staged window length per channel group (multiple of 64, >= max
 // width + kLdsK + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
@@ -257,9 +258,26 @@ inline size_t gather_lds_shmem(int coef_type, int NW, int PT) { return 2 * (size
 int gather_lds_blocks_per_cu(int coef_type, int NW, int PT);
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
                              const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
-                             int PT, double *partial, hipStream_t stream);
-// out[i] = sum over splits of partial[z][i], fixed order, rounded to float.
-hipError_t launch_reduce_splits(const double *partial, int splits, int64_t total, float *out, hipStream_t stream);
+                             int PT, float *partial, hipStream_t stream);
+// Matrix-core gather (fwh_gather_mfma.hip): per panel a Y tile [kObsTile][YR] floats in LDS covering
+// the window of the widest tile (wmax = largest n0 spread over a tile's observers).
+inline int gather_mfma_y_row(int wmax) { return ((wmax + kLdsK + kLdsHalo + 15) / 16) * 16 + 4; }
+inline size_t gather_mfma_shmem(int wmax) { return (size_t)kObsTile * gather_mfma_y_row(wmax) * sizeof(float); }
+// matrix units per wave and panel the kernel is compiled for (4, 6 or 8; 0: windows too wide)
+int gather_mfma_umax(int wmax);
+// resident blocks per CU (0 when the kernel does not apply)
+int gather_mfma_blocks_per_cu(int coef_type, int wmax);
+hipError_t launch_gather_mfma(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw,
+                              const int32_t *nt, const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max,
+                              int splits, int wmax, float *partial, hipStream_t stream);
+// Persistent batched form: `grid` blocks pull (case, tile, k block, split) items through counter[0]
+// (reset by the caller's stream order); every case's GatherArgs carries its Y row length in NW and
+// its rows per block; umax as for the widest case, shmem its Y tile.
+int gather_mfma_persistent_blocks_per_cu(int coef_type, int umax, size_t shmem);
+hipError_t launch_gather_mfma_persistent(int coef_type, int umax, const BatchCase *cases, const int4 *items,
+                                         int n_items, int *counter, int grid, size_t shmem, hipStream_t stream);
+// out[i] = sum over splits of partial[z][i], in FP64 and fixed order, rounded to float.
+hipError_t launch_reduce_splits(const float *partial, int splits, int64_t total, float *out, hipStream_t stream);
 
 hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int32_t *N0, const int32_t *nt,
                                  const double *gbar, int64_t P, int64_t O, int64_t NS, int64_t nt_max, double *cbar,
@@ -289,11 +307,19 @@ hipError_t launch_batch_source(int in_dtype, int coef_type, const BatchCase *cas
 hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, const int64_t *start_int,
                                        const int64_t *start_gen, int n, int64_t blocks_int, int64_t blocks_gen,
                                        hipStream_t stream);
-hipError_t launch_batch_forward(int in_dtype, int coef_type, const BatchCase *cases, BatchIndex idx,
+// forward: chunked source stage of all cases, counter reset, the persistent gather (matrix-core with
+// `umax` units per wave, or LDS-staged when umax is 0), then the split sums of all cases
+hipError_t launch_batch_forward(int in_dtype, int coef_type, int umax, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
                                 int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream);
+// adjoint: zero-padded dJ/dp' of all cases, then the persistent transposed gather over adj_items
+// (case, group of kAdjItemGroups x 4 waves), longest first, through counter[0] (reset first), then
+// the chunked source adjoint of all cases
+constexpr int kAdjItemGroups = 8;
+int adj_gather_blocks_per_cu();
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                int64_t waves_adj, int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream);
+                                const int2 *adj_items, int n_adj_items, int *counter, int grid_adj,
+                                int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream);
 
 // Post-processing: per-observer RMS and one-sided Welch PSD (segments of L
 // samples, 50 % overlap, Hann window), times span_ratio; psd [O][L/2+1], rms [O].

@@ -23,11 +23,11 @@ def valid_mask(n_t, width):
     return (np.arange(width)[None, :] < np.asarray(n_t)[:, None]).astype(np.float64)
 
 
-def make_plan(case, mode):
+def make_plan(case, mode, **kw):
     import paper_2312_16263_amd as fwh
     s = case.surface
     return fwh.Plan(s.y, s.normal, s.dS, case.x_obs, case.mach, case.aoa_deg, case.dtau, case.tau0, case.n_tau,
-                    mode=mode)
+                    mode=mode, **kw)
 
 
 def to_device(arrs, dtype=None):

@@ -169,3 +169,45 @@ def test_gm_profile_entry_points_host_only():
     assert L.fwh_gm_profile_read(h, 2, ctypes.byref(ms), ctypes.byref(n)) == fwh.FWH_EINVAL
     assert L.fwh_gm_profile_enable(None, 1) == fwh.FWH_EINVAL
     L.fwh_gm_destroy(h)
+
+
+def test_plan_tune_host_checks():
+    """fwh_plan_tune validates on the host: unknown variants, split counts beyond
+    min(256, ceil(P/128)), any choice in the plain FP64 form; fwh_plan_info needs
+    a set-up plan."""
+    L = fwh.lib()
+    s = surfaces.sphere(1.0, 91, 183)                 # 16653 panels: split cap ceil(P/128) = 131
+    a, keep = _args(y=s.y, normal=s.normal, dS=s.dS)
+    code, h, nb = _create(a)
+    assert code == fwh.FWH_OK
+    assert L.fwh_plan_tune(h, fwh.GATHER_DIRECT, 131) == fwh.FWH_OK
+    assert L.fwh_plan_tune(h, fwh.GATHER_LDS, 0) == fwh.FWH_OK
+    assert L.fwh_plan_tune(h, fwh.GATHER_AUTO, 132) == fwh.FWH_ESIZE
+    assert L.fwh_plan_tune(h, fwh.GATHER_AUTO, -1) == fwh.FWH_ESIZE
+    assert L.fwh_plan_tune(h, 7, 0) == fwh.FWH_EINVAL
+    assert L.fwh_plan_tune(None, 0, 0) == fwh.FWH_EINVAL
+    g, sp = ctypes.c_int32(), ctypes.c_int32()
+    assert L.fwh_plan_info(h, ctypes.byref(g), ctypes.byref(sp)) == fwh.FWH_ESTATE
+    L.fwh_destroy(h)
+    a, keep = _args(mode=fwh.MODE_F64)
+    code, h, nb = _create(a)
+    assert L.fwh_plan_tune(h, fwh.GATHER_AUTO, 0) == fwh.FWH_OK
+    assert L.fwh_plan_tune(h, fwh.GATHER_LDS, 0) == fwh.FWH_EINVAL
+    assert L.fwh_plan_tune(h, fwh.GATHER_AUTO, 1) == fwh.FWH_EINVAL
+    L.fwh_destroy(h)
+
+
+def test_partial_region_follows_split_cap():
+    """The FP32/BF16 workspace holds FP32 partial signals for at most
+    min(256, ceil(P/128)) panel splits: doubling P below 128 * 256 panels grows
+    the workspace by more than the coefficient region alone would need."""
+    sizes = {}
+    for nth in (8, 16):
+        s = surfaces.sphere(1.0, nth, 2 * nth)
+        a, keep = _args(y=s.y, normal=s.normal, dS=s.dS, mode=fwh.MODE_F32, n_tau=64)
+        code, h, nb = _create(a)
+        assert code == fwh.FWH_OK
+        sizes[s.n_panels] = nb
+        fwh.lib().fwh_destroy(h)
+    (p1, b1), (p2, b2) = sorted(sizes.items())
+    assert b2 > b1

@@ -111,6 +111,9 @@ def test_batch_graph_replays_match_eager():
 
 
 def test_batch_autotune_keeps_results(tmp_path):
+    """The per-class tile tuner (rows per block and work per item for each class
+    of case sizes, then the persistent grid) leaves the results within the
+    oracle tolerance, and a cached choice is reused as it was made."""
     import torch
 
     import paper_2312_16263_amd as fwh
@@ -118,17 +121,44 @@ def test_batch_autotune_keeps_results(tmp_path):
     plans = [make_plan(c, "f32") for c in CASES]
     inputs = [to_device(d[:3]) for d in data]
     batch = fwh.Batch(plans, inputs)
-    iu, bpc, table = fwh.autotune(batch, candidates=[(1e5, 2), (1e6, 1), (1e7, 2)], reps=2,
-                                  cache_path=str(tmp_path / "tune.json"))
-    print(f"    autotune table {table} -> {iu:.0e} units/item, {bpc} blocks/CU", flush=True)
+    res = fwh.autotune(batch, candidates=[(4, 1e5), (2, 1e6), (4, 1e7)], bpc_candidates=(1, 2), reps=2,
+                       cache_path=str(tmp_path / "tune.json"))
+    for key, v in res["classes"].items():
+        print(f"    class {key} ({v['cases']} cases): {v['table']} -> {v['choice']}", flush=True)
+    print(f"    grid {res['grid_table']} -> {res['blocks_per_cu']} blocks/CU", flush=True)
     p = [t.clone() for t in batch.forward()]
     torch.cuda.synchronize()
     for i, d in enumerate(data):
         m = valid_mask(d[4], d[3].shape[1])
         assert rel_l2(p[i].double().cpu().numpy(), d[3], m) <= TOL["f32"]
-    # cached choice is reused
-    iu2, bpc2, _ = fwh.autotune(batch, cache_path=str(tmp_path / "tune.json"))
-    assert (iu2, bpc2) == (iu, bpc)
+    # cached choices are reused
+    res2 = fwh.autotune(batch, cache_path=str(tmp_path / "tune.json"))
+    assert res2["blocks_per_cu"] == res["blocks_per_cu"]
+    assert {k: v["choice"] for k, v in res2["classes"].items()} == {k: v["choice"] for k, v in res["classes"].items()}
+
+
+@pytest.mark.parametrize("rows", [2, 3])
+def test_batch_rows_per_block(rows):
+    """Shorter k blocks of the matrix-core batched gather (2 or 3 rows of 61
+    samples) against the oracle."""
+    import torch
+
+    import paper_2312_16263_amd as fwh
+    data = _case_data(CASES)
+    plans = [make_plan(c, "f32") for c in CASES]
+    inputs = [to_device(d[:3]) for d in data]
+    batch = fwh.Batch(plans, inputs, item_units=3e5)
+    assert batch.gather == "mfma"
+    for i in range(len(CASES)):
+        batch.tune_case(i, None, rows, bind=False)
+    batch.bind()
+    p = [t.clone() for t in batch.forward()]
+    torch.cuda.synchronize()
+    for i, d in enumerate(data):
+        m = valid_mask(d[4], d[3].shape[1])
+        err = rel_l2(p[i].double().cpu().numpy(), d[3], m)
+        print(f"    rows={rows} case {i}: rel L2 vs oracle {err:.3e}", flush=True)
+        assert err <= TOL["f32"], err
 
 
 @pytest.mark.parametrize("mode", ["f32", "bf16"])

@@ -139,20 +139,22 @@ def test_window_error_is_reported():
     assert ei.value.code == fwh.FWH_EWINDOW
 
 
+@pytest.mark.parametrize("gather", ["mfma", "lds", "direct"])
 @pytest.mark.parametrize("mode", ["f32", "bf16"])
-def test_direct_load_gather_matches(mode, monkeypatch):
-    """The direct-load gather (used when a panel window does not fit in LDS)
-    against the oracle, forced through its test hook."""
+@pytest.mark.parametrize("name", ["dip_ragged", "foil_bb", "ragged65"])
+def test_gather_variants(name, mode, gather):
+    """Each forward gather kernel (matrix-core combine, LDS-staged windows,
+    direct loads), chosen through fwh_plan_tune, against the oracle."""
     import torch
-    monkeypatch.setenv("FWH_FORCE_DIRECT_GATHER", "1")
-    c = CASES["dip_ragged"]
-    rho, u, pp, p_ref, _, nt_ref = _data("dip_ragged")
-    plan = make_plan(c, mode)
+    c = CASES[name]
+    rho, u, pp, p_ref, _, nt_ref = _data(name)
+    plan = make_plan(c, mode, gather=gather)
+    assert plan.info()[0] == gather
     out = plan.forward(*to_device((rho, u, pp)))
     torch.cuda.synchronize()
     p = out.double().cpu().numpy()
     err = rel_l2(p, p_ref, valid_mask(nt_ref, p.shape[1]))
-    print(f"    direct gather {mode}: rel L2 vs oracle = {err:.3e}", flush=True)
+    print(f"    {name} {gather} gather {mode}: rel L2 vs oracle = {err:.3e}", flush=True)
     assert err <= TOL_FWD[mode], err
 
 
@@ -212,3 +214,29 @@ def test_post_rms_and_welch(mode, seg_len):
     print(f"    post {mode} L={seg_len}: PSD rel L2 {e_psd:.3e}, RMS rel L2 {e_rms:.3e}", flush=True)
     assert e_psd <= 1e-5, e_psd
     assert e_rms <= 1e-6, e_rms
+
+
+@pytest.mark.parametrize("gather", ["mfma", "lds", "direct"])
+@pytest.mark.parametrize("splits", [130, 131, 7])
+def test_many_panel_splits(gather, splits):
+    """Many panel splits, including an empty last one: 16641 panels in 130
+    splits of ceil(16641/130) = 129 panels leave split 130 without panels (its
+    partial signal must be zeros); 131 splits of 128 panels; 7 uneven splits.
+    Both forward gathers against the oracle on a short record with few observers."""
+    import torch
+    P = 16641
+    c = configs.Case("split_sphere", surfaces.sphere(1.0, 129, 129), surfaces.observer_circle(5, 40.0, start_deg=11.0),
+                     0.2, 7.0, 1.0 / 64.0, 128, kind="dipole")
+    assert c.n_panels == P
+    rho, u, pp = c.data()
+    p_ref, _, nt_ref = oracle_forward(c, rho, u, pp)
+    plan = make_plan(c, "f32", gather=gather, splits=splits)
+    assert plan.info() == (gather, splits)
+    out = plan.forward(*to_device((rho, u, pp)))
+    torch.cuda.synchronize()
+    p = out.double().cpu().numpy()
+    err = rel_l2(p, p_ref, valid_mask(nt_ref, p.shape[1]))
+    chunk = -(-P // splits)
+    print(f"    {gather} gather, {splits} splits of {chunk} panels (last {P - (splits - 1) * chunk}): "
+          f"rel L2 vs oracle = {err:.3e}", flush=True)
+    assert err <= TOL_FWD["f32"], err

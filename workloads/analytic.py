@@ -110,6 +110,34 @@ def surface_series(kind: str, y: np.ndarray, flow: Flow, amplitude: float, omega
             np.ascontiguousarray(pp, dtype=dtype))
 
 
+def surface_series_torch(kind: str, y: np.ndarray, flow: Flow, amplitude: float, omega: float,
+                         n_tau: int, dtau: float, tau0: float = 0.0, source=(0.0, 0.0, 0.0),
+                         dtype=np.float64, device="cuda"):
+    """surface_series built on a torch device: the spatial amplitudes and the
+    time factors come from the host (numpy, as above), the [N, P] products are
+    formed on the device with the same separately rounded FP64 operations, so
+    the values equal surface_series bit for bit."""
+    import torch
+    u_hat, p_hat = field_amplitudes(kind, y, flow, amplitude, omega, source)
+    tau = tau0 + dtau * np.arange(n_tau, dtype=np.float64)
+    c = torch.from_numpy(np.cos(omega * tau)).to(device)[:, None]
+    s = torch.from_numpy(np.sin(omega * tau)).to(device)[:, None]
+    tdt = {np.float64: torch.float64, np.float32: torch.float32}[np.dtype(dtype).type]
+
+    def re(a):  # Re(a exp(i w tau)) as [N, P], FP64
+        ar = torch.from_numpy(np.ascontiguousarray(a.real)).to(device)[None, :]
+        ai = torch.from_numpy(np.ascontiguousarray(a.imag)).to(device)[None, :]
+        return torch.sub(torch.mul(ar, c), torch.mul(ai, s))
+
+    pp = re(p_hat)
+    rho = torch.add(torch.mul(pp, flow.mach ** 2), 1.0).to(tdt)
+    U = flow.U
+    u = torch.empty((3, n_tau, y.shape[0]), dtype=tdt, device=device)
+    for i in range(3):
+        u[i] = torch.add(re(u_hat[:, i]), float(U[i])).to(tdt)
+    return rho.contiguous(), u, pp.to(tdt).contiguous()
+
+
 def far_field_pressure(kind: str, x_obs: np.ndarray, flow: Flow, amplitude: float, omega: float,
                        t: np.ndarray, source=(0.0, 0.0, 0.0)) -> np.ndarray:
     """Exact pressure pulsation p'(x_o, t) of the analytic field at observers

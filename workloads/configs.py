@@ -65,10 +65,11 @@ class Case:
     def data_device(self, device="cuda"):
         """Surface data as device tensors; broadband data are generated on the
         device (torch generator), analytic data on the host then copied."""
-        import torch
         if self.kind == "broadband":
             return broadband.surface_data_torch(self.n_panels, self.n_tau, self.aoa_deg, self.seed, device=device)
-        return tuple(torch.from_numpy(a).to(device) for a in self.data())
+        return analytic.surface_series_torch(self.kind, self.surface.y, analytic.Flow(self.mach, self.aoa_deg),
+                                             self.amplitude, self.omega, self.n_tau, self.dtau, self.tau0,
+                                             dtype=self.data_dtype, device=device)
 
     def exact(self, t):
         """Closed-form p'(x_o, t) of the analytic source ([O, K] times)."""
