@@ -50,6 +50,19 @@ def measured_traffic(kernel, path=TRAFFIC_PROFILE):
     return None
 
 
+GATHER_KERNELS = {"lds": "gather_lds_kernel", "stream": "gather_stream_kernel", "mfma": "gather_mfma_kernel",
+                  "direct": "gather_tuned_kernel"}
+
+
+def gather_kernel(plan, mode):
+    """Name of the forward gather kernel the plan runs, as the traffic summaries list it."""
+    kind = plan.info()[0]
+    name = GATHER_KERNELS.get(kind, "gather_f64_kernel")
+    if kind in ("lds", "stream", "mfma"):
+        name += "<float>" if mode == "f32" else "<unsigned short>"
+    return name
+
+
 def gm_traffic():
     """HBM bytes of one general-motion gather launch (gather + panel-range sum), or None."""
     g = measured_traffic("gm_gather_kernel", GM_TRAFFIC_PROFILE)
@@ -108,7 +121,7 @@ def bench_low_obs(c_full, d, steps, sync, n_obs=8):
         s_ms = st["source"][0] / st["source"][1]
         alg = 8 * esz * (c.n_tau + 3) * c.n_panels + 52 * n_obs * c.n_panels + 4 * int(plan.window.n_t.sum())
         gbs = alg / (g_ms * 1e-3)
-        kern = "gather_lds_kernel<float>" if mode == "f32" else "gather_lds_kernel<unsigned short>"
+        kern = gather_kernel(plan, mode)
         out[mode] = {"units": U, "gather_ms": g_ms, "reduce_ms": r_ms, "source_ms": s_ms,
                      "gather_units_per_s": U / (g_ms * 1e-3),
                      "roofline": {"bound": "hbm", "kernel": kern, "achieved": gbs / 1e9, "peak": HBM_PEAK / 1e9,
@@ -305,6 +318,23 @@ def bench_batch(replays, sync):
     ev[2].record()
     sync()
     fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    # the same adjoint as 64 single-case launches: HIP events around all of them back to back, and the
+    # sum of their transposed-gather and source-adjoint stage times (kernel time without launch gaps)
+    grads = [pl.adjoint(*d, gp) for pl, d, gp in zip(plans, inputs, batch.grad_p)]
+    for pl in plans:
+        pl.profile(True)
+    ev[0].record()
+    for pl, d, gp, g in zip(plans, inputs, batch.grad_p, grads):
+        pl.adjoint(*d, gp, out=g)
+    ev[1].record()
+    sync()
+    adj_single_ms = ev[0].elapsed_time(ev[1])
+    adj_single_stage_ms = 0.0
+    for pl in plans:
+        st = pl.profile_read()
+        adj_single_stage_ms += st["adj_gather"][0] + st["source_adj"][0]
+        pl.profile(False)
+    del grads
     p_b = [t.double().cpu().numpy() for t in batch.p_out]
     del graph, batch
     del plans
@@ -331,11 +361,13 @@ def bench_batch(replays, sync):
            "observers": [c.n_obs for c in cases],
            "units_per_step": U, "ms_per_step": ms, "value": U / (ms * 1e-3),
            "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+           "adjoint_64_single_launches_ms": adj_single_ms, "adjoint_64_single_stage_sum_ms": adj_single_stage_ms,
            "plain_f64_64_launches": {"ms_per_step": t_plain * 1e3, "value": U / t_plain},
            "speedup_vs_plain_f64": t_plain * 1e3 / ms, "max_rel_l2_vs_plain_f64": max(errs),
            "work_items": info["items"], "grid": info["grid"], "autotune": tune}
     log(f"[bench] batch: {ms:.2f} ms/step ({U / (ms * 1e-3):.3e} units/s; forward {fwd_ms:.1f} ms, adjoint "
-        f"{adj_ms:.1f} ms) vs 64 plain FP64 steps {t_plain * 1e3:.1f} ms; max rel L2 vs FP64 {max(errs):.3e}")
+        f"{adj_ms:.1f} ms; 64 single-case adjoints {adj_single_ms:.1f} ms, their kernels {adj_single_stage_ms:.1f} ms) "
+        f"vs 64 plain FP64 steps {t_plain * 1e3:.1f} ms; max rel L2 vs FP64 {max(errs):.3e}")
     del inputs
     torch.cuda.empty_cache()
     return out
@@ -543,7 +575,8 @@ def main():
     dom = "gather" if avg["gather"] >= avg["adj_gather"] else "adj_gather"
     t_dom = avg[dom] * 1e-3
     achieved = FLOP_PER_UNIT * U / t_dom / 1e12
-    dom_kernel = "gather_lds_kernel<float>" if dom == "gather" else "adj_gather_dpp_kernel"
+    fwd_kernel = gather_kernel(plan, "f32")
+    dom_kernel = fwd_kernel if dom == "gather" else "adj_gather_dpp_kernel"
     # algorithmic bytes per launch: coefficients (8 channels FP32 over NS) + pair records + output/input signal
     NSd = ((c.n_tau + 12 + 63) // 64) * 64
     alg_bytes = 8 * 4 * c.n_panels * NSd + 64 * c.n_obs * c.n_panels + 4 * c.n_obs * int(nt.max())
@@ -553,7 +586,7 @@ def main():
                 "algorithmic_bytes": alg_bytes,
                 "frac_of_nonpacked_fp32_peak": achieved * 1e12 / FP32_NONPACKED_PEAK,
                 "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom],
-                "other_gather": {"kernel": "adj_gather_dpp_kernel" if dom == "gather" else "gather_lds_kernel<float>",
+                "other_gather": {"kernel": "adj_gather_dpp_kernel" if dom == "gather" else fwd_kernel,
                                  "avg_launch_ms": avg["adj_gather" if dom == "gather" else "gather"],
                                  "frac": FLOP_PER_UNIT * U / (avg["adj_gather" if dom == "gather" else "gather"]
                                                               * 1e-3) / FP32_PEAK}}

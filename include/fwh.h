@@ -117,13 +117,16 @@ int fwh_plan_create(const fwh_setup_args *args, fwh_plan **out, size_t *workspac
 int fwh_setup(fwh_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Launch choices of the FP32/BF16 forward gather, for tests and measurements
- * (the defaults pick by themselves).  gather: FWH_GATHER_AUTO (the first of the
- * following that applies), FWH_GATHER_MFMA (channel combine on the matrix
+ * (the defaults pick by themselves).  gather: FWH_GATHER_AUTO (the first of
+ * STREAM, LDS, MFMA, DIRECT that applies), FWH_GATHER_STREAM (whole coefficient
+ * rows of each panel staged once, two waves per observer: at most 8 observers
+ * and 32 x 61 samples per observer; for cases bound by HBM), FWH_GATHER_LDS
+ * (coefficient windows of a 32-observer tile staged in LDS; needs one panel's
+ * window over a tile to fit), FWH_GATHER_MFMA (channel combine on the matrix
  * cores for 32 observers x 16 samples at a time, then the taps; needs a tile's
- * delay-index spread below about 260 samples), FWH_GATHER_LDS (coefficient
- * windows staged in LDS; needs one panel's window over a tile to fit) or
- * FWH_GATHER_DIRECT (direct loads); MFMA and LDS make fwh_setup fail with
- * FWH_EINVAL when they do not apply.
+ * delay-index spread below about 260 samples) or FWH_GATHER_DIRECT (direct
+ * loads); STREAM, LDS and MFMA make fwh_setup fail with FWH_EINVAL when they do
+ * not apply.
  * splits: number of panel ranges summed separately and then added in fixed
  * order (0: chosen by fwh_setup to fill whole rounds of resident workgroups;
  * else 1 .. min(256, ceil(P/128)), FWH_ESIZE beyond).  Every choice gives the
@@ -135,9 +138,10 @@ int fwh_setup(fwh_plan *plan, void *workspace, size_t workspace_bytes, void *str
 #define FWH_GATHER_LDS     1
 #define FWH_GATHER_DIRECT  2
 #define FWH_GATHER_MFMA    3
+#define FWH_GATHER_STREAM  4
 int fwh_plan_tune(fwh_plan *plan, int32_t gather, int32_t splits);
-/* The gather kernel and panel-split count fwh_setup chose (FWH_GATHER_MFMA,
- * _LDS or _DIRECT; FWH_GATHER_AUTO and 1 in FWH_MODE_F64).  FWH_ESTATE before
+/* The gather kernel and panel-split count fwh_setup chose (FWH_GATHER_STREAM,
+ * _LDS, _MFMA or _DIRECT; FWH_GATHER_AUTO and 1 in FWH_MODE_F64).  FWH_ESTATE before
  * fwh_setup.  Either pointer may be NULL. */
 int fwh_plan_info(const fwh_plan *plan, int32_t *gather, int32_t *splits);
 
@@ -213,8 +217,9 @@ int fwh_batch_tune(fwh_batch *batch, double item_units, int32_t blocks_per_cu);
  * window overlap; the autotuner of the Python binding picks both per class of
  * case sizes. */
 int fwh_batch_tune_case(fwh_batch *batch, int32_t case_index, double item_units, int32_t rows);
-/* The forward gather the batch runs for all its cases: FWH_GATHER_MFMA when
- * every case's windows fit it, else FWH_GATHER_LDS. */
+/* The forward gather the batch runs for all its cases: FWH_GATHER_LDS when
+ * every case's windows fit it, unless every plan was tuned to FWH_GATHER_MFMA
+ * (fwh_plan_tune); FWH_GATHER_MFMA when only it fits them all. */
 int fwh_batch_gather(const fwh_batch *batch, int32_t *gather);
 /* Build the work list and upload descriptors and list into the workspace
  * (>= workspace_bytes, 256-byte aligned) on `stream`; synchronises `stream`. */

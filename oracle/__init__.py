@@ -90,6 +90,9 @@ def _load():
         _lib.orc_forward_sources.restype = ctypes.c_int
         _lib.orc_adjoint.argtypes = [i64, i64, i64, D, D, D, D, f64, f64, f64, f64, D, D, D, D, i64, D, D, D]
         _lib.orc_adjoint.restype = ctypes.c_int
+        _lib.orc_adjoint_panels.argtypes = [i64, i64, i64, D, D, D, D, f64, f64, f64, f64, I, i64, D, D, D, D, i64,
+                                            D, D, D]
+        _lib.orc_adjoint_panels.restype = ctypes.c_int
         _lib.orc_adjoint_sources.argtypes = [i64, i64, i64, D, D, D, D, f64, f64, f64, f64, D, i64, D, D]
         _lib.orc_adjoint_sources.restype = ctypes.c_int
         _lib.orc_gm_window.argtypes = [i64, i64, i64, D, D, f64, f64, f64, D, I]
@@ -252,6 +255,31 @@ def adjoint(surf, x_obs, mach, aoa_deg, dtau, tau0, rho, u, pp, gbar):
     _check(lib.orc_adjoint(P, O, N, _d(y), _d(nrm), _d(dS), _d(x_obs), float(mach), float(aoa_deg), float(dtau),
                            float(tau0), _d(rho_pm), _d(u_pm), _d(pp_pm), _d(gbar), gbar.shape[1], _d(g_r), _d(g_u),
                            _d(g_p)))
+    return (np.ascontiguousarray(g_r.T), np.ascontiguousarray(np.transpose(g_u, (0, 2, 1))),
+            np.ascontiguousarray(g_p.T))
+
+
+def adjoint_panels(surf, x_obs, mach, aoa_deg, dtau, tau0, rho, u, pp, gbar, panel_idx):
+    """adjoint() restricted to the panels panel_idx: the observer windows come
+    from the whole surface, the gradients of each listed panel from its own data.
+    Returns time-major (g_rho [N,n], g_u [3,N,n], g_p [N,n]), columns in the
+    order of panel_idx."""
+    lib = _load()
+    y, nrm, dS, x_obs = _f64(surf.y), _f64(surf.normal), _f64(surf.dS), _f64(x_obs)
+    N, P = np.asarray(rho).shape
+    O = x_obs.shape[0]
+    idx = np.ascontiguousarray(np.asarray(panel_idx, dtype=np.int64))
+    n = idx.shape[0]
+    if n < 1 or idx.min() < 0 or idx.max() >= P:
+        raise ValueError(f"panel_idx must list panels in [0, {P})")
+    gbar = _f64(gbar)
+    g_r = np.empty((n, N)); g_u = np.empty((3, n, N)); g_p = np.empty((n, N))
+    rho_pm = _f64(np.asarray(rho)[:, idx].T)
+    u_pm = _f64(np.transpose(np.asarray(u)[:, :, idx], (0, 2, 1)))
+    pp_pm = _f64(np.asarray(pp)[:, idx].T)
+    _check(lib.orc_adjoint_panels(P, O, N, _d(y), _d(nrm), _d(dS), _d(x_obs), float(mach), float(aoa_deg),
+                                  float(dtau), float(tau0), _i(idx), n, _d(rho_pm), _d(u_pm), _d(pp_pm), _d(gbar),
+                                  gbar.shape[1], _d(g_r), _d(g_u), _d(g_p)))
     return (np.ascontiguousarray(g_r.T), np.ascontiguousarray(np.transpose(g_u, (0, 2, 1))),
             np.ascontiguousarray(g_p.T))
 

@@ -332,7 +332,8 @@ static int forward_core(const orc_case *cs, int src_mode, const double *a0, cons
                         const int64_t *obs_idx, int64_t n_sel, double *out, int64_t nt_stride)
 {
     const int64_t P = cs->P, N = cs->N, O = cs->O;
-    if (P < 1 || O < 1 || N < 4 || !(cs->mach > 0.0 && cs->mach < 1.0) || !(cs->dtau > 0.0)) return -3;
+    if (P < 1 || cs->P < 1 || O < 1 || N < 4 || !(cs->mach > 0.0 && cs->mach < 1.0) || !(cs->dtau > 0.0))
+        return -3;
     double *t_start = xmalloc((size_t)O);
     int64_t *n_t = (int64_t *)malloc((size_t)O * sizeof(int64_t));
     if (window_for_case(cs, t_start, n_t) != 0) { free(t_start); free(n_t); return -1; }
@@ -467,11 +468,21 @@ static void fd_transpose_add(int64_t N, const double *v, double h, double *out)
 /* Gradient of J with dJ/dp'(o,k) = gbar[o][k] (k < N_t(o); padding ignored).
  * mode 0: raw inputs (rho, u, p') -> (g_rho, g_u, g_p), panel-major.
  * mode 1: source terms -> (Qbar, Lbar), panel-major (the linear part). */
+/* Gradients of the panels pidx[0..np) (all P panels in order when pidx is NULL).
+ * The window comes from every panel of the case; the data and the outputs are
+ * those of the listed panels only ([np][N] per variable), since the gradient of
+ * a panel depends on its own data and the observer windows alone. */
 static int adjoint_core(const orc_case *cs, int mode, const double *rho, const double *u, const double *pp,
-                        const double *gbar, int64_t nt_stride, double *g0, double *g1, double *g2)
+                        const double *gbar, int64_t nt_stride, const int64_t *pidx, int64_t np,
+                        double *g0, double *g1, double *g2)
 {
-    const int64_t P = cs->P, N = cs->N, O = cs->O;
-    if (P < 1 || O < 1 || N < 4 || !(cs->mach > 0.0 && cs->mach < 1.0) || !(cs->dtau > 0.0)) return -3;
+    const int64_t N = cs->N, O = cs->O;
+    const int64_t P = pidx ? np : cs->P;  /* panels computed (data and output rows) */
+    if (pidx)
+        for (int64_t j = 0; j < np; ++j)
+            if (pidx[j] < 0 || pidx[j] >= cs->P) return -3;
+    if (P < 1 || cs->P < 1 || O < 1 || N < 4 || !(cs->mach > 0.0 && cs->mach < 1.0) || !(cs->dtau > 0.0))
+        return -3;
     double *t_start = xmalloc((size_t)O);
     int64_t *n_t = (int64_t *)malloc((size_t)O * sizeof(int64_t));
     if (window_for_case(cs, t_start, n_t) != 0) { free(t_start); free(n_t); return -1; }
@@ -484,15 +495,16 @@ static int adjoint_core(const orc_case *cs, int mode, const double *rho, const d
         double *work = xmalloc((size_t)16 * N);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < P; ++p) {
+            const int64_t pg = pidx ? pidx[p] : p;  /* panel of the case (geometry) */
             double *Sbar = work;               /* 8 channels: Qdot, Q, Ldot_1..3, L_1..3 */
             double *fbar = work + 8 * N;
             double *tmp = work + 9 * N;        /* 3N */
             double *srcbar = work + 12 * N;    /* Qbar, Lbar_1..3 */
             memset(Sbar, 0, sizeof(double) * 8 * (size_t)N);
-            pair_ctx c = {cs->dS[p], cs->mach, aoa, cs->dtau, cs->tau0, N};
+            pair_ctx c = {cs->dS[pg], cs->mach, aoa, cs->dtau, cs->tau0, N};
             for (int64_t o = 0; o < O; ++o) {
                 double R, Rs, Rhat[3], MR, D, a[8];
-                pair_geometry(cs->x_obs + 3 * o, cs->y + 3 * p, cs->mach, aoa, &R, &Rs, Rhat, &MR, &D);
+                pair_geometry(cs->x_obs + 3 * o, cs->y + 3 * pg, cs->mach, aoa, &R, &Rs, Rhat, &MR, &D);
                 pair_integrand_coeffs(&c, R, Rhat, MR, a);
                 spline_eval_transpose(N, cs->tau0, cs->dtau, t_start[o], D, n_t[o], gbar + o * nt_stride, fbar, tmp);
                 for (int ch = 0; ch < 8; ++ch)
@@ -513,7 +525,7 @@ static int adjoint_core(const orc_case *cs, int mode, const double *rho, const d
                 continue;
             }
             /* chain rule through Q = rho u.n - U0.n, L_i = p' n_i + rho (u_i - U0_i) u.n */
-            const double *nr = cs->normal + 3 * p;
+            const double *nr = cs->normal + 3 * pg;
             for (int64_t n = 0; n < N; ++n) {
                 const double r = rho[p * N + n];
                 const double uu[3] = {u[p * N + n], u[(P + p) * N + n], u[(2 * P + p) * N + n]};
@@ -540,7 +552,17 @@ int orc_adjoint(int64_t P, int64_t O, int64_t N, const double *y, const double *
                 double *g_rho, double *g_u, double *g_p)
 {
     orc_case cs = {P, O, N, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0};
-    return adjoint_core(&cs, 0, rho, u, pp, gbar, nt_stride, g_rho, g_u, g_p);
+    return adjoint_core(&cs, 0, rho, u, pp, gbar, nt_stride, NULL, 0, g_rho, g_u, g_p);
+}
+
+int orc_adjoint_panels(int64_t P, int64_t O, int64_t N, const double *y, const double *normal, const double *dS,
+                       const double *x_obs, double mach, double aoa_deg, double dtau, double tau0,
+                       const int64_t *pidx, int64_t np, const double *rho, const double *u, const double *pp,
+                       const double *gbar, int64_t nt_stride, double *g_rho, double *g_u, double *g_p)
+{
+    if (!pidx || np < 1) return -3;
+    orc_case cs = {P, O, N, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0};
+    return adjoint_core(&cs, 0, rho, u, pp, gbar, nt_stride, pidx, np, g_rho, g_u, g_p);
 }
 
 int orc_adjoint_sources(int64_t P, int64_t O, int64_t N, const double *y, const double *normal, const double *dS,
@@ -548,7 +570,7 @@ int orc_adjoint_sources(int64_t P, int64_t O, int64_t N, const double *y, const 
                         const double *gbar, int64_t nt_stride, double *Qbar, double *Lbar)
 {
     orc_case cs = {P, O, N, y, normal, dS, x_obs, mach, aoa_deg, dtau, tau0};
-    return adjoint_core(&cs, 1, NULL, NULL, NULL, gbar, nt_stride, Qbar, Lbar, NULL);
+    return adjoint_core(&cs, 1, NULL, NULL, NULL, gbar, nt_stride, NULL, 0, Qbar, Lbar, NULL);
 }
 
 /* ============================================ general motion (Sec. II B) */

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libfwh.so")
 
 FWH_OK, FWH_EINVAL, FWH_EDOMAIN, FWH_EWINDOW, FWH_ESIZE, FWH_EWORKSPACE, FWH_EHIP, FWH_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 FWH_F64, FWH_F32 = 0, 1
-GATHER_AUTO, GATHER_LDS, GATHER_DIRECT, GATHER_MFMA = 0, 1, 2, 3
-GATHERS = {"auto": GATHER_AUTO, "lds": GATHER_LDS, "direct": GATHER_DIRECT, "mfma": GATHER_MFMA}
+GATHER_AUTO, GATHER_LDS, GATHER_DIRECT, GATHER_MFMA, GATHER_STREAM = 0, 1, 2, 3, 4
+GATHERS = {"auto": GATHER_AUTO, "lds": GATHER_LDS, "direct": GATHER_DIRECT, "mfma": GATHER_MFMA,
+           "stream": GATHER_STREAM}
 MODE_F64, MODE_F32, MODE_BF16 = 0, 1, 2
 MODES = {"f64": MODE_F64, "f32": MODE_F32, "bf16": MODE_BF16}
 ERROR_NAMES = {FWH_EINVAL: "FWH_EINVAL", FWH_EDOMAIN: "FWH_EDOMAIN", FWH_EWINDOW: "FWH_EWINDOW",
@@ -176,7 +177,7 @@ class Plan:
 
     y, normal [P,3], dS [P], x_obs [O,3]: geometry (host arrays);
     mach, aoa_deg, dtau, tau0, n_tau: flow and time grid; mode: 'f64' | 'f32' | 'bf16';
-    gather: forward gather kernel of the FP32/BF16 modes, 'auto' | 'mfma' | 'lds' | 'direct';
+    gather: forward gather kernel of the FP32/BF16 modes, 'auto' | 'stream' | 'lds' | 'mfma' | 'direct';
     splits: panel splits of that gather (0: chosen at setup).
     """
 
@@ -220,7 +221,8 @@ class Plan:
         """(gather kernel, panel splits) chosen at setup: ('mfma' | 'lds' | 'direct' | 'f64', splits)."""
         g, s = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().fwh_plan_info(self._h, ctypes.byref(g), ctypes.byref(s)))
-        return {GATHER_LDS: "lds", GATHER_DIRECT: "direct", GATHER_MFMA: "mfma"}.get(g.value, "f64"), int(s.value)
+        names = {GATHER_LDS: "lds", GATHER_DIRECT: "direct", GATHER_MFMA: "mfma", GATHER_STREAM: "stream"}
+        return names.get(g.value, "f64"), int(s.value)
 
     def profile(self, enable: bool = True):
         """Bracket every stage of this plan with HIP events on its stream."""
@@ -463,7 +465,7 @@ def autotune(batch: "Batch", candidates=None, bpc_candidates=None, reps=2, cache
     cache = json.load(open(cache_path)) if cache_path and os.path.exists(cache_path) else {}
     groups = {}
     for i, pl in enumerate(batch.plans):
-        groups.setdefault(size_class(pl), []).append(i)
+        groups.setdefault(f"{batch.gather}|{size_class(pl)}", []).append(i)
     out = {"classes": {}}
     for key, idx in groups.items():
         if key in cache:

@@ -33,7 +33,6 @@ int fail(int code, const char *fmt, ...) {
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 
-
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 }  // namespace
@@ -56,6 +55,7 @@ struct fwh_plan {
     int lds_nw = 0, lds_pt = 0;  // staged window length and panels per stage of the LDS gather (0: not usable)
     int wmax = 0;                // widest delay-index window over a tile of observers
     int mfma_bpc = 0;            // resident blocks per CU of the matrix-core gather (0: not usable)
+    int stream_bpc = 0;          // resident blocks per CU of the streaming gather (0: not usable)
     bool ready = false;
     // workspace layout (byte offsets) and binding
     size_t off_y = 0, off_n = 0, off_dS = 0, off_x = 0, off_D = 0, off_dmm = 0, off_ts = 0, off_nt = 0, off_cp = 0;
@@ -312,8 +312,16 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit
         pl->wmax = wmax;
         pl->mfma_bpc = fwh::gather_mfma_blocks_per_cu(ctype, wmax);
-        // kernel: the matrix-core gather when its Y tile fits, else the LDS-staged one, else direct loads
+        pl->stream_bpc = O <= fwh::kLdsWaves ? fwh::gather_stream_blocks_per_cu(ctype, pl->NS, pl->n_t_max) : 0;
+        // kernel: the streaming gather for a few observers, else the LDS-staged one when a panel's
+        // window over a tile fits its staging, else the matrix-core one, else direct loads
         switch (pl->gather_variant) {
+            case FWH_GATHER_STREAM:
+                if (pl->stream_bpc <= 0)
+                    return fail(FWH_EINVAL, "fwh_setup: the streaming gather takes at most %d observers and %d "
+                                            "samples per observer", fwh::kLdsWaves, 32 * fwh::kLdsLanesOut);
+                pl->gather_kind = FWH_GATHER_STREAM;
+                break;
             case FWH_GATHER_MFMA:
                 if (pl->mfma_bpc <= 0)
                     return fail(FWH_EINVAL, "fwh_setup: the delay windows (%d samples) are too wide for the "
@@ -328,8 +336,10 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
                 break;
             case FWH_GATHER_DIRECT: pl->gather_kind = FWH_GATHER_DIRECT; break;
             default:
-                pl->gather_kind = pl->mfma_bpc > 0 ? FWH_GATHER_MFMA
-                                                   : (pl->lds_pt > 0 ? FWH_GATHER_LDS : FWH_GATHER_DIRECT);
+                pl->gather_kind = pl->stream_bpc > 0 ? FWH_GATHER_STREAM
+                                  : pl->lds_pt > 0   ? FWH_GATHER_LDS
+                                  : pl->mfma_bpc > 0 ? FWH_GATHER_MFMA
+                                                     : FWH_GATHER_DIRECT;
         }
     }
     // panel splits of the tuned gathers.  A split's block takes P/s panels, so a launch of B*s blocks
@@ -340,7 +350,9 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     // idle), and enough of them that blocks of unequal work even out
     int64_t blocks;
     const bool tiled = !f64 && pl->gather_kind != FWH_GATHER_DIRECT;  // 32-observer x 244-sample blocks
-    if (tiled)
+    if (!f64 && pl->gather_kind == FWH_GATHER_STREAM)
+        blocks = 1;  // one block per split covers every observer and sample
+    else if (tiled)
         blocks = ((O + fwh::kObsTile - 1) / fwh::kObsTile) * ((pl->n_t_max + fwh::kLdsK - 1) / fwh::kLdsK);
     else
         blocks = ((O + fwh::kGatherObsPerBlock - 1) / fwh::kGatherObsPerBlock) *
@@ -350,7 +362,8 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         return hip_fail("fwh_setup: device query", e);
     const int ctype_s = pl->mode == FWH_MODE_F32 ? 1 : 2;
     const int64_t resident =
-        (int64_t)cus * (pl->gather_kind == FWH_GATHER_MFMA  ? pl->mfma_bpc
+        (int64_t)cus * (pl->gather_kind == FWH_GATHER_STREAM ? pl->stream_bpc
+                        : pl->gather_kind == FWH_GATHER_MFMA  ? pl->mfma_bpc
                         : pl->gather_kind == FWH_GATHER_LDS ? fwh::gather_lds_blocks_per_cu(ctype_s, pl->lds_nw,
                                                                                             pl->lds_pt)
                                                             : 2);
@@ -365,7 +378,7 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
     pl->splits = (int)s;
     if (!f64) {
         // one launch: a 1-D grid of at most 2^32 work-items
-        const int64_t threads = blocks * s * (tiled ? (int64_t)fwh::kLdsWaves * 64 : 256);
+        const int64_t threads = blocks * s * (tiled ? (int64_t)2 * fwh::kLdsWaves * 64 : 256);
         if (blocks * s > INT32_MAX || threads >= ((int64_t)1 << 32))
             return fail(FWH_ESIZE, "fwh_setup: %lld observers x %lld samples x %lld panel splits exceed one gather launch",
                         (long long)O, (long long)pl->n_t_max, (long long)s);
@@ -378,7 +391,7 @@ int fwh_plan_tune(fwh_plan *pl, int32_t gather, int32_t splits) {
     g_last_error.clear();
     if (!pl) return fail(FWH_EINVAL, "fwh_plan_tune: null plan");
     if (gather != FWH_GATHER_AUTO && gather != FWH_GATHER_LDS && gather != FWH_GATHER_DIRECT &&
-        gather != FWH_GATHER_MFMA)
+        gather != FWH_GATHER_MFMA && gather != FWH_GATHER_STREAM)
         return fail(FWH_EINVAL, "fwh_plan_tune: unknown gather variant %d", (int)gather);
     if (pl->mode == FWH_MODE_F64 && (gather != FWH_GATHER_AUTO || splits != 0))
         return fail(FWH_EINVAL, "fwh_plan_tune: the plain FP64 form has one gather and no panel splits");
@@ -437,7 +450,11 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
     } else {
         {
             StageScope sc(pl, FWH_STAGE_GATHER, st);
-            if (pl->gather_kind == FWH_GATHER_MFMA)
+            if (pl->gather_kind == FWH_GATHER_STREAM)
+                e = fwh::launch_gather_stream(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                              pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O,
+                                              pl->NS, pl->n_t_max, pl->splits, pl->at<float>(pl->off_part), st);
+            else if (pl->gather_kind == FWH_GATHER_MFMA)
                 e = fwh::launch_gather_mfma(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
                                             pl->at<int2>(pl->off_tw), pl->at<int32_t>(pl->off_nt),
                                             pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
@@ -560,7 +577,7 @@ struct fwh_batch {
     std::vector<double> case_units;    // per case: target panel-observer-samples per forward item
     std::vector<int> case_rows;        // per case: rows of 61 samples per block (matrix-core gather)
     int64_t max_items = 0, n_items = 0, units = 0, grid = 0;
-    int64_t max_adj_items = 0, n_adj_items = 0, grid_adj = 0;
+    int64_t max_adj_items = 0, n_adj_items = 0;
     int64_t blocks_src = 0, blocks_srcg = 0, blocks_red = 0, blocks_pad = 0, waves_adj = 0, blocks_sadj = 0,
             blocks_sadjg = 0;
     size_t shmem = 0;
@@ -603,7 +620,7 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
                       kbs = ceil_div(k.plan->n_t_max, 2 * fwh::kLdsLanesOut);
         max_items += tiles * kbs * k.plan->max_splits;
         const int64_t nib = ceil_div(k.plan->NS, fwh::kAdjSub * fwh::kLdsLanesOut);
-        max_adj_items += ceil_div(ceil_div(k.plan->P * nib, 4), fwh::kAdjItemGroups);
+        max_adj_items += ceil_div(k.plan->P * nib, 4);
     }
     if (max_adj_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many adjoint work items");
     if (max_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many work items");
@@ -615,18 +632,20 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
     b->mode = mode;
     b->max_items = max_items;
     b->max_adj_items = max_adj_items;
-    // the matrix-core gather when every case can take it, else the LDS-staged one
-    bool all_mfma = true, all_lds = true;
+    // the LDS-staged gather when every case can take it, unless every plan asked for the matrix-core
+    // one (fwh_plan_tune); the matrix-core gather when only it takes the windows of every case
+    bool all_mfma = true, all_lds = true, want_mfma = true;
     for (int c = 0; c < n; ++c) {
         all_mfma = all_mfma && cases[c].plan->mfma_bpc > 0;
         all_lds = all_lds && cases[c].plan->lds_pt > 0;
+        want_mfma = want_mfma && cases[c].plan->gather_variant == FWH_GATHER_MFMA;
         b->umax = std::max(b->umax, fwh::gather_mfma_umax(cases[c].plan->wmax));
     }
     if (!all_mfma && !all_lds) {
         delete b;
         return fail(FWH_EINVAL, "fwh_batch_create: no batched gather takes the delay windows of every case");
     }
-    b->kind = all_mfma ? FWH_GATHER_MFMA : FWH_GATHER_LDS;
+    b->kind = all_mfma && (want_mfma || !all_lds) ? FWH_GATHER_MFMA : FWH_GATHER_LDS;
     b->case_units.assign((size_t)n, b->item_units);
     b->case_rows.assign((size_t)n, fwh::kLdsSub);
     size_t off = 0;
@@ -639,7 +658,7 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
     b->off_idx = take((size_t)7 * (n + 1) * sizeof(int64_t));
     b->off_items = take((size_t)max_items * sizeof(int4));
     b->off_adj_items = take((size_t)max_adj_items * sizeof(int2));
-    b->off_counter = take(2 * sizeof(int));  // forward and adjoint work-list counters
+    b->off_counter = take(sizeof(int));  // forward work-list counter
     b->ws_bytes = off;
     *out = b;
     if (workspace_bytes) *workspace_bytes = off;
@@ -751,11 +770,11 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
                     const int64_t nk = std::min<int64_t>(kstep, ntm - kb * kstep);
                     items.push_back({(double)np * no * nk, make_int4(c, (int)t, (int)kb, (int)z)});
                 }
-        // transposed gather: items of kAdjItemGroups groups of 4 (panel, index block) waves, each wave
-        // costing O x 244 panel-observer-samples (the last item of a case may be partly empty)
-        const int64_t groups = ceil_div(P * nib, 4), n_adj = ceil_div(groups, fwh::kAdjItemGroups);
-        for (int64_t g = 0; g < n_adj; ++g) {
-            const int64_t waves = std::min<int64_t>(4 * fwh::kAdjItemGroups, P * nib - 4 * fwh::kAdjItemGroups * g);
+        // transposed gather: items of 4 (panel, index block) waves, each wave costing O x 244
+        // panel-observer-samples (the last item of a case may be partly empty)
+        const int64_t groups = ceil_div(P * nib, 4);
+        for (int64_t g = 0; g < groups; ++g) {
+            const int64_t waves = std::min<int64_t>(4, P * nib - 4 * g);
             adj_items.push_back({(double)waves * O, make_int2(c, (int)g)});
         }
         int64_t sum_nt = 0;
@@ -784,7 +803,6 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
     if ((e = hipGetDevice(&dev)) || (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
         return hip_fail("fwh_batch_bind: device query", e);
     b->grid = (int64_t)cus * b->blocks_per_cu;
-    b->grid_adj = (int64_t)cus * fwh::adj_gather_blocks_per_cu();
     b->ws = static_cast<char *>(workspace);
     if ((e = hipMemcpyAsync(b->at<fwh::BatchCase>(b->off_cases), desc.data(), desc.size() * sizeof(fwh::BatchCase),
                             hipMemcpyHostToDevice, st)) ||
@@ -825,8 +843,8 @@ int fwh_batch_adjoint(fwh_batch *b, void *stream_) {
     if (!b || !b->bound) return fail(FWH_ESTATE, "fwh_batch_adjoint: batch is not bound");
     hipError_t e = fwh::launch_batch_adjoint(b->in_dtype == FWH_F64 ? 0 : 1, b->at<fwh::BatchCase>(b->off_cases),
                                              batch_index(b), b->blocks_pad, b->at<int2>(b->off_adj_items),
-                                             (int)b->n_adj_items, b->at<int>(b->off_counter) + 1, (int)b->grid_adj,
-                                             b->blocks_sadj, b->blocks_sadjg, as_stream(stream_));
+                                             (int)b->n_adj_items, b->blocks_sadj, b->blocks_sadjg,
+                                             as_stream(stream_));
     if (e) return hip_fail("fwh_batch_adjoint", e);
     return FWH_OK;
 }
@@ -1111,7 +1129,6 @@ void fwh_gm_destroy(fwh_gm_plan *pl) {
 }
 
 const char *fwh_last_error(void) { return g_last_error.c_str(); }
-
 
 const char *fwh_version(void) { return "fwh-mi355x 0.1 (gfx950)"; }
 

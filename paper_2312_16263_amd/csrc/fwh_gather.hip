@@ -212,6 +212,11 @@ struct Stage<uint16_t> {
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
+// Row of observer o in the partial signal of split z ([splits][O][nt_max]).
+__device__ __forceinline__ float *partial_row(float *partial, int64_t z, int64_t O, int64_t o, int64_t nt_max) {
+    return partial + (z * O + o) * nt_max;
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 // a.lo * b.lo + a.hi * b.hi + c for two bfloat16 pairs (v_dot2_f32_bf16)
 __device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
@@ -221,10 +226,10 @@ __device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
 // Direct global -> LDS copy of `count` units of Stage::kBytesPerLoad bytes from
 // src (byte address of unit u: src + u*bytes, clamped to unit `last`) to LDS at
 // dst (unit u at dst + u*bytes), wave w handling 64-unit chunks w, w + 8, ...
-template <int BYTES>  // 16 or 4
+template <int BYTES, int WAVES = kLdsWaves>  // 16 or 4 bytes per lane; waves sharing the copy
 __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t last, unsigned char *dst, int count,
                                             int wv, int lane) {
-    for (int ci = wv; ci * 64 < count; ci += kLdsWaves) {
+    for (int ci = wv; ci * 64 < count; ci += WAVES) {
         int64_t u = (int64_t)ci * 64 + lane;
         u = u < last ? u : last;
         if constexpr (BYTES == 16)
@@ -245,9 +250,12 @@ __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t la
 // window position n0 - lo + 61 m + l (two vector LDS reads), fetches the
 // combined values of lanes l+1..l+3 by three wavefront shifts and applies the
 // four taps.
+// The two stage buffers are separate static LDS arrays (stA, stB): the compiler
+// can then tell that the direct global->LDS loads into one buffer do not alias
+// the LDS reads of the other, and does not make those reads wait for the loads.
 template <typename TS>
 __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, int64_t kb, int64_t z,
-                                                unsigned char *smem_raw) {
+                                                unsigned char *stA, unsigned char *stB) {
     const PairRec *__restrict__ rec = a.rec;
     const int2 *__restrict__ tw = a.tw;
     const int32_t *__restrict__ nt = a.nt;
@@ -260,7 +268,6 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     constexpr bool kBf = std::is_same<TS, uint16_t>::value;
     const size_t win_bytes = (size_t)2 * NW * EB;                    // one panel, both groups
     // stage buffer: PT windows, then PT x kObsTile records, then (BF16) PT x kObsTile split weights
-    const size_t buf_bytes = (size_t)PT * (win_bytes + kObsTile * (sizeof(PairRec) + (kBf ? sizeof(PairBf) : 0)));
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t k0 = kb * kLdsK;
@@ -272,10 +279,9 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     const int2 *twt = tw + t * P;
     const int64_t ot_last = (O - 1 - t * kObsTile) < kObsTile - 1 ? (O - 1 - t * kObsTile) : kObsTile - 1;
 
-    // issue the loads of the stage starting at panel ps into buffer b
-    auto fill = [&](int64_t ps, int b) {
+    // issue the loads of the stage starting at panel ps into the stage buffer `base`
+    auto fill = [&](int64_t ps, unsigned char *base) {
         const int np = (int)(pe - ps < PT ? pe - ps : PT);
-        unsigned char *base = smem_raw + (size_t)b * buf_bytes;
         for (int q = 0; q < np; ++q) {
             const int64_t p = ps + q;
             const int64_t start = (int64_t)twt[p].x + k0;
@@ -414,7 +420,6 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
         int cnt = 0;
-        int b = 0;
         bool flushed = false;  // some chunk sum is already in the outputs
         // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
         auto load_lo = [&](int64_t ps) {
@@ -423,19 +428,20 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         };
         int lo_cur = 0;
         if (pb < pe) {
-            fill(pb, 0);
+            fill(pb, stA);
             lo_cur = load_lo(pb);
         }
-        for (int64_t ps = pb; ps < pe; ps += PT, b ^= 1) {
+        // one stage from buffer `cur` while the next one is copied into `nxt`
+        auto stage = [&](int64_t ps, const unsigned char *cur, unsigned char *nxt) __attribute__((always_inline)) {
             const int np = (int)(pe - ps < PT ? pe - ps : PT);
             __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
             __syncthreads();                // ... and every wave's; the other buffer is free
             const int lo_stage = lo_cur;
             if (ps + PT < pe) {
-                fill(ps + PT, b ^ 1);
+                fill(ps + PT, nxt);
                 lo_cur = load_lo(ps + PT);
             }
-            const unsigned char *base = smem_raw + (size_t)b * buf_bytes;
+            const unsigned char *base = cur;
             const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
             for (int q = 0; q < np; ++q) {
                 const int lo = __builtin_amdgcn_readlane(lo_stage, q);
@@ -454,6 +460,10 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                     cnt = 0;
                 }
             }
+        };
+        for (int64_t ps = pb; ps < pe; ps += 2 * PT) {
+            stage(ps, stA, stB);
+            if (ps + PT < pe) stage(ps + PT, stB, stA);
         }
         // final sums; outputs past an observer's window are zero
 #pragma unroll
@@ -493,23 +503,26 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     }
 }
 
-template <typename TS>
+// SB: bytes of each of the two stage buffers (a size class chosen at setup)
+template <typename TS, int SB>
 __global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ __align__(16) unsigned char stA[SB];
+    __shared__ __align__(16) unsigned char stB[SB];
     // 1-D grid, block order (tile fastest, k block, split) regrouped per XCD
     const int64_t L = xcd_block(blockIdx.x, gridDim.x);
     const int64_t t = L % tiles, rest = L / tiles;
-    gather_lds_body<TS>(a, t, rest % kblocks, rest / kblocks, smem_raw);
+    gather_lds_body<TS>(a, t, rest % kblocks, rest / kblocks, stA, stB);
 }
 
 // Persistent batched gather: blocks pull work items (case, tile, k-block, split)
 // in list order (longest first) through an atomic counter until the list is
 // exhausted; every block ends when it draws an index past the list.
-template <typename TS>
+template <typename TS, int SB>
 __global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_persistent(const BatchCase *__restrict__ cases,
                                                                         const int4 *__restrict__ items,
                                                                         int n_items, int *__restrict__ counter) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ __align__(16) unsigned char stA[SB];
+    __shared__ __align__(16) unsigned char stB[SB];
     __shared__ int cur;
     for (;;) {
         __syncthreads();  // the previous item is finished with LDS
@@ -520,8 +533,158 @@ __global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_persistent(const Ba
         const int4 w = items[it];
         const int c = __builtin_amdgcn_readfirstlane(w.x);
         gather_lds_body<TS>(cases[c].gat, __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
-                            __builtin_amdgcn_readfirstlane(w.w), smem_raw);
+                            __builtin_amdgcn_readfirstlane(w.w), stA, stB);
     }
+}
+
+// Streaming gather for at most kLdsWaves observers: every panel's whole
+// coefficient rows (both channel groups, NS indices) are staged once into LDS by
+// direct global->LDS loads, double-buffered, and the block computes all samples
+// of every observer from them: waves w and w + 8 share observer w, wave w taking
+// the rows of 61 samples [0, NRH) and wave w + 8 the rows [NRH, 2 NRH), in
+// registers.  Each coefficient leaves HBM once per panel split, which is what an
+// HBM-bound case (few observers: about 4 bytes per panel-observer-sample against
+// 24 flop) needs; the tiled gathers re-read overlapping windows per block of 244
+// samples.  The two stage buffers are separate static arrays of BUF bytes (a
+// size class of NS), so that reads of one do not wait for the copies into the other.
+constexpr int kStreamWaves = 2 * kLdsWaves;
+template <typename TS, int NRH, int BUF>
+__global__ __launch_bounds__(kStreamWaves * 64) void gather_stream_kernel(GatherArgs a) {
+    __shared__ __align__(16) unsigned char stA[BUF];
+    __shared__ __align__(16) unsigned char stB[BUF];
+    using QT = typename Quad<TS>::T;
+    constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels of one group)
+    constexpr bool kBf = std::is_same<TS, uint16_t>::value;
+    const PairRec *__restrict__ rec = a.rec;
+    const int32_t *__restrict__ nt = a.nt;
+    const int64_t P = a.P, O = a.O, NS = a.NS, nt_max = a.nt_max, p_chunk = a.p_chunk;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int jo = wv & (kLdsWaves - 1), half = wv / kLdsWaves;  // observer and row half of this wave
+    const int64_t z = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t pb = z * p_chunk;
+    const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
+    const int64_t o_last = O - 1;
+    const size_t row_bytes = (size_t)NS * EB;  // one channel group of one panel
+    const bool valid = jo <= o_last;
+    const int ntw = valid ? nt[jo] : 0;
+    const int r0 = half * NRH;  // first row of this wave
+    int nrow = (ntw + kLdsLanesOut - 1) / kLdsLanesOut - r0;
+    nrow = __builtin_amdgcn_readfirstlane(nrow < 0 ? 0 : (nrow > NRH ? NRH : nrow));
+
+    auto fill = [&](int64_t p, unsigned char *base) {
+        const unsigned char *src = reinterpret_cast<const unsigned char *>(a.coef) + (size_t)p * 2 * row_bytes;
+        const int units = (int)(2 * row_bytes / 16);
+        copy_to_lds<16, kStreamWaves>(src, units - 1, base, units, wv, lane);
+        // records of the observers (slots past the last observer repeat it): 4 pieces of 16 bytes each
+        unsigned char *rb = base + 2 * row_bytes;
+        if (wv == 0 && lane < kLdsWaves * 4) {
+            const int64_t j = (lane >> 2) < o_last ? (lane >> 2) : o_last;
+            const float4 *sr = reinterpret_cast<const float4 *>(rec + j * P + p) + (lane & 3);
+            __builtin_amdgcn_global_load_lds((const void *)sr, (lds_ptr_t)rb, 16, 0, 0);
+        }
+        if constexpr (kBf) {
+            if (wv == 1 && lane < kLdsWaves * 2) {
+                const int64_t j = (lane >> 1) < o_last ? (lane >> 1) : o_last;
+                const uint4 *sb = reinterpret_cast<const uint4 *>(a.rbf + j * P + p) + (lane & 1);
+                __builtin_amdgcn_global_load_lds((const void *)sb, (lds_ptr_t)(rb + kLdsWaves * sizeof(PairRec)),
+                                                 16, 0, 0);
+            }
+        }
+    };
+
+    float acc[NRH];
+#pragma unroll
+    for (int r = 0; r < NRH; ++r) acc[r] = 0.f;
+    int cnt = 0;
+    bool flushed = false;
+    auto flush = [&](bool final_sums) {
+        if (!valid) return;
+        float *row = partial_row(a.partial, z, O, (int64_t)jo, nt_max);
+#pragma unroll
+        for (int r = 0; r < NRH; ++r) {
+            const int k = (r0 + r) * kLdsLanesOut + lane;
+            if (lane < kLdsLanesOut && k < nt_max) {
+                const float prev = (flushed && r < nrow) ? row[k] : 0.f;
+                const float v = r < nrow ? prev + acc[r] : 0.f;
+                row[k] = (!final_sums || k < ntw) ? v : 0.f;
+            }
+            acc[r] = 0.f;
+        }
+        flushed = true;
+    };
+    // panel p from buffer `cur` while panel p + 1 is copied into `nxt`
+    auto panel = [&](int64_t p, const unsigned char *cur, unsigned char *nxt) __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of panel p have landed
+        __syncthreads();                // ... and every wave's; the other buffer is free
+        if (p + 1 < pe) fill(p + 1, nxt);
+        if (valid) {
+            const int nr = nrow;
+            const float4 *R = reinterpret_cast<const float4 *>(cur + 2 * row_bytes + (size_t)jo * sizeof(PairRec));
+            const float4 W = R[2];
+            const QT *P0 = reinterpret_cast<const QT *>(cur) + __float_as_int(R[3].x) + r0 * kLdsLanesOut + lane;
+            const QT *P1 = P0 + NS;
+            float4 Ka, Kb;
+            uint4 Kh, Kl;
+            if constexpr (kBf) {
+                const uint4 *B = reinterpret_cast<const uint4 *>(cur + 2 * row_bytes + kLdsWaves * sizeof(PairRec)) +
+                                 jo * 2;
+                Kh = B[0];
+                Kl = B[1];
+            } else {
+                Ka = R[0];
+                Kb = R[1];
+            }
+#pragma unroll
+            for (int r = 0; r < NRH; ++r) {
+                if (r < nr) {
+                    float g;
+                    if constexpr (kBf) {
+                        const uint2 e0 = P0[r * kLdsLanesOut], e1 = P1[r * kLdsLanesOut];
+                        g = dot2_bf16(Kh.x, e0.x, 0.f);
+                        g = dot2_bf16(Kh.y, e0.y, g);
+                        g = dot2_bf16(Kh.z, e1.x, g);
+                        g = dot2_bf16(Kh.w, e1.y, g);
+                        g = dot2_bf16(Kl.x, e0.x, g);
+                        g = dot2_bf16(Kl.y, e0.y, g);
+                        g = dot2_bf16(Kl.z, e1.x, g);
+                        g = dot2_bf16(Kl.w, e1.y, g);
+                    } else {
+                        float c0[4], c1[4];
+                        Quad<TS>::unpack(P0[r * kLdsLanesOut], c0);
+                        Quad<TS>::unpack(P1[r * kLdsLanesOut], c1);
+                        g = Ka.x * c0[0];
+                        g = fmaf(Ka.y, c0[1], g);
+                        g = fmaf(Ka.z, c0[2], g);
+                        g = fmaf(Ka.w, c0[3], g);
+                        g = fmaf(Kb.x, c1[0], g);
+                        g = fmaf(Kb.y, c1[1], g);
+                        g = fmaf(Kb.z, c1[2], g);
+                        g = fmaf(Kb.w, c1[3], g);
+                    }
+                    const float g1 = from_next_lane(g);
+                    const float g2 = from_next_lane(g1);
+                    const float g3 = from_next_lane(g2);
+                    float ac = acc[r];
+                    ac = fmaf(W.x, g, ac);
+                    ac = fmaf(W.y, g1, ac);
+                    ac = fmaf(W.z, g2, ac);
+                    ac = fmaf(W.w, g3, ac);
+                    acc[r] = ac;
+                }
+            }
+        }
+        if (++cnt == kLdsChunk) {
+            flush(false);
+            cnt = 0;
+        }
+    };
+    if (pb < pe) fill(pb, stA);
+    for (int64_t p = pb; p < pe; p += 2) {
+        panel(p, stA, stB);
+        if (p + 1 < pe) panel(p + 1, stB, stA);
+    }
+    flush(true);
 }
 
 __global__ void reset_counter_kernel(int *counter) { counter[0] = 0; }
@@ -647,27 +810,20 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
     adj_gather_dpp_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
-// Persistent batched transposed gather: blocks of 4 waves pull items in list
-// order (longest first: the paper's greedy partition by size) through an atomic
-// counter until the list is exhausted.  Item (case c, g) covers the waves
-// [4 kAdjItemGroups g, 4 kAdjItemGroups (g + 1)) of case c, wave w being
-// (panel w / nib, index block w % nib); waves past the case's P * nib return at once.
-__global__ __launch_bounds__(256) void adj_gather_persistent(const BatchCase *__restrict__ cases,
-                                                             const int2 *__restrict__ items, int n_items,
-                                                             int *__restrict__ counter) {
-    __shared__ int cur;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (;;) {
-        __syncthreads();  // every wave has read the previous item
-        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(cur);
-        if (it >= n_items) break;
-        const int2 w = items[it];
-        const int c = __builtin_amdgcn_readfirstlane(w.x);
-        const int64_t g0 = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * kAdjItemGroups;
-        for (int g = 0; g < kAdjItemGroups; ++g) adj_gather_dpp_body(cases[c].adj, (g0 + g) * 4 + wv);
-    }
+// Batched transposed gather over a longest-first work list: block b runs item b,
+// (case c, group g) = the waves 4 g .. 4 g + 3 of case c, wave w being (panel
+// w / nib, index block w % nib); waves past the case's P * nib return at once.
+// The items are sorted by their work (the paper's greedy partition by size) and
+// blocks are dispatched in order, so every compute unit takes the longest item
+// left when one of its blocks ends.  (A persistent form pulling items through a
+// counter keeps the case arguments live across items: 193 registers per lane,
+// against 122 here.)
+__global__ __launch_bounds__(256) void adj_gather_listed(const BatchCase *__restrict__ cases,
+                                                         const int2 *__restrict__ items) {
+    const int2 w = items[blockIdx.x];
+    const int c = __builtin_amdgcn_readfirstlane(w.x);
+    const int64_t g = __builtin_amdgcn_readfirstlane(w.y);
+    adj_gather_dpp_body(cases[c].adj, g * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 // out[o][k] = sum_z partial[z][o][k] in fixed order.
@@ -725,22 +881,120 @@ hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf 
     const int64_t p_chunk = (P + splits - 1) / splits;
     const GatherArgs a{rec_op, rbf, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
     const int64_t tiles = (O + kObsTile - 1) / kObsTile, kblocks = (nt_max + kLdsK - 1) / kLdsK;
-    const dim3 n1((unsigned)(tiles * kblocks * splits));
-    const size_t shmem = gather_lds_shmem(coef_type, NW, PT);
-    if (coef_type == 1)
-        gather_lds_kernel<float><<<n1, dim3(kLdsWaves * 64), shmem, stream>>>(a, tiles, kblocks);
-    else
-        gather_lds_kernel<uint16_t><<<n1, dim3(kLdsWaves * 64), shmem, stream>>>(a, tiles, kblocks);
+    const dim3 n1((unsigned)(tiles * kblocks * splits)), blk(kLdsWaves * 64);
+    const int sb = gather_lds_stage_class(coef_type, NW, PT);
+#define FWH_LDS_LAUNCH(T, S) gather_lds_kernel<T, S><<<n1, blk, 0, stream>>>(a, tiles, kblocks)
+    if (coef_type == 1) {
+        switch (sb) {
+            case 8192: FWH_LDS_LAUNCH(float, 8192); break;
+            case 12288: FWH_LDS_LAUNCH(float, 12288); break;
+            case 16384: FWH_LDS_LAUNCH(float, 16384); break;
+            case 24576: FWH_LDS_LAUNCH(float, 24576); break;
+            case 32768: FWH_LDS_LAUNCH(float, 32768); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (sb) {
+            case 8192: FWH_LDS_LAUNCH(uint16_t, 8192); break;
+            case 12288: FWH_LDS_LAUNCH(uint16_t, 12288); break;
+            case 16384: FWH_LDS_LAUNCH(uint16_t, 16384); break;
+            case 24576: FWH_LDS_LAUNCH(uint16_t, 24576); break;
+            case 32768: FWH_LDS_LAUNCH(uint16_t, 32768); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef FWH_LDS_LAUNCH
     return hipGetLastError();
 }
 
-int gather_lds_blocks_per_cu(int coef_type, int NW, int PT) {
-    const size_t shmem = gather_lds_shmem(coef_type, NW, PT);
+// Stage buffer size classes of the streaming gather: both channel groups of a
+// panel's row (NS <= NSMAX indices) plus the records of kLdsWaves observers.
+constexpr int kStreamNs32[2] = {1216, 2496};   // FP32 storage
+constexpr int kStreamNs16[2] = {2496, 5056};   // BF16 storage
+constexpr int stream_buf(int eb, int nsmax, int rb) { return 2 * nsmax * eb + rb; }
+constexpr int kRb32 = kLdsWaves * (int)sizeof(PairRec);
+constexpr int kRb16 = kLdsWaves * (int)(sizeof(PairRec) + sizeof(PairBf));
+
+size_t gather_stream_shmem(int coef_type, int64_t NS) {
+    const int *cls = coef_type == 1 ? kStreamNs32 : kStreamNs16;
+    for (int i = 0; i < 2; ++i)
+        if (NS <= cls[i])
+            return 2 * (size_t)stream_buf(coef_type == 1 ? 16 : 8, cls[i], coef_type == 1 ? kRb32 : kRb16);
+    return 0;
+}
+
+// rows of 61 samples per wave (two waves per observer), 0 when an observer has more than 32 rows
+// (the row loop is fully unrolled with the accumulators in registers)
+int gather_stream_rows(int64_t nt_max) {
+    const int64_t r = (nt_max + kLdsLanesOut - 1) / kLdsLanesOut;
+    return r <= 16 ? 8 : r <= 32 ? 16 : 0;
+}
+
+// kernel of (storage, rows, NS class), null when the combination is not compiled
+template <typename TS>
+static const void *stream_kernel(int nr, int cls) {
+#define FWH_SK(N, C) reinterpret_cast<const void *>(&gather_stream_kernel<TS, N, C>)
+    constexpr bool f32 = std::is_same<TS, float>::value;
+    constexpr int eb = f32 ? 16 : 8, rb = f32 ? kRb32 : kRb16;
+    constexpr int c0 = stream_buf(eb, f32 ? kStreamNs32[0] : kStreamNs16[0], rb);
+    constexpr int c1 = stream_buf(eb, f32 ? kStreamNs32[1] : kStreamNs16[1], rb);
+    if (cls == 0) return nr == 8 ? FWH_SK(8, c0) : nr == 16 ? FWH_SK(16, c0) : nullptr;
+    return nr == 8 ? FWH_SK(8, c1) : nr == 16 ? FWH_SK(16, c1) : nullptr;
+#undef FWH_SK
+}
+
+static int stream_class(int coef_type, int64_t NS) {
+    const int *cls = coef_type == 1 ? kStreamNs32 : kStreamNs16;
+    return NS <= cls[0] ? 0 : NS <= cls[1] ? 1 : -1;
+}
+
+hipError_t launch_gather_stream(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int32_t *nt,
+                                const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits,
+                                float *partial, hipStream_t stream) {
+    const int nr = gather_stream_rows(nt_max), cls = stream_class(coef_type, NS);
+    if (O > kLdsWaves || nr == 0 || cls < 0) return hipErrorInvalidValue;
+    const void *k = coef_type == 1 ? stream_kernel<float>(nr, cls) : stream_kernel<uint16_t>(nr, cls);
+    if (!k) return hipErrorInvalidValue;
+    const int64_t p_chunk = (P + splits - 1) / splits;
+    GatherArgs a{rec_op, rbf, nullptr, nt, coef, P, O, NS, nt_max, p_chunk, 0, 0, splits, partial, 0};
+    void *args[] = {&a};
+    return hipLaunchKernel(k, dim3((unsigned)splits), dim3(kStreamWaves * 64), args, 0, stream);
+}
+
+int gather_stream_blocks_per_cu(int coef_type, int64_t NS, int64_t nt_max) {
+    const int nr = gather_stream_rows(nt_max), cls = stream_class(coef_type, NS);
+    if (nr == 0 || cls < 0) return 0;
+    const void *k = coef_type == 1 ? stream_kernel<float>(nr, cls) : stream_kernel<uint16_t>(nr, cls);
+    if (!k) return 0;
     int n = 0;
-    const hipError_t e =
-        coef_type == 1
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_lds_kernel<float>, kLdsWaves * 64, shmem)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gather_lds_kernel<uint16_t>, kLdsWaves * 64, shmem);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kStreamWaves * 64, 0);
+    return e == hipSuccess && n > 0 ? n : 0;
+}
+
+int gather_lds_stage_class(int coef_type, int NW, int PT) {
+    const size_t need = gather_lds_shmem(coef_type, NW, PT) / 2;  // one of the two stage buffers
+    for (int sb : {8192, 12288, 16384, 24576, 32768})
+        if (need <= (size_t)sb) return sb;
+    return 0;
+}
+
+template <typename T>
+static const void *lds_kernel_ptr(int sb) {
+    switch (sb) {
+        case 8192: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 8192>);
+        case 12288: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 12288>);
+        case 16384: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 16384>);
+        case 24576: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 24576>);
+        default: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 32768>);
+    }
+}
+
+int gather_lds_blocks_per_cu(int coef_type, int NW, int PT) {
+    const int sb = gather_lds_stage_class(coef_type, NW, PT);
+    if (sb == 0) return 1;
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, coef_type == 1 ? lds_kernel_ptr<float>(sb) : lds_kernel_ptr<uint16_t>(sb), kLdsWaves * 64, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -781,32 +1035,46 @@ hipError_t launch_batch_forward(int in_dtype, int coef_type, int umax, const Bat
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (umax > 0)
         e = launch_gather_mfma_persistent(coef_type, umax, cases, items, n_items, counter, grid, shmem, stream);
-    else if (coef_type == 1)
-        gather_lds_persistent<float><<<dim3((unsigned)grid), dim3(kLdsWaves * 64), shmem, stream>>>(cases, items,
-                                                                                                   n_items, counter);
-    else
-        gather_lds_persistent<uint16_t><<<dim3((unsigned)grid), dim3(kLdsWaves * 64), shmem, stream>>>(
-            cases, items, n_items, counter);
+    else {
+        // stage buffers of the widest case: shmem holds both of them
+        int sb = 0;
+        for (int c : {8192, 12288, 16384, 24576, 32768})
+            if (sb == 0 && shmem / 2 <= (size_t)c) sb = c;
+        const dim3 g((unsigned)grid), blk(kLdsWaves * 64);
+#define FWH_LDS_PERSIST(T, S) gather_lds_persistent<T, S><<<g, blk, 0, stream>>>(cases, items, n_items, counter)
+        if (coef_type == 1) {
+            switch (sb) {
+                case 8192: FWH_LDS_PERSIST(float, 8192); break;
+                case 12288: FWH_LDS_PERSIST(float, 12288); break;
+                case 16384: FWH_LDS_PERSIST(float, 16384); break;
+                case 24576: FWH_LDS_PERSIST(float, 24576); break;
+                case 32768: FWH_LDS_PERSIST(float, 32768); break;
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (sb) {
+                case 8192: FWH_LDS_PERSIST(uint16_t, 8192); break;
+                case 12288: FWH_LDS_PERSIST(uint16_t, 12288); break;
+                case 16384: FWH_LDS_PERSIST(uint16_t, 16384); break;
+                case 24576: FWH_LDS_PERSIST(uint16_t, 24576); break;
+                case 32768: FWH_LDS_PERSIST(uint16_t, 32768); break;
+                default: return hipErrorInvalidValue;
+            }
+        }
+#undef FWH_LDS_PERSIST
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     reduce_batched<<<dim3((unsigned)blocks_red), dim3(256), 0, stream>>>(cases, idx.red, idx.n);
     return hipGetLastError();
 }
 
-int adj_gather_blocks_per_cu() {
-    int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_gather_persistent, 256, 0);
-    return e == hipSuccess && n > 0 ? n : 1;
-}
-
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                const int2 *adj_items, int n_adj_items, int *counter, int grid_adj,
-                                int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream) {
+                                const int2 *adj_items, int n_adj_items, int64_t blocks_sadj, int64_t blocks_sadjg,
+                                hipStream_t stream) {
     pad_grad_batched<<<dim3((unsigned)blocks_pad), dim3(256), 0, stream>>>(cases, idx.pad, idx.n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    adj_gather_persistent<<<dim3((unsigned)grid_adj), dim3(256), 0, stream>>>(cases, adj_items, n_adj_items, counter);
+    adj_gather_listed<<<dim3((unsigned)n_adj_items), dim3(256), 0, stream>>>(cases, adj_items);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_batch_source_adjoint(in_dtype, cases, idx.sadj, idx.sadjg, idx.n, blocks_sadj, blocks_sadjg, stream);
 }

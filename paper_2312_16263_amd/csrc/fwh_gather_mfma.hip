@@ -81,6 +81,8 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
     const int YR = a.NW;      // row length (floats) of the Y tile
     const int rows = a.rows;  // rows of 61 samples per block
     float *__restrict__ partial = a.partial;
+    // the tile's pair records (and BF16 split weights) of one panel, two buffers after the Y tile
+    unsigned char *recs = reinterpret_cast<unsigned char *>(Y + kObsTile * YR);
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -110,19 +112,16 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
     const int nsub = rows_below(nt_wave);
     nobs = __builtin_amdgcn_readfirstlane(nobs);
 
-    // this wave's output element of observer slot j, row m (null outside the output)
-    auto out_ptr = [&](int j, int m) -> float * {
-        const int64_t o = tbase + j * kLdsWaves + wv;
-        const int64_t k = k0 + m * kLdsLanesOut + lane;
-        return (lane < kLdsLanesOut && o < O && k < nt_max) ? partial + (z * O + o) * nt_max + k : nullptr;
+    // this wave's outputs of observer slot j: the split's partial signal row (uniform) and the lane's
+    // sample offsets k0 + 61 m + lane; the row address is formed where it is used (an empty asm makes
+    // it opaque, so that it is not kept live across the panel loop)
+    auto out_row = [&](int j) -> float * {
+        float *row = partial + (z * O + tbase + j * kLdsWaves + wv) * nt_max;
+        asm volatile("" : "+s"(row));
+        return row;
     };
-
-    // matrix-unit weights (B operand) of this wave's observer half (wv & 1): FP32 channel lq and
-    // 4 + lq of observer 16 h + li; BF16 four high (lq < 2) or low parts, channel block lq & 1
-    const int h = wv & 1;
-    const int64_t ob = tbase + ((16 * h + li) < ot_last ? (16 * h + li) : ot_last);
-    const PairRec *__restrict__ rb = rec + ob * P;
-    const PairBf *__restrict__ rbb = a.rbf + ob * P;
+    const int k_lane = (int)k0 + lane;
+    const bool lane_out = lane < kLdsLanesOut;
 
     // window start and width of panel p (lane q of `win` holds panel ps + q)
     auto load_win = [&](int64_t ps) {
@@ -133,50 +132,95 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
         return 2 * ((width + kLdsLanesOut * nsub_blk + kLdsHalo + 15) / 16);
     };
 
+    // Records of a panel through registers: waves 0 and 1 load the 32 records (128 pieces of 16
+    // bytes), wave 2 in BF16 the 32 split weights (64 pieces), while the taps of the previous panel
+    // run, and write them to the panel's record buffer afterwards.  (Direct global->LDS loads would
+    // make the compiler wait for them before the taps' LDS reads.)
+    constexpr int kRecBytes = kObsTile * (int)sizeof(PairRec);
+    constexpr int kRecBuf = kRecBytes + (kBf ? kObsTile * (int)sizeof(PairBf) : 0);
+    uint4 rstage = make_uint4(0u, 0u, 0u, 0u);
+    auto load_recs = [&](int64_t p) {
+        if (wv < 2) {
+            const int u = wv * 64 + lane, j = u >> 2;
+            const int64_t o = tbase + (j < ot_last ? j : ot_last);
+            rstage = reinterpret_cast<const uint4 *>(rec + o * P + p)[u & 3];
+        } else if (kBf && wv == 2) {
+            const int j = lane >> 1;
+            const int64_t o = tbase + (j < ot_last ? j : ot_last);
+            rstage = reinterpret_cast<const uint4 *>(a.rbf + o * P + p)[lane & 1];
+        }
+    };
+    auto store_recs = [&](int b) {
+        unsigned char *rb = recs + b * kRecBuf;
+        if (wv < 2) reinterpret_cast<uint4 *>(rb)[wv * 64 + lane] = rstage;
+        else if (kBf && wv == 2) reinterpret_cast<uint4 *>(rb + kRecBytes)[lane] = rstage;
+    };
+
     MfmaA<TS> A[UMAX];
-    float b0 = 0.f, b1 = 0.f;
-    uint2 bb = make_uint2(0u, 0u);
-    // issue the operand loads of panel p (window start lo, width)
+    // issue the coefficient loads of panel p (window start lo, width) for this wave's units: a
+    // uniform base per channel group and 32-bit byte offsets within the panel's rows
+    const uint32_t row_bytes = (uint32_t)NS * 4u * (uint32_t)sizeof(TS);
+    const int ci_max = (int)NS - 1;
+    const int ci_lane = (int)k0 + li;
     auto load_ops = [&](int64_t p, int lo, int width) {
         const int nu = n_units(width);
-        if constexpr (kBf) {
-            bb = reinterpret_cast<const uint2 *>(rbb + p)[lq];
-        } else {
-            b0 = rb[p].K[lq];
-            b1 = rb[p].K[4 + lq];
-        }
+        const unsigned char *g0 = reinterpret_cast<const unsigned char *>(coef) + (size_t)p * 2 * row_bytes;
+        const unsigned char *g1 = g0 + row_bytes;
 #pragma unroll
         for (int s = 0; s < UMAX; ++s) {
             const int u = wv + kLdsWaves * s;
             if (u < nu) {
-                int64_t ci = (int64_t)lo + k0 + 16 * (u >> 1) + li;
-                ci = ci < NS - 1 ? ci : NS - 1;  // indices past the row are never read by valid outputs
+                int ci = lo + ci_lane + 16 * (u >> 1);
+                ci = ci < ci_max ? ci : ci_max;  // indices past the row are never read by valid outputs
                 if constexpr (kBf) {
-                    A[s].a = *reinterpret_cast<const uint2 *>(coef + ((p * 2 + (lq & 1)) * NS + ci) * 4);
+                    const uint32_t off = (uint32_t)ci * 8u;
+                    A[s].a = *reinterpret_cast<const uint2 *>(((lq & 1) ? g1 : g0) + off);
                 } else {
-                    A[s].a0 = coef[((p * 2) * NS + ci) * 4 + lq];
-                    A[s].a1 = coef[((p * 2 + 1) * NS + ci) * 4 + lq];
+                    const uint32_t off = ((uint32_t)ci * 4u + (uint32_t)lq) * 4u;
+                    A[s].a0 = *reinterpret_cast<const float *>(g0 + off);
+                    A[s].a1 = *reinterpret_cast<const float *>(g1 + off);
                 }
             }
         }
     };
-    // matrix units of the panel whose operands are loaded: Y[16 h + li][16 (u >> 1) + 4 lq + r]
-    auto mma_units = [&](int width) {
+    // matrix units of the panel whose operands are loaded: Y[16 h + li][16 (u >> 1) + 4 lq + r], the
+    // weights (B operand) of observer 16 h + li read from the record buffer: FP32 channels lq and
+    // 4 + lq; BF16 the high (lq < 2) or low parts of channel block lq & 1.  All products are issued
+    // before the first result is written.
+    const int h = wv & 1;
+    float *ybase = Y + (16 * h + li) * YR + 4 * lq;
+    auto mma_units = [&](int width, int b) {
         const int nu = n_units(width);
+        const unsigned char *rb = recs + b * kRecBuf;
+        uint2 bb = make_uint2(0u, 0u);
+        float b0 = 0.f, b1 = 0.f;
+        if constexpr (kBf) {
+            bb = reinterpret_cast<const uint2 *>(rb + kRecBytes + (16 * h + li) * sizeof(PairBf))[lq];
+        } else {
+            const float *K = reinterpret_cast<const float *>(rb + (16 * h + li) * sizeof(PairRec));
+            b0 = K[lq];
+            b1 = K[4 + lq];
+        }
+        // two units at a time: their products are issued before either result is written
 #pragma unroll
-        for (int s = 0; s < UMAX; ++s) {
-            const int u = wv + kLdsWaves * s;
-            if (u < nu) {
-                floatx4 d = {0.f, 0.f, 0.f, 0.f};
-                if constexpr (kBf) {
-                    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(shortx4, A[s].a),
-                                                                 __builtin_bit_cast(shortx4, bb), d, 0, 0, 0);
-                } else {
-                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s].a0, b0, d, 0, 0, 0);
-                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s].a1, b1, d, 0, 0, 0);
-                }
-                *reinterpret_cast<floatx4 *>(Y + (16 * h + li) * YR + 16 * (u >> 1) + 4 * lq) = d;
+        for (int s = 0; s < UMAX; s += 2) {
+            const bool v0 = wv + kLdsWaves * s < nu, v1 = wv + kLdsWaves * (s + 1) < nu;
+            floatx4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (kBf) {
+                if (v0)
+                    d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(shortx4, A[s].a),
+                                                                   __builtin_bit_cast(shortx4, bb), d0, 0, 0, 0);
+                if (v1)
+                    d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(shortx4, A[s + 1].a),
+                                                                   __builtin_bit_cast(shortx4, bb), d1, 0, 0, 0);
+            } else {
+                if (v0) d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s].a0, b0, d0, 0, 0, 0);
+                if (v1) d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s + 1].a0, b0, d1, 0, 0, 0);
+                if (v0) d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s].a1, b1, d0, 0, 0, 0);
+                if (v1) d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s + 1].a1, b1, d1, 0, 0, 0);
             }
+            if (v0) *reinterpret_cast<floatx4 *>(ybase + 16 * ((wv + kLdsWaves * s) >> 1)) = d0;
+            if (v1) *reinterpret_cast<floatx4 *>(ybase + 16 * ((wv + kLdsWaves * (s + 1)) >> 1)) = d1;
         }
     };
 
@@ -187,7 +231,7 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
         for (int m = 0; m < kLdsSub; ++m) acc[j][m] = 0.f;
 
     // the panel loop, compiled once per (observers, rows) of the wave; a wave without taps (NOBS = 0)
-    // still does its matrix units and meets every barrier
+    // still does its matrix units and record staging and meets every barrier
     auto panel_loop = [&](auto nobs_c, auto nsub_c) {
         constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
@@ -195,34 +239,35 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
         bool flushed = false;
         int2 win = make_int2(0, 0);
         if (pb < pe) {  // an empty split (possible when P < splits * p_chunk) loads nothing
+            load_recs(pb);
             win = load_win(pb);
             const int lo = __builtin_amdgcn_readlane(win.x, 0), hi = __builtin_amdgcn_readlane(win.y, 0);
             load_ops(pb, lo, hi - lo);
+            store_recs(0);
+            lds_barrier();
         }
         for (int64_t p = pb; p < pe; ++p) {
-            const int q = (int)((p - pb) & 63);
+            const int q = (int)((p - pb) & 63), b = (int)((p - pb) & 1);
             const int lo = __builtin_amdgcn_readlane(win.x, q), hi = __builtin_amdgcn_readlane(win.y, q);
-            mma_units(hi - lo);
-            // weights, taps and delay indices of this wave's observers at panel p (uniform loads)
-            float4 W[NOBS > 0 ? NOBS : 1];
-            int d[NOBS > 0 ? NOBS : 1];
-#pragma unroll
-            for (int j = 0; j < NOBS; ++j) {
-                const PairRec *r = rec + (tbase + j * kLdsWaves + wv) * P + p;
-                W[j] = *reinterpret_cast<const float4 *>(r->w);
-                d[j] = r->n0 - lo;
-            }
-            // next panel's window and operands, in flight during the taps
-            if (p + 1 < pe) {
+            mma_units(hi - lo, b);
+            // next panel's records, window and operands, in flight during the taps
+            const bool more = p + 1 < pe;
+            if (more) {
+                load_recs(p + 1);
                 if (q == 63) win = load_win(p + 1);
                 const int q1 = (int)((p + 1 - pb) & 63);
                 const int lo1 = __builtin_amdgcn_readlane(win.x, q1), hi1 = __builtin_amdgcn_readlane(win.y, q1);
                 load_ops(p + 1, lo1, hi1 - lo1);
             }
             lds_barrier();
+            // taps, weights and delay indices of this wave's observers from the record buffer
+            const unsigned char *rb = recs + b * kRecBuf;
 #pragma unroll
             for (int j = 0; j < NOBS; ++j) {
-                const float *y = Y + (j * kLdsWaves + wv) * YR + d[j] + lane;
+                const unsigned char *r = rb + (j * kLdsWaves + wv) * sizeof(PairRec);
+                const float4 W = *reinterpret_cast<const float4 *>(r + 32);
+                const int d = *reinterpret_cast<const int *>(r + 48) - lo;
+                const float *y = Y + (j * kLdsWaves + wv) * YR + d + lane;
 #pragma unroll
                 for (int m = 0; m < NSUB; ++m) {
                     const float g = y[m * kLdsLanesOut];
@@ -230,39 +275,43 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
                     const float g2 = next_lane(g1);
                     const float g3 = next_lane(g2);
                     float ac = acc[j][m];
-                    ac = fmaf(W[j].x, g, ac);
-                    ac = fmaf(W[j].y, g1, ac);
-                    ac = fmaf(W[j].z, g2, ac);
-                    ac = fmaf(W[j].w, g3, ac);
+                    ac = fmaf(W.x, g, ac);
+                    ac = fmaf(W.y, g1, ac);
+                    ac = fmaf(W.z, g2, ac);
+                    ac = fmaf(W.w, g3, ac);
                     acc[j][m] = ac;
                 }
             }
+            if (more) store_recs(b ^ 1);
             lds_barrier();
             if (++cnt == kMfmaChunk) {
 #pragma unroll
-                for (int j = 0; j < NOBS; ++j)
+                for (int j = 0; j < NOBS; ++j) {
+                    float *row = out_row(j);
 #pragma unroll
                     for (int m = 0; m < NSUB; ++m) {
-                        float *dst = out_ptr(j, m);
-                        if (dst) *dst = (flushed ? *dst : 0.f) + acc[j][m];
+                        const int k = k_lane + m * kLdsLanesOut;
+                        if (lane_out && k < nt_max) row[k] = (flushed ? row[k] : 0.f) + acc[j][m];
                         acc[j][m] = 0.f;
                     }
+                }
                 flushed = true;
                 cnt = 0;
             }
         }
-        // final sums; outputs past an observer's window are zero
+        // final sums; outputs past an observer's window are zero (only this block's `rows` rows: the
+        // next ones belong to the next k block)
 #pragma unroll
         for (int j = 0; j < kObsPerWave; ++j) {
-            const int64_t o = tbase + j * kLdsWaves + wv;
-            const int64_t ntl = o < O ? nt[o] : 0;
+            if (tbase + j * kLdsWaves + wv >= O) continue;
+            const int ntl = nt[tbase + j * kLdsWaves + wv];
+            float *row = out_row(j);
 #pragma unroll
             for (int m = 0; m < kLdsSub; ++m) {
-                float *dst = out_ptr(j, m);
-                if (dst) {
-                    const int64_t k = k0 + m * kLdsLanesOut + lane;
-                    const float prev = (j < NOBS && m < NSUB && flushed) ? *dst : 0.f;
-                    *dst = k < ntl ? prev + acc[j][m] : 0.f;
+                const int k = k_lane + m * kLdsLanesOut;
+                if (m < rows && lane_out && k < nt_max) {
+                    const float prev = (j < NOBS && m < NSUB && flushed) ? row[k] : 0.f;
+                    row[k] = k < ntl ? prev + acc[j][m] : 0.f;
                 }
             }
         }
@@ -278,12 +327,15 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
     if (nsub_blk == 0) {
         // no sample of this block lies in a window of the tile: zeros (every wave, no barrier)
 #pragma unroll
-        for (int j = 0; j < kObsPerWave; ++j)
+        for (int j = 0; j < kObsPerWave; ++j) {
+            if (tbase + j * kLdsWaves + wv >= O) continue;
+            float *row = out_row(j);
 #pragma unroll
             for (int m = 0; m < kLdsSub; ++m) {
-                float *dst = out_ptr(j, m);
-                if (dst) *dst = 0.f;
+                const int k = k_lane + m * kLdsLanesOut;
+                if (m < rows && lane_out && k < nt_max) row[k] = 0.f;
             }
+        }
         return;
     }
     if (nobs == 0 || nsub == 0) {
@@ -297,8 +349,10 @@ __device__ __forceinline__ void gather_mfma_body(const GatherArgs &a, int64_t t,
     }
 }
 
+// four waves per SIMD (two blocks per compute unit): at most 128 VGPRs, a few of them spilled
 template <typename TS, int UMAX>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_mfma_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void gather_mfma_kernel(
+    GatherArgs a, int64_t tiles, int64_t kblocks) {
     extern __shared__ __align__(16) float ysm[];
     // 1-D grid, block order (tile fastest, k block, split) regrouped per XCD
     const int64_t L = xcd_block(blockIdx.x, gridDim.x);
@@ -312,7 +366,8 @@ __global__ __launch_bounds__(kLdsWaves * 64) void gather_mfma_kernel(GatherArgs 
 // is reused from item to item (the loop-top barrier orders the last reads of one
 // item before the first writes of the next).
 template <typename TS, int UMAX>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_mfma_persistent(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void gather_mfma_persistent(
+    const BatchCase *__restrict__ cases,
                                                                          const int4 *__restrict__ items, int n_items,
                                                                          int *__restrict__ counter) {
     extern __shared__ __align__(16) float ysm[];

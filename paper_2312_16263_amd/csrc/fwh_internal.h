@@ -254,6 +254,8 @@ inline size_t gather_lds_panel_bytes(int coef_type, int NW) {
     return (size_t)8 * NW * esz + (size_t)kObsTile * (sizeof(PairRec) + (coef_type == 1 ? 0 : sizeof(PairBf)));
 }
 inline size_t gather_lds_shmem(int coef_type, int NW, int PT) { return 2 * (size_t)PT * gather_lds_panel_bytes(coef_type, NW); }
+// size class (bytes) of each of the two static stage buffers for this staging size (0: too large)
+int gather_lds_stage_class(int coef_type, int NW, int PT);
 // blocks of the LDS-staged gather resident per CU at this staging size (registers and LDS)
 int gather_lds_blocks_per_cu(int coef_type, int NW, int PT);
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
@@ -262,7 +264,10 @@ hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf 
 // Matrix-core gather (fwh_gather_mfma.hip): per panel a Y tile [kObsTile][YR] floats in LDS covering
 // the window of the widest tile (wmax = largest n0 spread over a tile's observers).
 inline int gather_mfma_y_row(int wmax) { return ((wmax + kLdsK + kLdsHalo + 15) / 16) * 16 + 4; }
-inline size_t gather_mfma_shmem(int wmax) { return (size_t)kObsTile * gather_mfma_y_row(wmax) * sizeof(float); }
+// Y tile, then two record buffers of the tile (pair records and, in BF16, split weights)
+inline size_t gather_mfma_shmem(int wmax) {
+    return (size_t)kObsTile * gather_mfma_y_row(wmax) * sizeof(float) + 2 * (size_t)kObsTile * (sizeof(PairRec) + sizeof(PairBf));
+}
 // matrix units per wave and panel the kernel is compiled for (4, 6 or 8; 0: windows too wide)
 int gather_mfma_umax(int wmax);
 // resident blocks per CU (0 when the kernel does not apply)
@@ -276,6 +281,15 @@ hipError_t launch_gather_mfma(int coef_type, const PairRec *rec_op, const PairBf
 int gather_mfma_persistent_blocks_per_cu(int coef_type, int umax, size_t shmem);
 hipError_t launch_gather_mfma_persistent(int coef_type, int umax, const BatchCase *cases, const int4 *items,
                                          int n_items, int *counter, int grid, size_t shmem, hipStream_t stream);
+// Streaming gather for O <= kLdsWaves observers: whole coefficient rows of each panel staged in LDS
+// (two buffers), two waves per observer, every sample in registers (rows of 61, up to 32 rows).
+// Grid: one block per panel split.  0 blocks per CU when it does not apply (rows or LDS).
+size_t gather_stream_shmem(int coef_type, int64_t NS);
+int gather_stream_rows(int64_t nt_max);  // rows per wave it is compiled for (0: record too long)
+int gather_stream_blocks_per_cu(int coef_type, int64_t NS, int64_t nt_max);
+hipError_t launch_gather_stream(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int32_t *nt,
+                                const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits,
+                                float *partial, hipStream_t stream);
 // out[i] = sum over splits of partial[z][i], in FP64 and fixed order, rounded to float.
 hipError_t launch_reduce_splits(const float *partial, int splits, int64_t total, float *out, hipStream_t stream);
 
@@ -312,14 +326,11 @@ hipError_t launch_batch_source_adjoint(int in_dtype, const BatchCase *cases, con
 hipError_t launch_batch_forward(int in_dtype, int coef_type, int umax, const BatchCase *cases, BatchIndex idx,
                                 const int4 *items, int n_items, int *counter, int grid, size_t shmem,
                                 int64_t blocks_src, int64_t blocks_srcg, int64_t blocks_red, hipStream_t stream);
-// adjoint: zero-padded dJ/dp' of all cases, then the persistent transposed gather over adj_items
-// (case, group of kAdjItemGroups x 4 waves), longest first, through counter[0] (reset first), then
-// the chunked source adjoint of all cases
-constexpr int kAdjItemGroups = 8;
-int adj_gather_blocks_per_cu();
+// adjoint: zero-padded dJ/dp' of all cases, then the transposed gather over adj_items (case, group of
+// 4 waves) in their longest-first order, one block per item, then the chunked source adjoint
 hipError_t launch_batch_adjoint(int in_dtype, const BatchCase *cases, BatchIndex idx, int64_t blocks_pad,
-                                const int2 *adj_items, int n_adj_items, int *counter, int grid_adj,
-                                int64_t blocks_sadj, int64_t blocks_sadjg, hipStream_t stream);
+                                const int2 *adj_items, int n_adj_items, int64_t blocks_sadj, int64_t blocks_sadjg,
+                                hipStream_t stream);
 
 // Post-processing: per-observer RMS and one-sided Welch PSD (segments of L
 // samples, 50 % overlap, Hann window), times span_ratio; psd [O][L/2+1], rms [O].

@@ -145,7 +145,7 @@ def test_batch_rows_per_block(rows):
 
     import paper_2312_16263_amd as fwh
     data = _case_data(CASES)
-    plans = [make_plan(c, "f32") for c in CASES]
+    plans = [make_plan(c, "f32", gather="mfma") for c in CASES]
     inputs = [to_device(d[:3]) for d in data]
     batch = fwh.Batch(plans, inputs, item_units=3e5)
     assert batch.gather == "mfma"

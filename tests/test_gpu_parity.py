@@ -139,12 +139,19 @@ def test_window_error_is_reported():
     assert ei.value.code == fwh.FWH_EWINDOW
 
 
-@pytest.mark.parametrize("gather", ["mfma", "lds", "direct"])
+@pytest.mark.parametrize("gather", ["mfma", "lds", "direct", "stream"])
 @pytest.mark.parametrize("mode", ["f32", "bf16"])
 @pytest.mark.parametrize("name", ["dip_ragged", "foil_bb", "ragged65"])
 def test_gather_variants(name, mode, gather):
     """Each forward gather kernel (matrix-core combine, LDS-staged windows,
-    direct loads), chosen through fwh_plan_tune, against the oracle."""
+    direct loads, whole-row streaming for at most 8 observers), chosen through
+    fwh_plan_tune, against the oracle; the streaming one refuses 9 observers."""
+    import paper_2312_16263_amd as fwh
+    if gather == "stream" and CASES[name].n_obs > 8:
+        with pytest.raises(fwh.FwhError) as ei:
+            make_plan(CASES[name], mode, gather=gather)
+        assert ei.value.code == fwh.FWH_EINVAL
+        return
     import torch
     c = CASES[name]
     rho, u, pp, p_ref, _, nt_ref = _data(name)
@@ -216,7 +223,7 @@ def test_post_rms_and_welch(mode, seg_len):
     assert e_rms <= 1e-6, e_rms
 
 
-@pytest.mark.parametrize("gather", ["mfma", "lds", "direct"])
+@pytest.mark.parametrize("gather", ["mfma", "lds", "direct", "stream"])
 @pytest.mark.parametrize("splits", [130, 131, 7])
 def test_many_panel_splits(gather, splits):
     """Many panel splits, including an empty last one: 16641 panels in 130

@@ -122,3 +122,23 @@ def test_analytic_generator_derivatives_and_wave_equation(kind):
     np.testing.assert_allclose(lhs, lap, rtol=1e-5, atol=1e-7 * np.abs(lap).max())
     # p' = -(d/dt + U0.grad) phi
     np.testing.assert_allclose(p_hat, -(1j * w * ph + dU), rtol=1e-9, atol=1e-12)
+
+
+def test_adjoint_panel_subset_matches_full():
+    """adjoint_panels on a subset (unsorted, with a repeat) returns exactly the
+    columns of the full adjoint: the windows come from the whole surface."""
+    rng, s, x = _case(6)
+    N, P = 40, s.n_panels
+    args = (s, x, 0.4, 8.0, 0.05, 0.1)
+    rho = 1 + 0.05 * rng.normal(size=(N, P))
+    u = 0.1 * rng.normal(size=(3, N, P))
+    pp = 0.01 * rng.normal(size=(N, P))
+    p, ts, nt = oracle.forward(*args, rho, u, pp)
+    g = 2.0 * p
+    full = oracle.adjoint(*args, rho, u, pp, g)
+    idx = np.array([P - 1, 0, 7, 7, 3 * P // 5])
+    sub = oracle.adjoint_panels(*args, rho, u, pp, g, idx)
+    for f, s_ in zip(full, sub):
+        assert np.array_equal(f[..., idx], s_)
+    with pytest.raises(ValueError):
+        oracle.adjoint_panels(*args, rho, u, pp, g, np.array([P]))
