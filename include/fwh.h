@@ -321,6 +321,28 @@ int fwh_gm_profile_read(fwh_gm_plan *plan, int32_t stage, double *total_ms, int6
 /* Frees the host side of the plan (the workspace is the caller's). */
 void fwh_gm_destroy(fwh_gm_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it): fwh_plan_create + fwh_setup + fwh_forward in one call, with the
+ * workspace taken from a static device array of FWH_NOALLOC_BYTES that each
+ * GPU the library runs on holds from the first such call until the process
+ * ends.  Inputs as for fwh_forward (device, time-major, in_dtype); p_out is a
+ * caller-owned device buffer of out_capacity elements (double in FWH_MODE_F64,
+ * float otherwise) that receives [O][*n_t_max] as fwh_forward writes it
+ * (O x N elements always suffice, since N_t <= N); *n_t_max (host) returns
+ * the row length.  No hipMalloc, hipFree or other device allocation; the plan's
+ * host copy of the geometry is allocated and freed inside the call.  Like
+ * fwh_setup it synchronises `stream`.  FWH_ESIZE when the case needs a larger
+ * workspace (the message names both sizes) or p_out is too small; the other
+ * codes as for fwh_plan_create, fwh_setup and fwh_forward.  Every call on one
+ * GPU uses that GPU's one array: calls that overlap on one GPU (other threads,
+ * other streams) race and must be serialised by the caller.  Each call writes
+ * every workspace region before reading it, so nothing needs clearing. */
+#define FWH_NOALLOC_BYTES (64u << 20)
+int fwh_forward_noalloc(const fwh_setup_args *args, int32_t in_dtype, const void *rho, const void *u,
+                        const void *p_prime, void *p_out, int64_t out_capacity, int64_t *n_t_max, void *stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *fwh_last_error(void);
 

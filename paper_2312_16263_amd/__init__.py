@@ -33,8 +33,9 @@ EXPORTED = ["fwh_plan_create", "fwh_plan_tune", "fwh_plan_info", "fwh_setup", "f
             "fwh_profile_read", "fwh_batch_create", "fwh_batch_tune", "fwh_batch_tune_case", "fwh_batch_gather", "fwh_batch_bind", "fwh_batch_forward",
             "fwh_batch_adjoint", "fwh_batch_info", "fwh_batch_destroy", "fwh_destroy", "fwh_gm_plan_create",
             "fwh_gm_window", "fwh_gm_obs_window", "fwh_gm_forward", "fwh_gm_profile_enable",
-            "fwh_gm_profile_read", "fwh_gm_destroy", "fwh_last_error",
+            "fwh_gm_profile_read", "fwh_gm_destroy", "fwh_forward_noalloc", "fwh_last_error",
             "fwh_version"]
+NOALLOC_BYTES = 64 << 20  # FWH_NOALLOC_BYTES
 # names declared in include/fwh_io.h
 IO_EXPORTED = ["fwh_io_control_read", "fwh_io_geometry_read", "fwh_io_geometry_write", "fwh_io_observers_read",
                "fwh_io_frame_path", "fwh_io_frames_read", "fwh_io_frame_write", "fwh_io_last_error"]
@@ -134,6 +135,8 @@ def lib():
         L.fwh_gm_destroy.restype = None
         L.fwh_destroy.argtypes = [vp]
         L.fwh_destroy.restype = None
+        L.fwh_forward_noalloc.argtypes = [ctypes.POINTER(SetupArgs), i32, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+        L.fwh_forward_noalloc.restype = ctypes.c_int
         L.fwh_last_error.argtypes = []
         L.fwh_last_error.restype = ctypes.c_char_p
         L.fwh_version.argtypes = []

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <new>
@@ -32,6 +33,16 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
+
+// Workspace of fwh_forward_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses the
+// array's name as an address: the device address of each GPU's copy is taken
+// once per device with hipGetSymbolAddress and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocBytes = (size_t)FWH_NOALLOC_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -1129,6 +1140,53 @@ void fwh_gm_destroy(fwh_gm_plan *pl) {
 }
 
 const char *fwh_last_error(void) { return g_last_error.c_str(); }
+
+int fwh_forward_noalloc(const fwh_setup_args *args, int32_t in_dtype, const void *rho, const void *u,
+                        const void *pp, void *p_out, int64_t out_capacity, int64_t *n_t_max, void *stream) {
+    g_last_error.clear();
+    if (!args || !rho || !u || !pp || !p_out || !n_t_max)
+        return fail(FWH_EINVAL, "fwh_forward_noalloc: null argument");
+    if (in_dtype != FWH_F64 && in_dtype != FWH_F32)
+        return fail(FWH_EINVAL, "fwh_forward_noalloc: bad in_dtype %d", in_dtype);
+    fwh_plan *pl = nullptr;
+    size_t need = 0;
+    int rc = fwh_plan_create(args, &pl, &need);
+    if (rc != FWH_OK) return rc;
+    struct Release {
+        fwh_plan *p;
+        ~Release() { fwh_destroy(p); }
+    } release{pl};
+    if (need > kNoAllocBytes)
+        return fail(FWH_ESIZE,
+                    "fwh_forward_noalloc: the case needs a %zu-byte workspace, more than the %zu bytes of the "
+                    "static one (use fwh_plan_create / fwh_setup / fwh_forward with a caller workspace)",
+                    need, kNoAllocBytes);
+    // this device's copy of the static workspace, looked up once per device
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return hip_fail("fwh_forward_noalloc: hipGetDevice", e);
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(FWH_EINVAL, "fwh_forward_noalloc: device %d beyond the %d supported", dev, kNoAllocMaxDevices);
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_fail("fwh_forward_noalloc: address of the static workspace", e);
+            g_noalloc_ptr[dev] = p;
+        }
+        ws = g_noalloc_ptr[dev];
+    }
+    // setup writes every table it later reads, the forward every coefficient and partial it reads,
+    // so nothing left by an earlier call is read and nothing needs clearing
+    if ((rc = fwh_setup(pl, ws, kNoAllocBytes, stream)) != FWH_OK) return rc;
+    *n_t_max = pl->n_t_max;
+    if (pl->O * pl->n_t_max > out_capacity)
+        return fail(FWH_ESIZE, "fwh_forward_noalloc: p_out holds %lld elements, the output needs %lld x %lld",
+                    (long long)out_capacity, (long long)pl->O, (long long)pl->n_t_max);
+    return fwh_forward(pl, in_dtype, rho, u, pp, p_out, stream);
+}
 
 const char *fwh_version(void) { return "fwh-mi355x 0.1 (gfx950)"; }
 
