@@ -630,7 +630,7 @@ int fwh_batch_create(const fwh_batch_case *cases, int32_t n, int32_t in_dtype, f
         const int64_t tiles = ceil_div(k.plan->O, fwh::kObsTile),
                       kbs = ceil_div(k.plan->n_t_max, 2 * fwh::kLdsLanesOut);
         max_items += tiles * kbs * k.plan->max_splits;
-        const int64_t nib = ceil_div(k.plan->NS, fwh::kAdjSub * fwh::kLdsLanesOut);
+        const int64_t nib = fwh::adj_blocks(k.plan->NS);
         max_adj_items += ceil_div(k.plan->P * nib, 4);
     }
     if (max_adj_items > INT32_MAX) return fail(FWH_ESIZE, "fwh_batch_create: too many adjoint work items");
@@ -747,7 +747,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         S = std::max<int64_t>(1, std::min<int64_t>(S, pl->max_splits));
         const int64_t p_chunk = ceil_div(P, S);
         const int64_t LR = fwh::adj_pad_row(N, NS), padlo = fwh::adj_pad_lo(N);
-        const int64_t nib = ceil_div(NS, fwh::kAdjSub * fwh::kLdsLanesOut);
+        const int64_t nib = fwh::adj_blocks(NS);
         fwh::BatchCase &d = desc[c];
         d.src = fwh::SrcFwdArgs{k.rho, k.u, k.p_prime, pl->at<double>(pl->off_n), P, N, NS, pl->flow,
                                 pl->at<double>(pl->off_cp), pl->scratch(), pl->ws + pl->off_coef};

@@ -10,10 +10,11 @@
 // weights K_c of the 8 source channels, so
 //   p'(o, k) = sum_p sum_jj w_jj(o,p) g_{o,p}(n0 + k + jj),
 //   g_{o,p}(i) = sum_c K_c(o,p) coef_c(p, i).
-// The tuned kernel combines the channels first (8 FMA per new index) and then
-// applies the 4 taps (4 FMA per output): 12 FMA per (panel, observer, sample).
-// No matrix cores: the contraction over channels has length 8 and each pair
-// has its own shift, so the work is a shifted gather, not a dense GEMM.
+// The forward kernels combine the channels first (8 FMA per new index) and then
+// apply the 4 taps (4 FMA per output): 12 FMA per (panel, observer, sample); the
+// contraction over channels has length 8 and each pair has its own shift.  The
+// transposed gather sums over observers, a contraction of length O for every
+// (panel, index): it runs on the matrix cores.
 #include <type_traits>
 
 #include "fwh_internal.h"
@@ -707,107 +708,157 @@ __global__ __launch_bounds__(256) void pad_grad_batched(const BatchCase *__restr
     pad_grad_body(cases[c].pad, ((int64_t)blockIdx.x - start[c]) * 256 + threadIdx.x);
 }
 
-// Value of lane l-1 (wavefront shift by one lane; lane 0 receives 0).
-__device__ __forceinline__ float from_prev_lane(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138 /* wave_shr:1 */, 0xF, 0xF, true));
+// Transposed gather on the matrix cores.  For panel p and coefficient index i,
+//   cbar_c(p, i) = sum_o K_c(o, p) H(o, i),  H(o, i) = sum_j w_j(o, p) gbar(o, i - n0(o, p) - j),
+// a contraction over observers, one 16x16x4 FP32 MFMA per 4 observers and 16
+// indices: A[m][k] = H(observer o + k, index m), B[k][n] = K_n(o + k, p) (zero for
+// n >= 8), D[m][n] = the cbar contribution of channel n at index m.  The taps
+// stay on the VALU: lane (q, s) of the wave (q = lane / 16, s = lane % 16) owns
+// observer o + q and the 4 indices ib + 4 s + t (t = 0..3), loads gbar at the 4
+// shifted positions with one 16-byte load, takes the 3 positions below from lane
+// s - 1 of its row (a row shift; lane s = 0 takes them from lane 15's load of
+// the previous block of 64, by a row rotation, and loads them for the first
+// block), and forms H for its 4 indices.  MFMA t takes the rows m = s as index ib + 4 m + t, so lane (q', n)
+// of its output holds channel n at indices ib + 16 q' + 4 r + t (r = 0..3): 16
+// consecutive indices per lane over t and r, stored as 4 float4.
+//
+// A wave owns panel p and kAdjMW blocks of 64 indices.  Waves go in tiles of
+// kAdjPT panels x all index blocks, panels fastest: the 4 waves of a block (and
+// neighbouring blocks on one XCD) read the same observers' gbar windows a few
+// samples apart and adjacent pair records, and a tile's records stay in L2 for
+// all its index blocks.  Each row q fetches its pair record with one dword per lane (lane s:
+// dword s of the 64-byte record, so lanes s < 8 hold K_s) and takes the taps and
+// n0 from lanes 8..12 of the row by row broadcasts.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float adj_row_rot(float x) {
+    // lane s of each row of 16 receives lane s - 1 (mod 16)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121 /* row_ror:1 */, 0xF, 0xF, false));
 }
 
-// Transposed gather.  A wave owns panel p and coefficient indices
-// i = 61 b + l - 3 (lanes 0..2 only supply shifted values to lanes 3..5).  Per
-// observer, lane l loads gpad at i - n0 (one coalesced load), receives the
-// values at i - n0 - 1 .. i - n0 - 3 from lanes l-1..l-3 by wavefront shifts,
-// applies the four taps and accumulates the 8 channel weights.
-__device__ __forceinline__ void adj_gather_dpp_body(const AdjArgs &a, int64_t wave_id) {
-    const PairRec *__restrict__ rec = a.rec;
-    const float *__restrict__ gpad = a.gpad;
-    const int64_t P = a.P, O = a.O, NS = a.NS, LR = a.LR, padlo = a.padlo, nib = a.nib;
-    float *__restrict__ cbar = a.cbar;
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ float adj_row_prev(float x, float old) {
+    // lane s of each row of 16 receives lane s - 1's x; lane 0 keeps `old`
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), 0x111 /* row_shr:1 */,
+                                                      0xF, 0xF, false));
+}
+
+template <int LANE>
+__device__ __forceinline__ float adj_row_bcast(float x) {
+    // every lane of each row of 16 receives lane LANE of its row
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + LANE /* row_newbcast */, 0xF, 0xF, false));
+}
+
+struct __attribute__((packed, aligned(4))) AdjF4 {
+    float x, y, z, w;
+};
+
+// One group of 4 observers (one per row q of the wave): the row's pair record
+// spread over its 16 lanes, and the gbar windows.
+struct AdjGroup {
+    float rv;          // dword s of the record of (o + q, p)
+    AdjF4 x[kAdjMW];   // gbar at e .. e + 3, e = ib + 64 u + 4 s - n0
+    AdjF4 pv;          // gbar at e - 4 .. e - 1 of block u = 0 (lane s = 0 only)
+};
+
+__device__ __forceinline__ void adj_gather_mfma_body(const AdjArgs &a, int64_t wave_id) {
+    const int64_t P = a.P, O = a.O, NS = a.NS, LR = a.LR, nib = a.nib;
     if (wave_id >= P * nib) return;
-    const int64_t p = wave_id / nib;
-    const int64_t b = wave_id - p * nib;
-    constexpr int S = kAdjSub;  // index blocks per wave: each record load serves S blocks
-    const int64_t i0 = b * S * kLdsLanesOut + lane - kLdsHalo;
-    const PairRec *rr = rec + p;  // record of (o, p) at rr[o * P]
-    const float *g = gpad + i0 + padlo;
-    float acc[S][8];
-    double accd[S][8];
+    // tile of kAdjPT panels (the last one narrower) x nib index blocks, panels fastest
+    const int64_t tile = wave_id / (kAdjPT * nib);
+    const int64_t r = wave_id - tile * (kAdjPT * nib);
+    const int64_t tw = min<int64_t>(kAdjPT, P - tile * kAdjPT);
+    const int64_t bi = r / tw;
+    const int64_t p = tile * kAdjPT + (r - bi * tw);
+    const int64_t ib = bi * (64 * kAdjMW);
+    const int nsub = (int)min<int64_t>(kAdjMW, (NS - ib) >> 6);  // NS is a multiple of 64
+    const int lane = threadIdx.x & 63, q = lane >> 4, s = lane & 15;
+    const float *g = a.gpad + a.padlo + ib + 4 * s;
+    const float *rp = reinterpret_cast<const float *>(a.rec + p) + s;
+    // index blocks past nsub load the last one again (in bounds) and skip their MFMAs
+    int uoff[kAdjMW];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int u = 0; u < kAdjMW; ++u) uoff[u] = 64 * min(u, nsub - 1);
+    floatx4_t acc[kAdjMW][4];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            acc[s][c] = 0.f;
-            accd[s][c] = 0.0;
-        }
-    // observers in groups of 4: the 4 records and the 4 S gpad values are fetched before any is used
-    auto step = [&](const PairRec &r, const float *v) {
+    for (int u = 0; u < kAdjMW; ++u)
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float s1 = from_prev_lane(v[s]);
-            const float s2 = from_prev_lane(s1);
-            const float s3 = from_prev_lane(s2);
-            float h = r.w[0] * v[s];
-            h = fmaf(r.w[1], s1, h);
-            h = fmaf(r.w[2], s2, h);
-            h = fmaf(r.w[3], s3, h);
+        for (int t = 0; t < 4; ++t) acc[u][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    // Loads run ahead of the arithmetic: while group o is on the VALU and the matrix cores, the
+    // gbar windows of group o + 4 and the records of group o + 8 are in flight.  Observers past O
+    // are clamped to O - 1 for the loads and get K = 0.
+    constexpr int64_t kRecDwords = sizeof(PairRec) / 4;
+    auto load_rec = [&](int64_t o) { return rp[min(o + q, O - 1) * P * kRecDwords]; };
+    auto load_x = [&](int64_t o, AdjGroup &b) {
+        const int n0 = __float_as_int(adj_row_bcast<12>(b.rv));
+        const float *go = g + min(o + q, O - 1) * LR - n0;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[s][c] = fmaf(r.K[c], h, acc[s][c]);
-        }
+        for (int u = 0; u < kAdjMW; ++u) b.x[u] = *reinterpret_cast<const AdjF4 *>(go + uoff[u]);
+        if (s == 0) b.pv = *reinterpret_cast<const AdjF4 *>(go - 4);
     };
-    auto fetch = [&](int64_t o, int n0, float *v) {
+    auto compute = [&](int64_t o, const AdjGroup &b) {
+        const float kb = (o + q < O && s < 8) ? b.rv : 0.f;
+        const float w0 = adj_row_bcast<8>(b.rv), w1 = adj_row_bcast<9>(b.rv), w2 = adj_row_bcast<10>(b.rv),
+                    w3 = adj_row_bcast<11>(b.rv);
 #pragma unroll
-        for (int s = 0; s < S; ++s) v[s] = g[o * LR - n0 + s * kLdsLanesOut];
-    };
-    auto flush = [&]() {
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                accd[s][c] += (double)acc[s][c];
-                acc[s][c] = 0.f;
-            }
-    };
-    const int64_t O4 = O & ~(int64_t)3;
-    int cnt = 0;
-    for (int64_t o = 0; o < O4; o += 4) {
-        const PairRec r0 = rr[o * P], r1 = rr[(o + 1) * P], r2 = rr[(o + 2) * P], r3 = rr[(o + 3) * P];
-        float v0[S], v1[S], v2[S], v3[S];
-        fetch(o, r0.n0, v0);
-        fetch(o + 1, r1.n0, v1);
-        fetch(o + 2, r2.n0, v2);
-        fetch(o + 3, r3.n0, v3);
-        step(r0, v0);
-        step(r1, v1);
-        step(r2, v2);
-        step(r3, v3);
-        cnt += 4;
-        if (cnt >= kChunk) {
-            flush();
-            cnt = 0;
-        }
-    }
-    for (int64_t o = O4; o < O; ++o) {
-        const PairRec r = rr[o * P];
-        float v[S];
-        fetch(o, r.n0, v);
-        step(r, v);
-    }
-    flush();
-    if (lane >= kLdsHalo) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int64_t i = i0 + s * kLdsLanesOut;
-            if (i < NS) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) cbar[((int64_t)c * P + p) * NS + i] = (float)accd[s][c];
+        for (int u = 0; u < kAdjMW; ++u) {
+            if (u < nsub) {
+                const AdjF4 xv = b.x[u];
+                // lane 0's values below e: its own load (u = 0) or lane 15's of block u - 1
+                const AdjF4 &xp = b.x[u > 0 ? u - 1 : 0];
+                const float o1 = u == 0 ? b.pv.w : adj_row_rot(xp.w);
+                const float o2 = u == 0 ? b.pv.z : adj_row_rot(xp.z);
+                const float o3 = u == 0 ? b.pv.y : adj_row_rot(xp.y);
+                const float m1 = adj_row_prev(xv.w, o1);  // gbar at e - 1
+                const float m2 = adj_row_prev(xv.z, o2);  // e - 2
+                const float m3 = adj_row_prev(xv.y, o3);  // e - 3
+                const float h0 = fmaf(w3, m3, fmaf(w2, m2, fmaf(w1, m1, w0 * xv.x)));
+                const float h1 = fmaf(w3, m2, fmaf(w2, m1, fmaf(w1, xv.x, w0 * xv.y)));
+                const float h2 = fmaf(w3, m1, fmaf(w2, xv.x, fmaf(w1, xv.y, w0 * xv.z)));
+                const float h3 = fmaf(w3, xv.x, fmaf(w2, xv.y, fmaf(w1, xv.z, w0 * xv.w)));
+                acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, kb, acc[u][0], 0, 0, 0);
+                acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(h1, kb, acc[u][1], 0, 0, 0);
+                acc[u][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(h2, kb, acc[u][2], 0, 0, 0);
+                acc[u][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(h3, kb, acc[u][3], 0, 0, 0);
             }
         }
+    };
+    // before step(o, cur, nxt): cur holds the record and windows of group o, nxt the record of
+    // group o + 4.  Loads complete in issue order, so the record of o + 8 goes first: the next
+    // step waits for it without waiting for the windows issued after it.
+    auto step = [&](int64_t o, AdjGroup &cur, AdjGroup &nxt) {
+        const float rnew = load_rec(o + 8);
+        load_x(o + 4, nxt);
+        compute(o, cur);
+        cur.rv = rnew;
+    };
+    AdjGroup A, B;
+    A.pv = B.pv = AdjF4{0.f, 0.f, 0.f, 0.f};
+    A.rv = load_rec(0);
+    B.rv = load_rec(4);
+    load_x(0, A);
+#pragma unroll 1
+    for (int64_t o = 0; o < O; o += 8) {
+        step(o, A, B);
+        if (o + 4 >= O) break;
+        step(o + 4, B, A);
+    }
+    if (s < 8) {
+        float *out = a.cbar + ((int64_t)s * P + p) * NS + ib + 16 * q;
+#pragma unroll
+        for (int u = 0; u < kAdjMW; ++u)
+            if (u < nsub) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    *reinterpret_cast<float4 *>(out + 64 * u + 4 * rr) =
+                        make_float4(acc[u][0][rr], acc[u][1][rr], acc[u][2][rr], acc[u][3][rr]);
+            }
     }
 }
 
-__global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
-    // consecutive blocks (the waves of neighbouring panels) regrouped per XCD
-    adj_gather_dpp_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void adj_gather_mfma_kernel(AdjArgs a) {
+    // consecutive blocks (neighbouring index blocks and panels) regrouped per XCD
+    adj_gather_mfma_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 // Batched transposed gather over a longest-first work list: block b runs item b,
@@ -818,12 +869,12 @@ __global__ __launch_bounds__(256) void adj_gather_dpp_kernel(AdjArgs a) {
 // left when one of its blocks ends.  (A persistent form pulling items through a
 // counter keeps the case arguments live across items: 193 registers per lane,
 // against 122 here.)
-__global__ __launch_bounds__(256) void adj_gather_listed(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void adj_gather_listed(const BatchCase *__restrict__ cases,
                                                          const int2 *__restrict__ items) {
     const int2 w = items[blockIdx.x];
     const int c = __builtin_amdgcn_readfirstlane(w.x);
     const int64_t g = __builtin_amdgcn_readfirstlane(w.y);
-    adj_gather_dpp_body(cases[c].adj, g * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    adj_gather_mfma_body(cases[c].adj, g * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 // out[o][k] = sum_z partial[z][o][k] in fixed order.
@@ -1019,9 +1070,9 @@ hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const flo
     pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t nib = (NS + kAdjSub * kLdsLanesOut - 1) / (kAdjSub * kLdsLanesOut);
+    const int64_t nib = adj_blocks(NS);
     const AdjArgs aa{rec_op, gpad, P, O, NS, LR, padlo, nib, cbar};
-    adj_gather_dpp_kernel<<<dim3((unsigned)((P * nib + 3) / 4)), dim3(256), 0, stream>>>(aa);
+    adj_gather_mfma_kernel<<<dim3((unsigned)((P * nib + 3) / 4)), dim3(256), 0, stream>>>(aa);
     return hipGetLastError();
 }
 
