@@ -320,11 +320,13 @@ def bench_batch(replays, sync):
     fwd_ms, adj_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     # the same adjoint as 64 single-case launches: HIP events around all of them back to back, and the
     # sum of their transposed-gather and source-adjoint stage times (kernel time without launch gaps)
-    grads = [pl.adjoint(*d, gp) for pl, d, gp in zip(plans, inputs, batch.grad_p)]
+    # (into the batch's own gradient buffers: the device has no room for a second set)
+    for pl, d, gp, g in zip(plans, inputs, batch.grad_p, batch.grads):
+        pl.adjoint(*d, gp, out=g)
     for pl in plans:
         pl.profile(True)
     ev[0].record()
-    for pl, d, gp, g in zip(plans, inputs, batch.grad_p, grads):
+    for pl, d, gp, g in zip(plans, inputs, batch.grad_p, batch.grads):
         pl.adjoint(*d, gp, out=g)
     ev[1].record()
     sync()
@@ -334,7 +336,6 @@ def bench_batch(replays, sync):
         st = pl.profile_read()
         adj_single_stage_ms += st["adj_gather"][0] + st["source_adj"][0]
         pl.profile(False)
-    del grads
     p_b = [t.double().cpu().numpy() for t in batch.p_out]
     del graph, batch
     del plans
@@ -457,7 +458,7 @@ def main():
     ap.add_argument("--mode", default="f32", choices=["f32", "bf16"], help="mode of the profile run")
     ap.add_argument("--ingest-only", action="store_true", help="only the file-ingestion measurement (JSON line)")
     ap.add_argument("--workload", default="dipole_sphere",
-                    choices=["dipole_sphere", "airfoil_broadband", "general_motion"],
+                    choices=["dipole_sphere", "dipole_sphere_obs8", "airfoil_broadband", "general_motion"],
                     help="workload of the profile run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -576,17 +577,20 @@ def main():
     t_dom = avg[dom] * 1e-3
     achieved = FLOP_PER_UNIT * U / t_dom / 1e12
     fwd_kernel = gather_kernel(plan, "f32")
-    dom_kernel = fwd_kernel if dom == "gather" else "adj_gather_dpp_kernel"
+    adj_kernel = "adj_gather_mfma_kernel"
+    dom_kernel = fwd_kernel if dom == "gather" else adj_kernel
     # algorithmic bytes per launch: coefficients (8 channels FP32 over NS) + pair records + output/input signal
     NSd = ((c.n_tau + 12 + 63) // 64) * 64
     alg_bytes = 8 * 4 * c.n_panels * NSd + 64 * c.n_obs * c.n_panels + 4 * c.n_obs * int(nt.max())
-    roofline = {"bound": "alu", "kernel": dom_kernel, "achieved": achieved, "peak": FP32_PEAK / 1e12,
+    # the forward gather is VALU work, the transposed gather runs its channel sums on the matrix cores
+    # (FP32 MFMA, the same 157.3 TFLOP/s peak)
+    roofline = {"bound": "alu" if dom == "gather" else "mfma", "kernel": dom_kernel, "achieved": achieved, "peak": FP32_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved * 1e12 / FP32_PEAK, "traffic": measured_traffic(dom_kernel),
                 "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes": alg_bytes,
                 "frac_of_nonpacked_fp32_peak": achieved * 1e12 / FP32_NONPACKED_PEAK,
                 "flop_per_unit": FLOP_PER_UNIT, "units_per_launch": U, "avg_launch_ms": avg[dom],
-                "other_gather": {"kernel": "adj_gather_dpp_kernel" if dom == "gather" else fwd_kernel,
+                "other_gather": {"kernel": adj_kernel if dom == "gather" else fwd_kernel,
                                  "avg_launch_ms": avg["adj_gather" if dom == "gather" else "gather"],
                                  "frac": FLOP_PER_UNIT * U / (avg["adj_gather" if dom == "gather" else "gather"]
                                                               * 1e-3) / FP32_PEAK}}
@@ -619,9 +623,11 @@ def main():
         n_s = int(min(c.n_obs, max(1, round((args.cpu_seconds - fixed) / per_obs))))
         idx = np.unique(np.linspace(0, c.n_obs - 1, n_s).round().astype(int))
         t_cpu, u_cpu = oracle_step(idx)
-        # the same on one thread, on one observer
+        # the same on one thread: one and two observers, whose difference is the per-observer cost
+        # without the fixed per-panel work (layout transposes, source terms)
         oracle.set_num_threads(1)
         t_1, u_1 = oracle_step(np.array([c.n_obs // 2]))
+        t_2, u_2 = oracle_step(np.array([c.n_obs // 2, c.n_obs // 2 + 1]))
         oracle.set_num_threads(n_threads)
         cpu = {"value": u_cpu / t_cpu, "unit": "panel-obs-samples/s", "cores": n_threads, "kind": "oracle",
                "sample": f"forward + adjoint of the FP64 oracle on {len(idx)} of {c.n_obs} observers (all "
@@ -629,8 +635,12 @@ def main():
                          f"excludes input generation", "seconds": t_cpu,
                "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
                "compile_flags": flags,
-               "value_1thread": u_1 / t_1, "sample_1thread": f"one observer, {u_1:.3e} units in {t_1:.1f} s"}
+               "value_1thread": u_1 / t_1, "sample_1thread": f"one observer, {u_1:.3e} units in {t_1:.1f} s",
+               "value_1thread_per_observer": (u_2 - u_1) / max(t_2 - t_1, 1e-6),
+               "sample_1thread_per_observer": f"two observers minus one: {u_2 - u_1:.3e} units in "
+                                              f"{t_2 - t_1:.1f} s"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} units/s on {cpu['cores']} threads, {u_1 / t_1:.3e} on one "
+            f"(one observer; {cpu['value_1thread_per_observer']:.3e} per added observer) "
             f"({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     extra = {}

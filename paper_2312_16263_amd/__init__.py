@@ -197,6 +197,7 @@ class Plan:
         nbytes = ctypes.c_size_t()
         _check(L.fwh_plan_create(ctypes.byref(args), ctypes.byref(h), ctypes.byref(nbytes)))
         self._h = h
+        self._free = lib().fwh_destroy  # kept: at interpreter exit the module globals may be gone
         if gather != "auto" or splits:
             _check(L.fwh_plan_tune(h, GATHERS[gather], int(splits)))
         self.P, self.O, self.N = yy.shape[0], xx.shape[0], int(n_tau)
@@ -244,7 +245,7 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().fwh_destroy(h)
+            self._free(h)
             self._h = None
 
     def _in_dtype(self, t):
@@ -348,6 +349,7 @@ class Batch:
         nb = ctypes.c_size_t()
         _check(L.fwh_batch_create(arr, len(self.plans), self.in_dtype, ctypes.byref(h), ctypes.byref(nb)))
         self._h = h
+        self._free = lib().fwh_batch_destroy  # kept: at interpreter exit the module globals may be gone
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.plans[0].device)
         self.blocks_per_cu = blocks_per_cu
         self.tune(item_units, blocks_per_cu)
@@ -414,7 +416,7 @@ class Batch:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().fwh_batch_destroy(h)
+            self._free(h)
             self._h = None
 
 
@@ -568,6 +570,7 @@ class GMPlan:
         nbytes = ctypes.c_size_t()
         _check(L.fwh_gm_plan_create(ctypes.byref(args), ctypes.byref(h), ctypes.byref(nbytes)))
         self._h = h
+        self._free = lib().fwh_gm_destroy  # kept: at interpreter exit the module globals may be gone
         self.P, self.O, self.N = P, O, N
         self.workspace_bytes = int(nbytes.value)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
@@ -584,7 +587,7 @@ class GMPlan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().fwh_gm_destroy(h)
+            self._free(h)
             self._h = None
 
     def profile(self, enable: bool = True):

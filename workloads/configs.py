@@ -101,6 +101,7 @@ def airfoil_broadband(n_points=1200, n_stations=200, n_tau=4096, n_obs=72, seed=
 
 def by_name(name: str) -> Case:
     return {"monopole_small": monopole_small, "dipole_sphere": dipole_sphere,
+            "dipole_sphere_obs8": lambda: dipole_sphere(n_obs=8),
             "airfoil_broadband": airfoil_broadband}[name]()
 
 
