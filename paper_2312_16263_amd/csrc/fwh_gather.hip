@@ -351,10 +351,12 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     nobs = __builtin_amdgcn_readfirstlane(nobs);
     int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
     nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > kLdsSub ? kLdsSub : nsub));
-    // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows
-    // (Lq: the panel's first-group window shifted by lane - lo, so that one add per observer
-    // gives each lane's element; the second group follows NW elements later)
-    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const QT *Lq, int q) {
+    // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows.  The window
+    // elements are addressed by one byte offset from the stage buffer `sb` (e0: the lane's first
+    // element of the panel's first channel group, less n0; the second group is NW elements
+    // later): a longer chain of pointer arithmetic hides from the compiler which of the two buffers
+    // a read touches, and it then makes the read wait for the copies into the other one.
+    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const unsigned char *sb, int e0, int q) {
         constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
@@ -362,8 +364,9 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const int slot = q * kObsTile + j * kLdsWaves + wv;
             const float4 *R = lrec + slot * 4;
             const float4 W = R[2];
-            const QT *P0 = Lq + __float_as_int(R[3].x);
-            const QT *P1 = P0 + NW;
+            const int b0 = (e0 + __float_as_int(R[3].x)) * EB;
+            const QT *P0 = reinterpret_cast<const QT *>(sb + b0);
+            const QT *P1 = reinterpret_cast<const QT *>(sb + (b0 + NW * EB));
             float4 Ka, Kb;
             uint4 Kh, Kl;
             if constexpr (kBf) {
@@ -446,8 +449,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
             for (int q = 0; q < np; ++q) {
                 const int lo = __builtin_amdgcn_readlane(lo_stage, q);
-                const QT *L0 = reinterpret_cast<const QT *>(base + q * win_bytes);
-                panel_work(nobs_c, nsub_c, lrec, L0 + (lane - lo), q);
+                panel_work(nobs_c, nsub_c, lrec, base, (int)(q * win_bytes / EB) + lane - lo, q);
                 if (++cnt == kLdsChunk) {
 #pragma unroll
                     for (int j = 0; j < NOBS; ++j)
@@ -623,8 +625,11 @@ __global__ __launch_bounds__(kStreamWaves * 64) void gather_stream_kernel(Gather
             const int nr = nrow;
             const float4 *R = reinterpret_cast<const float4 *>(cur + 2 * row_bytes + (size_t)jo * sizeof(PairRec));
             const float4 W = R[2];
-            const QT *P0 = reinterpret_cast<const QT *>(cur) + __float_as_int(R[3].x) + r0 * kLdsLanesOut + lane;
-            const QT *P1 = P0 + NS;
+            // both groups' rows addressed from the buffer base (formed as P0 + NS, the second would make
+            // the compiler wait for the copies into the other buffer before reading it)
+            const int e0 = __float_as_int(R[3].x) + r0 * kLdsLanesOut + lane;
+            const QT *P0 = reinterpret_cast<const QT *>(cur) + e0;
+            const QT *P1 = reinterpret_cast<const QT *>(cur + row_bytes) + e0;
             float4 Ka, Kb;
             uint4 Kh, Kl;
             if constexpr (kBf) {
