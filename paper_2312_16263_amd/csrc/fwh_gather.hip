@@ -248,9 +248,11 @@ __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t la
 // ([2][NW][4], lo = min n0 over the tile's observers, NW >= max width + kLdsK +
 // kLdsHalo) and the tile's pair records.  Every wave, for each of its observers
 // and each of the kLdsSub sub-blocks, lets lane l combine the 8 channels at
-// window position n0 - lo + 61 m + l (two vector LDS reads), fetches the
-// combined values of lanes l+1..l+3 by three wavefront shifts and applies the
-// four taps.
+// window position n0 - lo + 61 m + l (two vector LDS reads) and adds the
+// combined value times each of the four taps w_t into four accumulators; the
+// output of lane l, sum_t of accumulator t at lane l + t, is formed by three
+// wavefront shifts once per flush (12 VALU operations per panel and sub-row
+// instead of 15).
 // The two stage buffers are separate static LDS arrays (stA, stB): the compiler
 // can then tell that the direct global->LDS loads into one buffer do not alias
 // the LDS reads of the other, and does not make those reads wait for the loads.
@@ -326,11 +328,24 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
 
     // FP32 sums over kLdsChunk panels, added into the wave's own outputs of the split's partial signal
     // (no other wave writes them)
-    float acc[kObsPerWave][kLdsSub];
+    // Per (observer slot j, sub-row m) four tap accumulators: acc[j][m][t] = sum over panels of
+    // w_t times the lane's combined value.  The output of lane l is sum_t acc[j][m][t] at lane l + t;
+    // the shift is the same for every panel, so it is applied once per flush (tap_sum) instead of
+    // three lane shifts per panel.
+    float acc[kObsPerWave][kLdsSub][4];
 #pragma unroll
     for (int j = 0; j < kObsPerWave; ++j)
 #pragma unroll
-        for (int m = 0; m < kLdsSub; ++m) acc[j][m] = 0.f;
+        for (int m = 0; m < kLdsSub; ++m)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[j][m][t] = 0.f;
+    // sum_t acc[j][m][t] at lane + t (every lane must take part: lane shifts)
+    auto tap_sum = [&](int j, int m) {
+        float v = acc[j][m][3];
+        v = acc[j][m][2] + from_next_lane(v);
+        v = acc[j][m][1] + from_next_lane(v);
+        return acc[j][m][0] + from_next_lane(v);
+    };
     // this wave's output element of observer slot j, sub-row m (null outside the output)
     auto out_ptr = [&](int j, int m) -> float * {
         const int64_t o = tbase + j * kLdsWaves + wv;
@@ -405,15 +420,10 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                     g = fmaf(Kb.z, c[2], g);
                     g = fmaf(Kb.w, c[3], g);
                 }
-                const float g1 = from_next_lane(g);
-                const float g2 = from_next_lane(g1);
-                const float g3 = from_next_lane(g2);
-                float ac = acc[j][m];
-                ac = fmaf(W.x, g, ac);
-                ac = fmaf(W.y, g1, ac);
-                ac = fmaf(W.z, g2, ac);
-                ac = fmaf(W.w, g3, ac);
-                acc[j][m] = ac;
+                acc[j][m][0] = fmaf(W.x, g, acc[j][m][0]);
+                acc[j][m][1] = fmaf(W.y, g, acc[j][m][1]);
+                acc[j][m][2] = fmaf(W.z, g, acc[j][m][2]);
+                acc[j][m][3] = fmaf(W.w, g, acc[j][m][3]);
             }
         }
     };
@@ -455,9 +465,11 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                     for (int j = 0; j < NOBS; ++j)
 #pragma unroll
                         for (int m = 0; m < NSUB; ++m) {
+                            const float v = tap_sum(j, m);
                             float *dst = out_ptr(j, m);
-                            if (dst) *dst = (flushed ? *dst : 0.f) + acc[j][m];
-                            acc[j][m] = 0.f;
+                            if (dst) *dst = (flushed ? *dst : 0.f) + v;
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) acc[j][m][t] = 0.f;
                         }
                     flushed = true;
                     cnt = 0;
@@ -475,11 +487,12 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const int64_t ntl = o < O ? nt[o] : 0;
 #pragma unroll
             for (int m = 0; m < kLdsSub; ++m) {
+                const float v = tap_sum(j, m);
                 float *dst = out_ptr(j, m);
                 if (dst) {
                     const int64_t k = k0 + m * kLdsLanesOut + lane;
                     const float prev = (j < NOBS && m < NSUB && flushed) ? *dst : 0.f;
-                    *dst = k < ntl ? prev + acc[j][m] : 0.f;
+                    *dst = k < ntl ? prev + v : 0.f;
                 }
             }
         }
@@ -596,23 +609,37 @@ __global__ __launch_bounds__(kStreamWaves * 64) void gather_stream_kernel(Gather
         }
     };
 
-    float acc[NRH];
+    // BF16 (bound by VALU issue): four tap accumulators per row, the lane shifts of the taps applied
+    // once per flush as in the LDS-staged gather.  FP32 (bound by HBM): one accumulator per row and
+    // the shifts per panel, which keeps the 16-row form within its registers.
+    constexpr int NT = kBf ? 4 : 1;
+    float acc[NRH][NT];
 #pragma unroll
-    for (int r = 0; r < NRH; ++r) acc[r] = 0.f;
+    for (int r = 0; r < NRH; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[r][t] = 0.f;
     int cnt = 0;
     bool flushed = false;
     auto flush = [&](bool final_sums) {
-        if (!valid) return;
+        if (!valid) return;  // wave-uniform
         float *row = partial_row(a.partial, z, O, (int64_t)jo, nt_max);
 #pragma unroll
         for (int r = 0; r < NRH; ++r) {
+            float sum = acc[r][0];
+            if constexpr (NT == 4) {
+                float s3 = acc[r][3];
+                s3 = acc[r][2] + from_next_lane(s3);
+                s3 = acc[r][1] + from_next_lane(s3);
+                sum = acc[r][0] + from_next_lane(s3);
+            }
             const int k = (r0 + r) * kLdsLanesOut + lane;
             if (lane < kLdsLanesOut && k < nt_max) {
                 const float prev = (flushed && r < nrow) ? row[k] : 0.f;
-                const float v = r < nrow ? prev + acc[r] : 0.f;
+                const float v = r < nrow ? prev + sum : 0.f;
                 row[k] = (!final_sums || k < ntw) ? v : 0.f;
             }
-            acc[r] = 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[r][t] = 0.f;
         }
         flushed = true;
     };
@@ -668,15 +695,22 @@ __global__ __launch_bounds__(kStreamWaves * 64) void gather_stream_kernel(Gather
                         g = fmaf(Kb.z, c1[2], g);
                         g = fmaf(Kb.w, c1[3], g);
                     }
-                    const float g1 = from_next_lane(g);
-                    const float g2 = from_next_lane(g1);
-                    const float g3 = from_next_lane(g2);
-                    float ac = acc[r];
-                    ac = fmaf(W.x, g, ac);
-                    ac = fmaf(W.y, g1, ac);
-                    ac = fmaf(W.z, g2, ac);
-                    ac = fmaf(W.w, g3, ac);
-                    acc[r] = ac;
+                    if constexpr (NT == 4) {
+                        acc[r][0] = fmaf(W.x, g, acc[r][0]);
+                        acc[r][1] = fmaf(W.y, g, acc[r][1]);
+                        acc[r][2] = fmaf(W.z, g, acc[r][2]);
+                        acc[r][NT - 1] = fmaf(W.w, g, acc[r][NT - 1]);
+                    } else {
+                        const float g1 = from_next_lane(g);
+                        const float g2 = from_next_lane(g1);
+                        const float g3 = from_next_lane(g2);
+                        float ac = acc[r][0];
+                        ac = fmaf(W.x, g, ac);
+                        ac = fmaf(W.y, g1, ac);
+                        ac = fmaf(W.z, g2, ac);
+                        ac = fmaf(W.w, g3, ac);
+                        acc[r][0] = ac;
+                    }
                 }
             }
         }
