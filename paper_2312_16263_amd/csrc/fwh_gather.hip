@@ -92,6 +92,18 @@ __device__ __forceinline__ float from_next_lane(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */, 0xF, 0xF, true));
 }
 
+// a0 += w0 * (x of the next lane), a1 += w1 * (x of the next lane): two FMAs whose first source is
+// read through a DPP wave_shl:1 (lane 63 reads 0), so the lane shift costs no instruction of its
+// own (the compiler does not fold a DPP move into an FMA with a tied accumulator by itself).  The
+// s_nop gives the two wait states a DPP read needs after the VALU write of x.
+__device__ __forceinline__ void fmac2_next_lane(float &a0, float &a1, float x, float w0, float w1) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %2, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %2, %4 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(a0), "+v"(a1)
+        : "v"(x), "v"(w0), "v"(w1));
+}
+
 constexpr int kChunk = 64;  // panels summed in FP32 before adding into the FP64 accumulator
 // the LDS-staged gather keeps no accumulators beyond one FP32 sum per output in registers: it adds
 // its sums over kLdsChunk panels into the split's partial signal in memory (a split of at most
@@ -328,23 +340,19 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
 
     // FP32 sums over kLdsChunk panels, added into the wave's own outputs of the split's partial signal
     // (no other wave writes them)
-    // Per (observer slot j, sub-row m) four tap accumulators: acc[j][m][t] = sum over panels of
-    // w_t times the lane's combined value.  The output of lane l is sum_t acc[j][m][t] at lane l + t;
-    // the shift is the same for every panel, so it is applied once per flush (tap_sum) instead of
-    // three lane shifts per panel.
-    float acc[kObsPerWave][kLdsSub][4];
+    // Per (observer slot j, sub-row m) two tap-pair accumulators: with g the lane's combined value
+    // and g' = g of the next lane, acc[j][m][0] sums w_0 g + w_1 g' and acc[j][m][1] sums
+    // w_2 g + w_3 g' over panels (the next-lane operand is a DPP source of the FMA, no extra
+    // instruction).  The output of lane l is acc[j][m][0] at l plus acc[j][m][1] at l + 2; that
+    // shift is the same for every panel, so it is applied once per flush (tap_sum).
+    float acc[kObsPerWave][kLdsSub][2];
 #pragma unroll
     for (int j = 0; j < kObsPerWave; ++j)
 #pragma unroll
-        for (int m = 0; m < kLdsSub; ++m)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[j][m][t] = 0.f;
-    // sum_t acc[j][m][t] at lane + t (every lane must take part: lane shifts)
+        for (int m = 0; m < kLdsSub; ++m) acc[j][m][0] = acc[j][m][1] = 0.f;
+    // acc[j][m][0] + acc[j][m][1] two lanes up (every lane must take part: lane shifts)
     auto tap_sum = [&](int j, int m) {
-        float v = acc[j][m][3];
-        v = acc[j][m][2] + from_next_lane(v);
-        v = acc[j][m][1] + from_next_lane(v);
-        return acc[j][m][0] + from_next_lane(v);
+        return acc[j][m][0] + from_next_lane(from_next_lane(acc[j][m][1]));
     };
     // this wave's output element of observer slot j, sub-row m (null outside the output)
     auto out_ptr = [&](int j, int m) -> float * {
@@ -421,9 +429,8 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                     g = fmaf(Kb.w, c[3], g);
                 }
                 acc[j][m][0] = fmaf(W.x, g, acc[j][m][0]);
-                acc[j][m][1] = fmaf(W.y, g, acc[j][m][1]);
-                acc[j][m][2] = fmaf(W.z, g, acc[j][m][2]);
-                acc[j][m][3] = fmaf(W.w, g, acc[j][m][3]);
+                acc[j][m][1] = fmaf(W.z, g, acc[j][m][1]);
+                fmac2_next_lane(acc[j][m][0], acc[j][m][1], g, W.y, W.w);
             }
         }
     };
@@ -468,8 +475,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                             const float v = tap_sum(j, m);
                             float *dst = out_ptr(j, m);
                             if (dst) *dst = (flushed ? *dst : 0.f) + v;
-#pragma unroll
-                            for (int t = 0; t < 4; ++t) acc[j][m][t] = 0.f;
+                            acc[j][m][0] = acc[j][m][1] = 0.f;
                         }
                     flushed = true;
                     cnt = 0;
@@ -521,7 +527,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
 
 // SB: bytes of each of the two stage buffers (a size class chosen at setup)
 template <typename TS, int SB>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(6))) void gather_lds_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
     __shared__ __align__(16) unsigned char stA[SB];
     __shared__ __align__(16) unsigned char stB[SB];
     // 1-D grid, block order (tile fastest, k block, split) regrouped per XCD
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_kernel(GatherArgs a
 // in list order (longest first) through an atomic counter until the list is
 // exhausted; every block ends when it draws an index past the list.
 template <typename TS, int SB>
-__global__ __launch_bounds__(kLdsWaves * 64) void gather_lds_persistent(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(6))) void gather_lds_persistent(const BatchCase *__restrict__ cases,
                                                                         const int4 *__restrict__ items,
                                                                         int n_items, int *__restrict__ counter) {
     __shared__ __align__(16) unsigned char stA[SB];
