@@ -777,8 +777,9 @@ __global__ __launch_bounds__(256) void pad_grad_batched(const BatchCase *__restr
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float adj_row_rot(float x) {
-    // lane s of each row of 16 receives lane s - 1 (mod 16)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121 /* row_ror:1 */, 0xF, 0xF, false));
+    // lane s of each row of 16 receives lane s - 1 (mod 16); every lane has a source, so no old value
+    // (and no move to set one) is needed
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x121 /* row_ror:1 */, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ float adj_row_prev(float x, float old) {
@@ -789,9 +790,8 @@ __device__ __forceinline__ float adj_row_prev(float x, float old) {
 
 template <int LANE>
 __device__ __forceinline__ float adj_row_bcast(float x) {
-    // every lane of each row of 16 receives lane LANE of its row
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + LANE /* row_newbcast */, 0xF, 0xF, false));
+    // every lane of each row of 16 receives lane LANE of its row (no old value needed)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + LANE /* row_newbcast */, 0xF, 0xF, false));
 }
 
 struct __attribute__((packed, aligned(4))) AdjF4 {
