@@ -64,6 +64,7 @@ struct fwh_plan {
     int gather_variant = FWH_GATHER_AUTO, forced_splits = 0;  // fwh_plan_tune
     int gather_kind = FWH_GATHER_AUTO;  // kernel chosen by fwh_setup (FP32/BF16 modes)
     int lds_nw = 0, lds_pt = 0;  // staged window length and panels per stage of the LDS gather (0: not usable)
+    int tail_nw = 0, tail_pt = 0;  // the same for a last tile of at most 16 observers (2 x 8 wave shape; 0: none)
     int wmax = 0;                // widest delay-index window over a tile of observers
     int mfma_bpc = 0;            // resident blocks per CU of the matrix-core gather (0: not usable)
     int stream_bpc = 0;          // resident blocks per CU of the streaming gather (0: not usable)
@@ -321,6 +322,23 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         }
         pl->lds_nw = nw;
         pl->lds_pt = (int)pt;  // 0 when one panel's window does not fit
+        // a last tile of at most 16 observers runs with the 2 x 8 wave shape (16 observers x 488
+        // samples per block) and its own window length: the widest window over that tile's panels
+        pl->tail_nw = pl->tail_pt = 0;
+        const int64_t n_tiles = (O + fwh::kObsTile - 1) / fwh::kObsTile, bpt = (P + 255) / 256;
+        if (O - (n_tiles - 1) * fwh::kObsTile <= fwh::kObsTile / 2) {
+            int wt = 0;
+            for (int64_t b = (n_tiles - 1) * bpt; b < n_tiles * bpt; ++b) wt = wblk[b] > wt ? wblk[b] : wt;
+            const int nwt = ((wt + fwh::kLdsShapeK[1] + fwh::kLdsHalo + nwq - 1) / nwq) * nwq;
+            int64_t ptt = (int64_t)(fwh::kLdsBudget / (2 * fwh::gather_lds_panel_bytes(ctype, nwt, 1)));
+            if (ptt > fwh::kMaxPanelsPerStage) ptt = fwh::kMaxPanelsPerStage;
+            if (ptt > 1) {
+                const int occ1 = fwh::gather_lds_blocks_per_cu(ctype, nwt, 1, 1);
+                while (ptt > 1 && fwh::gather_lds_blocks_per_cu(ctype, nwt, (int)ptt, 1) < occ1) --ptt;
+            }
+            pl->tail_nw = nwt;
+            pl->tail_pt = (int)ptt;
+        }
         pl->wmax = wmax;
         pl->mfma_bpc = fwh::gather_mfma_blocks_per_cu(ctype, wmax);
         pl->stream_bpc = O <= fwh::kLdsWaves ? fwh::gather_stream_blocks_per_cu(ctype, pl->NS, pl->n_t_max) : 0;
@@ -470,12 +488,23 @@ int fwh_forward(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
                                             pl->at<int2>(pl->off_tw), pl->at<int32_t>(pl->off_nt),
                                             pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
                                             pl->wmax, pl->at<float>(pl->off_part), st);
-            else if (pl->gather_kind == FWH_GATHER_LDS)
-                e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
-                                           pl->at<int2>(pl->off_tw),
-                                           pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O, pl->NS,
-                                           pl->n_t_max, pl->splits, pl->lds_nw, pl->lds_pt,
-                                           pl->at<float>(pl->off_part), st);
+            else if (pl->gather_kind == FWH_GATHER_LDS) {
+                // full tiles with the 4 x 4 wave shape; a last tile of at most 16 observers with 2 x 8
+                const int64_t n_tiles = (pl->O + fwh::kObsTile - 1) / fwh::kObsTile;
+                const int64_t t_full = pl->tail_pt > 0 ? n_tiles - 1 : n_tiles;
+                e = hipSuccess;
+                if (t_full > 0)
+                    e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                               pl->at<int2>(pl->off_tw), pl->at<int32_t>(pl->off_nt),
+                                               pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
+                                               pl->lds_nw, pl->lds_pt, pl->at<float>(pl->off_part), st, 0, t_full, 0);
+                if (!e && t_full < n_tiles)
+                    e = fwh::launch_gather_lds(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                               pl->at<int2>(pl->off_tw), pl->at<int32_t>(pl->off_nt),
+                                               pl->ws + pl->off_coef, pl->P, pl->O, pl->NS, pl->n_t_max, pl->splits,
+                                               pl->tail_nw, pl->tail_pt, pl->at<float>(pl->off_part), st, t_full,
+                                               n_tiles, 1);
+            }
             else
                 e = fwh::launch_gather_tuned(coef_type, pl->at<fwh::PairRec>(pl->off_rec_op),
                                              pl->at<int32_t>(pl->off_nt), pl->ws + pl->off_coef, pl->P, pl->O,

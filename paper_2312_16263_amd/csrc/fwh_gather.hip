@@ -252,25 +252,30 @@ __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t la
     }
 }
 
-// LDS-staged gather.  Block = kLdsWaves waves, observer tile t (kObsPerWave
-// observers per wave), samples k0 .. k0 + kLdsK - 1, panels [z*p_chunk, ...) in
-// stages of PT panels, double-buffered: while the waves work on one stage the
-// direct global->LDS loads of the next are in flight.  Per panel a stage holds
-// the coefficient windows [lo + k0, lo + k0 + NW) of both channel groups
-// ([2][NW][4], lo = min n0 over the tile's observers, NW >= max width + kLdsK +
-// kLdsHalo) and the tile's pair records.  Every wave, for each of its observers
-// and each of the kLdsSub sub-blocks, lets lane l combine the 8 channels at
-// window position n0 - lo + 61 m + l (two vector LDS reads) and adds the
-// combined value times each of the four taps w_t into four accumulators; the
-// output of lane l, sum_t of accumulator t at lane l + t, is formed by three
-// wavefront shifts once per flush (12 VALU operations per panel and sub-row
-// instead of 15).
+// LDS-staged gather.  Block = kLdsWaves waves; a wave shape OPW x SUBW: each wave
+// takes OPW observers of the block's tile (TILE = kLdsWaves * OPW observers, the
+// first TILE of the 32-observer tile t) and SUBW sub-rows of kLdsLanesOut samples,
+// so the block covers samples k0 .. k0 + SUBW * kLdsLanesOut - 1; panels
+// [z*p_chunk, ...) in stages of PT panels, double-buffered: while the waves work
+// on one stage the direct global->LDS loads of the next are in flight.  Per panel
+// a stage holds the coefficient windows [lo + k0, lo + k0 + NW) of both channel
+// groups ([2][NW][4], lo = min n0 over the tile's observers, NW >= max width +
+// block samples + kLdsHalo) and the TILE pair records.  Every wave, for each of
+// its observers and sub-rows, lets lane l combine the 8 channels at window
+// position n0 - lo + 61 m + l (two vector LDS reads) and adds the combined value
+// into two tap-pair accumulators (below).  Shapes: 4 x 4 (32 observers x 244
+// samples) for full tiles; 2 x 8 (16 observers x 488 samples) for a last tile of
+// at most 16 observers, whose waves would otherwise hold one or two observers
+// each while the block still staged the full window for 244 samples (the same
+// 32 accumulators per lane, about half the staged bytes per output).
 // The two stage buffers are separate static LDS arrays (stA, stB): the compiler
 // can then tell that the direct global->LDS loads into one buffer do not alias
 // the LDS reads of the other, and does not make those reads wait for the loads.
-template <typename TS>
+template <typename TS, int OPW = kObsPerWave, int SUBW = kLdsSub>
 __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, int64_t kb, int64_t z,
                                                 unsigned char *stA, unsigned char *stB) {
+    constexpr int TILE = kLdsWaves * OPW;         // observer slots of the block
+    constexpr int KB = SUBW * kLdsLanesOut;       // samples of the block
     const PairRec *__restrict__ rec = a.rec;
     const int2 *__restrict__ tw = a.tw;
     const int32_t *__restrict__ nt = a.nt;
@@ -282,17 +287,17 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     constexpr int EB = 4 * (int)sizeof(TS);  // bytes per element (4 channels)
     constexpr bool kBf = std::is_same<TS, uint16_t>::value;
     const size_t win_bytes = (size_t)2 * NW * EB;                    // one panel, both groups
-    // stage buffer: PT windows, then PT x kObsTile records, then (BF16) PT x kObsTile split weights
+    // stage buffer: PT windows, then PT x TILE records, then (BF16) PT x TILE split weights
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t k0 = kb * kLdsK;
+    const int64_t k0 = kb * KB;
     const int64_t pb = z * p_chunk;
     const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
-    // wave wv takes the tile's observers wv, wv + 8, wv + 16, wv + 24, so that a partly filled
+    // wave wv takes the tile's observers wv, wv + 8, ... (OPW of them), so that a partly filled
     // tile spreads its observers over all waves
     const int64_t tbase = t * kObsTile;
     const int2 *twt = tw + t * P;
-    const int64_t ot_last = (O - 1 - t * kObsTile) < kObsTile - 1 ? (O - 1 - t * kObsTile) : kObsTile - 1;
+    const int64_t ot_last = (O - 1 - tbase) < TILE - 1 ? (O - 1 - tbase) : TILE - 1;
 
     // issue the loads of the stage starting at panel ps into the stage buffer `base`
     auto fill = [&](int64_t ps, unsigned char *base) {
@@ -312,27 +317,27 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
                 copy_to_lds<16>(src, last, base + q * win_bytes + g * NW * EB, units, wv, lane);
             }
         }
-        // records: for panel q, observer j of the tile -> 64 bytes at [q][j]
+        // records: for panel q, observer slot j -> 64 bytes at [q][j]
         unsigned char *rbase = base + (size_t)PT * win_bytes;
-        const int runits = np * kObsTile * 4;  // 16-byte units
+        const int runits = np * TILE * 4;  // 16-byte units
         for (int ci = wv; ci * 64 < runits; ci += kLdsWaves) {
             int u = ci * 64 + lane;
             u = u < runits ? u : runits - 1;
-            const int q = u / (kObsTile * 4), r = u - q * (kObsTile * 4);
+            const int q = u / (TILE * 4), r = u - q * (TILE * 4);
             const int64_t jj = (r >> 2) < ot_last ? (r >> 2) : ot_last;
-            const float4 *srec = reinterpret_cast<const float4 *>(rec + (t * kObsTile + jj) * P + ps + q) + (r & 3);
+            const float4 *srec = reinterpret_cast<const float4 *>(rec + (tbase + jj) * P + ps + q) + (r & 3);
             __builtin_amdgcn_global_load_lds((const void *)srec, (lds_ptr_t)(rbase + ci * 64 * 16), 16, 0, 0);
         }
         if constexpr (kBf) {
-            // split weights: for panel q, observer j of the tile -> 32 bytes at [q][j]
-            unsigned char *bbase = rbase + (size_t)PT * kObsTile * sizeof(PairRec);
-            const int bunits = np * kObsTile * 2;
+            // split weights: for panel q, observer slot j -> 32 bytes at [q][j]
+            unsigned char *bbase = rbase + (size_t)PT * TILE * sizeof(PairRec);
+            const int bunits = np * TILE * 2;
             for (int ci = wv; ci * 64 < bunits; ci += kLdsWaves) {
                 int u = ci * 64 + lane;
                 u = u < bunits ? u : bunits - 1;
-                const int q = u / (kObsTile * 2), r = u - q * (kObsTile * 2);
+                const int q = u / (TILE * 2), r = u - q * (TILE * 2);
                 const int64_t jj = (r >> 1) < ot_last ? (r >> 1) : ot_last;
-                const uint4 *sb = reinterpret_cast<const uint4 *>(a.rbf + (t * kObsTile + jj) * P + ps + q) + (r & 1);
+                const uint4 *sb = reinterpret_cast<const uint4 *>(a.rbf + (tbase + jj) * P + ps + q) + (r & 1);
                 __builtin_amdgcn_global_load_lds((const void *)sb, (lds_ptr_t)(bbase + ci * 64 * 16), 16, 0, 0);
             }
         }
@@ -345,11 +350,11 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     // w_2 g + w_3 g' over panels (the next-lane operand is a DPP source of the FMA, no extra
     // instruction).  The output of lane l is acc[j][m][0] at l plus acc[j][m][1] at l + 2; that
     // shift is the same for every panel, so it is applied once per flush (tap_sum).
-    float acc[kObsPerWave][kLdsSub][2];
+    float acc[OPW][SUBW][2];
 #pragma unroll
-    for (int j = 0; j < kObsPerWave; ++j)
+    for (int j = 0; j < OPW; ++j)
 #pragma unroll
-        for (int m = 0; m < kLdsSub; ++m) acc[j][m][0] = acc[j][m][1] = 0.f;
+        for (int m = 0; m < SUBW; ++m) acc[j][m][0] = acc[j][m][1] = 0.f;
     // acc[j][m][0] + acc[j][m][1] two lanes up (every lane must take part: lane shifts)
     auto tap_sum = [&](int j, int m) {
         return acc[j][m][0] + from_next_lane(from_next_lane(acc[j][m][1]));
@@ -364,7 +369,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     // largest of their windows (0: nothing to do)
     int nt_wave = 0, nobs = 0;
 #pragma unroll
-    for (int j = 0; j < kObsPerWave; ++j) {
+    for (int j = 0; j < OPW; ++j) {
         const int64_t o = tbase + j * kLdsWaves + wv;
         if (o < O) {
             nt_wave = nt[o] > nt_wave ? nt[o] : nt_wave;
@@ -373,7 +378,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     }
     nobs = __builtin_amdgcn_readfirstlane(nobs);
     int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
-    nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > kLdsSub ? kLdsSub : nsub));
+    nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > SUBW ? SUBW : nsub));
     // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows.  The window
     // elements are addressed by one byte offset from the stage buffer `sb` (e0: the lane's first
     // element of the panel's first channel group, less n0; the second group is NW elements
@@ -384,7 +389,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
         for (int j = 0; j < NOBS; ++j) {
-            const int slot = q * kObsTile + j * kLdsWaves + wv;
+            const int slot = q * TILE + j * kLdsWaves + wv;
             const float4 *R = lrec + slot * 4;
             const float4 W = R[2];
             const int b0 = (e0 + __float_as_int(R[3].x)) * EB;
@@ -393,7 +398,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             float4 Ka, Kb;
             uint4 Kh, Kl;
             if constexpr (kBf) {
-                const uint4 *B = reinterpret_cast<const uint4 *>(lrec + PT * kObsTile * 4) + slot * 2;
+                const uint4 *B = reinterpret_cast<const uint4 *>(lrec + PT * TILE * 4) + slot * 2;
                 Kh = B[0];
                 Kl = B[1];
             } else {
@@ -488,11 +493,11 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         }
         // final sums; outputs past an observer's window are zero
 #pragma unroll
-        for (int j = 0; j < kObsPerWave; ++j) {
+        for (int j = 0; j < OPW; ++j) {
             const int64_t o = tbase + j * kLdsWaves + wv;
             const int64_t ntl = o < O ? nt[o] : 0;
 #pragma unroll
-            for (int m = 0; m < kLdsSub; ++m) {
+            for (int m = 0; m < SUBW; ++m) {
                 const float v = tap_sum(j, m);
                 float *dst = out_ptr(j, m);
                 if (dst) {
@@ -505,42 +510,67 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     };
     // every record slot of the tile holds a valid record (slots past the last observer repeat
     // it); the wave skips the sub-rows past its observers' windows and the observer slots past its
-    // last valid one (3 valid slots run as 4)
+    // last valid one.  Compiled (observers, sub-rows) pairs: 4 x 4 shape: observers 1, 2, 4 (3 runs
+    // as 4), sub-rows 1 .. 4; 2 x 8 shape: observers 1, 2, sub-rows 2, 4, 6, 8 (odd counts run one
+    // more sub-row, whose outputs lie past the windows and are not kept)
     auto by_sub = [&](auto nobs_c) {
-        switch (nsub) {
-            case 1: stage_loop(nobs_c, std::integral_constant<int, 1>{}); break;
-            case 2: stage_loop(nobs_c, std::integral_constant<int, 2>{}); break;
-            case 3: stage_loop(nobs_c, std::integral_constant<int, 3>{}); break;
-            default: stage_loop(nobs_c, std::integral_constant<int, kLdsSub>{}); break;
+        if constexpr (SUBW == 4) {
+            switch (nsub) {
+                case 1: stage_loop(nobs_c, std::integral_constant<int, 1>{}); break;
+                case 2: stage_loop(nobs_c, std::integral_constant<int, 2>{}); break;
+                case 3: stage_loop(nobs_c, std::integral_constant<int, 3>{}); break;
+                default: stage_loop(nobs_c, std::integral_constant<int, 4>{}); break;
+            }
+        } else {
+            static_assert(SUBW == 8, "wave shapes: 4 x 4 and 2 x 8");
+            switch ((nsub + 1) >> 1) {
+                case 1: stage_loop(nobs_c, std::integral_constant<int, 2>{}); break;
+                case 2: stage_loop(nobs_c, std::integral_constant<int, 4>{}); break;
+                case 3: stage_loop(nobs_c, std::integral_constant<int, 6>{}); break;
+                default: stage_loop(nobs_c, std::integral_constant<int, 8>{}); break;
+            }
         }
     };
     if (nobs == 0 || nsub == 0) {
         stage_loop(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
-    } else {
+    } else if constexpr (OPW == 4) {
         switch (nobs) {
             case 1: by_sub(std::integral_constant<int, 1>{}); break;
             case 2: by_sub(std::integral_constant<int, 2>{}); break;
-            default: by_sub(std::integral_constant<int, kObsPerWave>{}); break;
+            default: by_sub(std::integral_constant<int, 4>{}); break;
         }
+    } else {
+        static_assert(OPW == 2, "wave shapes: 4 x 4 and 2 x 8");
+        if (nobs == 1) by_sub(std::integral_constant<int, 1>{});
+        else by_sub(std::integral_constant<int, 2>{});
     }
 }
 
-// SB: bytes of each of the two stage buffers (a size class chosen at setup)
-template <typename TS, int SB>
-__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(6))) void gather_lds_kernel(GatherArgs a, int64_t tiles, int64_t kblocks) {
+// SB: bytes of each of the two stage buffers (a size class chosen at setup).  Up to 24 KiB
+// three 8-wave blocks fit a CU (80 registers per lane, six waves per SIMD); 32 KiB buffers
+// leave room for two.
+constexpr int lds_waves_per_eu(int SB) { return SB <= 24576 ? 6 : 4; }
+
+// SHAPE 0: 4 observers x 4 sub-rows per wave; SHAPE 1: 2 x 8.  Tiles t0 .. t0 + tiles - 1.
+template <typename TS, int SB, int SHAPE>
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(SB))))
+void gather_lds_kernel(GatherArgs a, int64_t t0, int64_t tiles, int64_t kblocks) {
     __shared__ __align__(16) unsigned char stA[SB];
     __shared__ __align__(16) unsigned char stB[SB];
     // 1-D grid, block order (tile fastest, k block, split) regrouped per XCD
     const int64_t L = xcd_block(blockIdx.x, gridDim.x);
     const int64_t t = L % tiles, rest = L / tiles;
-    gather_lds_body<TS>(a, t, rest % kblocks, rest / kblocks, stA, stB);
+    if constexpr (SHAPE == 0)
+        gather_lds_body<TS, 4, 4>(a, t0 + t, rest % kblocks, rest / kblocks, stA, stB);
+    else
+        gather_lds_body<TS, 2, 8>(a, t0 + t, rest % kblocks, rest / kblocks, stA, stB);
 }
 
 // Persistent batched gather: blocks pull work items (case, tile, k-block, split)
 // in list order (longest first) through an atomic counter until the list is
 // exhausted; every block ends when it draws an index past the list.
 template <typename TS, int SB>
-__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(6))) void gather_lds_persistent(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(kLdsWaves * 64) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(SB)))) void gather_lds_persistent(const BatchCase *__restrict__ cases,
                                                                         const int4 *__restrict__ items,
                                                                         int n_items, int *__restrict__ counter) {
     __shared__ __align__(16) unsigned char stA[SB];
@@ -973,13 +1003,19 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
 
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
                              const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
-                             int PT, float *partial, hipStream_t stream) {
+                             int PT, float *partial, hipStream_t stream, int64_t t0, int64_t t1, int shape) {
     const int64_t p_chunk = (P + splits - 1) / splits;
     const GatherArgs a{rec_op, rbf, tw, nt, coef, P, O, NS, nt_max, p_chunk, NW, PT, splits, partial};
-    const int64_t tiles = (O + kObsTile - 1) / kObsTile, kblocks = (nt_max + kLdsK - 1) / kLdsK;
+    const int64_t n_tiles = (O + kObsTile - 1) / kObsTile;
+    if (t1 < 0) t1 = n_tiles;
+    if (t0 < 0 || t1 > n_tiles || t0 >= t1 || shape < 0 || shape > 1) return hipErrorInvalidValue;
+    const int64_t kb_len = shape == 0 ? kLdsK : 2 * kLdsK;
+    const int64_t tiles = t1 - t0, kblocks = (nt_max + kb_len - 1) / kb_len;
     const dim3 n1((unsigned)(tiles * kblocks * splits)), blk(kLdsWaves * 64);
-    const int sb = gather_lds_stage_class(coef_type, NW, PT);
-#define FWH_LDS_LAUNCH(T, S) gather_lds_kernel<T, S><<<n1, blk, 0, stream>>>(a, tiles, kblocks)
+    const int sb = gather_lds_stage_class(coef_type, NW, PT, shape);
+#define FWH_LDS_LAUNCH(T, S)                                                                   \
+    (shape == 0 ? gather_lds_kernel<T, S, 0><<<n1, blk, 0, stream>>>(a, t0, tiles, kblocks)   \
+                : gather_lds_kernel<T, S, 1><<<n1, blk, 0, stream>>>(a, t0, tiles, kblocks))
     if (coef_type == 1) {
         switch (sb) {
             case 8192: FWH_LDS_LAUNCH(float, 8192); break;
@@ -1067,30 +1103,31 @@ int gather_stream_blocks_per_cu(int coef_type, int64_t NS, int64_t nt_max) {
     return e == hipSuccess && n > 0 ? n : 0;
 }
 
-int gather_lds_stage_class(int coef_type, int NW, int PT) {
-    const size_t need = gather_lds_shmem(coef_type, NW, PT) / 2;  // one of the two stage buffers
+int gather_lds_stage_class(int coef_type, int NW, int PT, int shape) {
+    const size_t need = gather_lds_shmem(coef_type, NW, PT, shape) / 2;  // one of the two stage buffers
     for (int sb : {8192, 12288, 16384, 24576, 32768})
         if (need <= (size_t)sb) return sb;
     return 0;
 }
 
-template <typename T>
+template <typename T, int SHAPE>
 static const void *lds_kernel_ptr(int sb) {
     switch (sb) {
-        case 8192: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 8192>);
-        case 12288: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 12288>);
-        case 16384: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 16384>);
-        case 24576: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 24576>);
-        default: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 32768>);
+        case 8192: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 8192, SHAPE>);
+        case 12288: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 12288, SHAPE>);
+        case 16384: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 16384, SHAPE>);
+        case 24576: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 24576, SHAPE>);
+        default: return reinterpret_cast<const void *>(&gather_lds_kernel<T, 32768, SHAPE>);
     }
 }
 
-int gather_lds_blocks_per_cu(int coef_type, int NW, int PT) {
-    const int sb = gather_lds_stage_class(coef_type, NW, PT);
+int gather_lds_blocks_per_cu(int coef_type, int NW, int PT, int shape) {
+    const int sb = gather_lds_stage_class(coef_type, NW, PT, shape);
     if (sb == 0) return 1;
+    const void *k = coef_type == 1 ? (shape == 0 ? lds_kernel_ptr<float, 0>(sb) : lds_kernel_ptr<float, 1>(sb))
+                                   : (shape == 0 ? lds_kernel_ptr<uint16_t, 0>(sb) : lds_kernel_ptr<uint16_t, 1>(sb));
     int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, coef_type == 1 ? lds_kernel_ptr<float>(sb) : lds_kernel_ptr<uint16_t>(sb), kLdsWaves * 64, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kLdsWaves * 64, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -191,8 +191,9 @@ hipError_t launch_tables(int mode, const double *y, const double *dS, const doub
 // per block of 256 (t, p) entries the largest hi - lo -> wblk[block].
 hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
                               hipStream_t stream);
+// blocks of the tile-window reduction: ceil(P / 256) per tile of kObsTile observers
 inline int64_t tile_window_blocks(int64_t P, int64_t O) {
-    return ((O + kObsTile - 1) / kObsTile * P + 255) / 256;
+    return (O + kObsTile - 1) / kObsTile * ((P + 255) / 256);
 }
 
 // Chunked source stage (FP32/BF16 modes).  A block owns kSrcPanels panels and
@@ -247,20 +248,29 @@ hipError_t launch_gather_tuned(int coef_type, const PairRec *rec_op, const int32
                                int64_t O, int64_t NS, int64_t nt_max, int splits, float *partial,
                                hipStream_t stream);
 // LDS-staged gather; NW = staged window length per channel group (multiple of 64, >= max
-// width + kLdsK + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
+// width + block samples + kLdsHalo), PT = panels per stage (two stages fit in kLdsBudget).
+// Wave shapes: 0 = 4 observers x 4 sub-rows (tiles of 32 observers, kLdsK samples per block);
+// 1 = 2 observers x 8 sub-rows (a last tile of at most 16 observers, 2 kLdsK samples per block).
+constexpr int kLdsShapeTile[2] = {kObsTile, kObsTile / 2};
+constexpr int kLdsShapeK[2] = {kLdsK, 2 * kLdsK};
 // Per panel of a stage: both windows, the tile's records and, in BF16 mode, its split weights.
-inline size_t gather_lds_panel_bytes(int coef_type, int NW) {
+inline size_t gather_lds_panel_bytes(int coef_type, int NW, int shape = 0) {
     const size_t esz = coef_type == 1 ? 4 : 2;
-    return (size_t)8 * NW * esz + (size_t)kObsTile * (sizeof(PairRec) + (coef_type == 1 ? 0 : sizeof(PairBf)));
+    return (size_t)8 * NW * esz +
+           (size_t)kLdsShapeTile[shape] * (sizeof(PairRec) + (coef_type == 1 ? 0 : sizeof(PairBf)));
 }
-inline size_t gather_lds_shmem(int coef_type, int NW, int PT) { return 2 * (size_t)PT * gather_lds_panel_bytes(coef_type, NW); }
+inline size_t gather_lds_shmem(int coef_type, int NW, int PT, int shape = 0) {
+    return 2 * (size_t)PT * gather_lds_panel_bytes(coef_type, NW, shape);
+}
 // size class (bytes) of each of the two static stage buffers for this staging size (0: too large)
-int gather_lds_stage_class(int coef_type, int NW, int PT);
+int gather_lds_stage_class(int coef_type, int NW, int PT, int shape = 0);
 // blocks of the LDS-staged gather resident per CU at this staging size (registers and LDS)
-int gather_lds_blocks_per_cu(int coef_type, int NW, int PT);
+int gather_lds_blocks_per_cu(int coef_type, int NW, int PT, int shape = 0);
+// tiles t0 .. t1 - 1 of 32 observers (t1 < 0: all) with wave shape `shape`
 hipError_t launch_gather_lds(int coef_type, const PairRec *rec_op, const PairBf *rbf, const int2 *tw, const int32_t *nt,
                              const void *coef, int64_t P, int64_t O, int64_t NS, int64_t nt_max, int splits, int NW,
-                             int PT, float *partial, hipStream_t stream);
+                             int PT, float *partial, hipStream_t stream, int64_t t0 = 0, int64_t t1 = -1,
+                             int shape = 0);
 // Matrix-core gather (fwh_gather_mfma.hip): per panel a Y tile [kObsTile][YR] floats in LDS covering
 // the window of the widest tile (wmax = largest n0 spread over a tile's observers).
 inline int gather_mfma_y_row(int wmax) { return ((wmax + kLdsK + kLdsHalo + 15) / 16) * 16 + 4; }

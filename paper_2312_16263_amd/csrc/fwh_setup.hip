@@ -155,14 +155,17 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
     }
 }
 
-// Window of the fractional-delay index over an observer tile, per panel.
+// Window of the fractional-delay index over an observer tile, per panel; wblk[b] = the widest
+// window of block b, and a block covers panels of one tile only (blocks t * bpt .. t * bpt +
+// bpt - 1 belong to tile t, bpt = ceil(P / 256)), so every tile's widest window can be read off.
 __global__ __launch_bounds__(256) void tile_window_kernel(const PairRec *__restrict__ rec_op, int64_t P, int64_t O,
-                                                          int64_t n_tiles, int2 *__restrict__ tw,
+                                                          int64_t bpt, int2 *__restrict__ tw,
                                                           int32_t *__restrict__ wblk) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = blockIdx.x / bpt;
+    const int64_t p = (blockIdx.x - t * bpt) * 256 + threadIdx.x;
     int width = 0;
-    if (i < n_tiles * P) {
-        const int64_t t = i / P, p = i - t * P;
+    if (p < P) {
+        const int64_t i = t * P + p;
         const int64_t o0 = t * kObsTile;
         const int64_t o1 = o0 + kObsTile < O ? o0 + kObsTile : O;
         int lo = INT_MAX, hi = INT_MIN;
@@ -188,9 +191,8 @@ __global__ __launch_bounds__(256) void tile_window_kernel(const PairRec *__restr
 
 hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
                               hipStream_t stream) {
-    const int64_t n_tiles = (O + kObsTile - 1) / kObsTile;
-    tile_window_kernel<<<dim3((unsigned)tile_window_blocks(P, O)), dim3(256), 0, stream>>>(rec_op, P, O, n_tiles, tw,
-                                                                                         wblk);
+    tile_window_kernel<<<dim3((unsigned)tile_window_blocks(P, O)), dim3(256), 0, stream>>>(rec_op, P, O,
+                                                                                         (P + 255) / 256, tw, wblk);
     return hipGetLastError();
 }
 
