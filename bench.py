@@ -38,16 +38,23 @@ LOWO_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_dipole32768_o
 
 def measured_traffic(kernel, path=TRAFFIC_PROFILE):
     """HBM bytes per launch of `kernel` (read + written, copy-calibrated) from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None."""
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None.  A name `k<T>` also
+    takes the rows `k<T, s>` of its wave shapes s (one launch each per gather), summed."""
+    total, found = 0.0, False
+    shaped = kernel[:-1] + ", " if kernel.endswith(">") else None
     try:
         with open(path) as f:
             for line in f:
                 cells = [c.strip() for c in line.strip().strip("|").split("|")]
-                if len(cells) == 5 and cells[0].strip("`") == kernel:
-                    return (float(cells[3]) + float(cells[4])) * 1e9
+                if len(cells) != 5:
+                    continue
+                name = cells[0].strip("`")
+                if name == kernel or (shaped and name.startswith(shaped)):
+                    total += (float(cells[3]) + float(cells[4])) * 1e9
+                    found = True
     except (OSError, ValueError):
         return None
-    return None
+    return total if found else None
 
 
 GATHER_KERNELS = {"lds": "gather_lds_kernel", "stream": "gather_stream_kernel", "mfma": "gather_mfma_kernel",
