@@ -795,10 +795,13 @@ __device__ __forceinline__ void src_adj_general_block(const SrcAdjArgs &a, int64
     src_adj_chain_out<TIn>(lds + (kAdjLo - 1) * kSrcRS, a, pbk * kSrcPanels, k * kSrcTC);
 }
 
-// grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
+// 1-D grid of (panel block, interior chunk) pairs, chunks fastest, renumbered per XCD: the chunks of
+// one panel block run together on one XCD, so the coefficient-adjoint rows that neighbouring chunks
+// both read (the recurrences' overlap) come from that XCD's L2 rather than from HBM twice.
 template <typename TIn>
-__global__ __launch_bounds__(256) void src_adj_interior_kernel(SrcAdjArgs a) {
-    src_adj_interior_block<TIn>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
+__global__ __launch_bounds__(256) void src_adj_interior_kernel(SrcAdjArgs a, int64_t nint) {
+    const int64_t L = xcd_block(blockIdx.x, gridDim.x), pbk = L / nint;
+    src_adj_interior_block<TIn>(a, pbk, 1 + L - pbk * nint);
 }
 // grid (panel blocks, general chunks)
 template <typename TIn>
@@ -808,8 +811,9 @@ __global__ __launch_bounds__(256) void src_adj_general_kernel(SrcAdjArgs a) {
 template <typename TIn>
 __global__ __launch_bounds__(256) void src_adj_interior_batched(const BatchCase *__restrict__ cases,
                                                                 const int64_t *__restrict__ start, int n) {
-    const int c = find_case(start, n, blockIdx.x);
-    const int64_t local = (int64_t)blockIdx.x - start[c];
+    const int64_t h = xcd_block(blockIdx.x, gridDim.x);
+    const int c = find_case(start, n, h);
+    const int64_t local = h - start[c];
     const int64_t nk = adj_interior_chunks(cases[c].sadj.N);
     const int64_t pbk = local / nk;
     src_adj_interior_block<TIn>(cases[c].sadj, pbk, 1 + local - pbk * nk);
@@ -832,7 +836,7 @@ hipError_t src_adj_chunk_launch_t(const SrcAdjArgs &a, hipStream_t stream) {
     const int64_t nint = adj_interior_chunks(a.N);
     const int64_t ngen = adj_chunks(a.N) - nint;
     if (nint > 0) {
-        src_adj_interior_kernel<TIn><<<dim3(pb, (unsigned)nint), dim3(256), 0, stream>>>(a);
+        src_adj_interior_kernel<TIn><<<dim3((unsigned)(pb * nint)), dim3(256), 0, stream>>>(a, nint);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -976,7 +980,9 @@ __global__ __launch_bounds__(256) void source_fwd_kernel(SrcFwdArgs a) {
     source_fwd_body<TIn, TScr, TOut>(a, blockIdx.x, blockIdx.y);
 }
 
-// grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y
+// grid (panel blocks, interior chunks): chunk k = 1 + blockIdx.y.  (Chunks of one panel block on one
+// XCD, as the source adjoint runs them, did not cut this stage's HBM reads: a chunk reads the rows it
+// shares with the next one last, the next chunk reads them first.)
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_kernel(SrcFwdArgs a) {
     src_chunk_block<TIn, TOut, false>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
