@@ -381,6 +381,7 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                                           float *tile, float *dvt) {
     const int64_t P = a.P, N = a.N;
     const int pl = threadIdx.x & 31;
+    const int half = (threadIdx.x >> 5) & 1;  // row of a pair this half-wave computes X for
     const int64_t pbase = pbk * kSrcPanels;
     const int64_t pc = min(pbase + pl, P - 1);
     const SrcLane<TIn> L(a, pc);
@@ -428,71 +429,81 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
         __syncthreads();
         if (m + 1 < kSrcNG) dma.issue(m + 1, ((m + 1) & 1) ? ring1 : ring0, wv, lane_row, lane_off, R0, N);
         const TIn *buf = (m & 1) ? ring1 : ring0;
-#pragma unroll
-        for (int r = 0; r < kSrcG; ++r) {
-            const int k = m * kSrcG + r;
-            if (k < kSrcNX) {
-                const TIn *rw = buf + r * kSrcPanels + pl;
-                constexpr int VS = kSrcG * kSrcPanels;  // variable stride
-                const Raw v{rw[0], rw[VS], rw[2 * VS], rw[3 * VS], rw[4 * VS]};
-                double Xn = L.X(v);
-                if constexpr (GEN) {
-                    const int mrow = R0i - 3 + k;
-                    if ((unsigned)mrow >= (unsigned)Ni) Xn = 0.0;
-                }
-                Xa = Xb;
-                Xb = Xc;
-                Xc = Xd;
-                Xd = Xe;
-                Xe = Xn;
-                if (k >= 4) {
-                    const int it = k - 4;
-                    const int n = R0i - 1 + it;
-                    double fn;
-                    if constexpr (!GEN) {
-                        fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
-                    } else {
-                        fn = 0.0;
-                        if ((unsigned)n < (unsigned)Ni) {
-                            const double dx = n == 0 ? -3.0 * Xc + 4.0 * Xd - Xe
-                                                     : (n == Ni - 1 ? 3.0 * Xc - 4.0 * Xb + Xa : Xd - Xb);
-                            fn = L.s_der * dx + L.s_val * Xc;
-                        }
-                        if (n == 0) f0 = fn;
-                        if (n == Ni - 1) fN1 = fn;
+        // Rows go in pairs: lanes 0-31 compute X of row k, lanes 32-63 (the same panel and base
+        // quantity) X of row k + 1, and one swap of the halves (v_permlane32_swap, per dword) gives
+        // every lane both, so each source term is computed once instead of once per half.
+        auto row_step = [&](const int k, const double Xn) __attribute__((always_inline)) {
+            Xa = Xb;
+            Xb = Xc;
+            Xc = Xd;
+            Xd = Xe;
+            Xe = Xn;
+            if (k >= 4) {
+                const int it = k - 4;
+                const int n = R0i - 1 + it;
+                double fn;
+                if constexpr (!GEN) {
+                    fn = L.s_der * (Xd - Xb) + L.s_val * Xc;
+                } else {
+                    fn = 0.0;
+                    if ((unsigned)n < (unsigned)Ni) {
+                        const double dx = n == 0 ? -3.0 * Xc + 4.0 * Xd - Xe
+                                                 : (n == Ni - 1 ? 3.0 * Xc - 4.0 * Xb + Xa : Xd - Xb);
+                        fn = L.s_der * dx + L.s_val * Xc;
                     }
-                    if (it >= 2) {
-                        float dvs;
-                        if constexpr (!GEN) {
-                            const double d = (6.0 * fprev - dprev) * cpi;
+                    if (n == 0) f0 = fn;
+                    if (n == Ni - 1) fN1 = fn;
+                }
+                if (it >= 2) {
+                    float dvs;
+                    if constexpr (!GEN) {
+                        const double d = (6.0 * fprev - dprev) * cpi;
+                        dprev = d;
+                        dvs = (float)d;
+                    } else {
+                        const int rr = n - 1;  // system row
+                        dvs = 0.f;
+                        if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) {
+                            double rhs = 6.0 * fprev;
+                            if (rr == 1) rhs -= f0;
+                            if (rr == Ni - 2) rhs -= fn;
+                            const double piv = cpi * (1.0 - qf) / (1.0 - qf * q);
+                            qf *= q;
+                            const double d = (rhs - dprev) * piv;
                             dprev = d;
                             dvs = (float)d;
-                        } else {
-                            const int rr = n - 1;  // system row
-                            dvs = 0.f;
-                            if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) {
-                                double rhs = 6.0 * fprev;
-                                if (rr == 1) rhs -= f0;
-                                if (rr == Ni - 2) rhs -= fn;
-                                const double piv = cpi * (1.0 - qf) / (1.0 - qf * q);
-                                qf *= q;
-                                const double d = (rhs - dprev) * piv;
-                                dprev = d;
-                                dvs = (float)d;
-                                if (rr == Ni - 2) dN2 = d;
-                            }
-                        }
-                        if constexpr (GEN) {
-                            DV(it - 2) = dvs;
-                        } else {
-                            dvr[it - 2] = dvs;
-                            // computed here, not sunk to the back substitution (which would keep
-                            // every row's inputs live)
-                            asm volatile("" : "+v"(dvr[it - 2]));
+                            if (rr == Ni - 2) dN2 = d;
                         }
                     }
-                    fprev = fn;
+                    if constexpr (GEN) {
+                        DV(it - 2) = dvs;
+                    } else {
+                        dvr[it - 2] = dvs;
+                        // computed here, not sunk to the back substitution (which would keep
+                        // every row's inputs live)
+                        asm volatile("" : "+v"(dvr[it - 2]));
+                    }
                 }
+                fprev = fn;
+            }
+        };
+#pragma unroll
+        for (int r = 0; r < kSrcG; r += 2) {
+            const int k = m * kSrcG + r;
+            if (k < kSrcNX) {
+                const TIn *rw = buf + (r + half) * kSrcPanels + pl;
+                constexpr int VS = kSrcG * kSrcPanels;  // variable stride
+                const Raw v{rw[0], rw[VS], rw[2 * VS], rw[3 * VS], rw[4 * VS]};
+                double Xm = L.X(v);
+                if constexpr (GEN) {
+                    const int mrow = R0i - 3 + k + half;
+                    if ((unsigned)mrow >= (unsigned)Ni) Xm = 0.0;
+                }
+                const unsigned xl = (unsigned)__double2loint(Xm), xh = (unsigned)__double2hiint(Xm);
+                const auto sl = __builtin_amdgcn_permlane32_swap(xl, xl, false, false);
+                const auto sh = __builtin_amdgcn_permlane32_swap(xh, xh, false, false);
+                row_step(k, __hiloint2double((int)sh[0], (int)sl[0]));  // row k (lanes 0-31's value)
+                if (k + 1 < kSrcNX) row_step(k + 1, __hiloint2double((int)sh[1], (int)sl[1]));
             }
             __builtin_amdgcn_sched_barrier(0);
         }
