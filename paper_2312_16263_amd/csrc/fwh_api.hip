@@ -289,13 +289,13 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
                                 pl->at<double>(pl->off_x), pl->at<double>(pl->off_ts), pl->at<int32_t>(pl->off_nt), P,
                                 O, N, pl->flow, f64 ? pl->at<double>(pl->off_K64) : nullptr,
                                 f64 ? pl->at<double>(pl->off_W64) : nullptr, f64 ? pl->at<int32_t>(pl->off_N0) : nullptr,
-                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(), st)))
+                                f64 ? nullptr : pl->at<fwh::PairRec>(pl->off_rec_op), pl->rbf(),
+                                f64 ? nullptr : pl->at<int2>(pl->off_tw), f64 ? nullptr : pl->at<int32_t>(pl->off_wblk),
+                                st)))
         return hip_fail("fwh_setup: table kernel", e);
     if (!f64) {
-        // per (observer tile, panel) windows of n0 and their largest width -> LDS staging geometry
-        if ((e = fwh::launch_tile_window(pl->at<fwh::PairRec>(pl->off_rec_op), P, O, pl->at<int2>(pl->off_tw),
-                                         pl->at<int32_t>(pl->off_wblk), st)))
-            return hip_fail("fwh_setup: tile window kernel", e);
+        // per (observer tile, panel) windows of n0 (from the table kernel) and their largest width
+        // -> LDS staging geometry
         const int64_t nb = fwh::tile_window_blocks(P, O);
         std::vector<int32_t> wblk((size_t)nb);
         if ((e = hipMemcpyAsync(wblk.data(), pl->at<int32_t>(pl->off_wblk), nb * sizeof(int32_t),
@@ -325,7 +325,8 @@ int fwh_setup(fwh_plan *pl, void *workspace, size_t workspace_bytes, void *strea
         // a last tile of at most 16 observers runs with the 2 x 8 wave shape (16 observers x 488
         // samples per block) and its own window length: the widest window over that tile's panels
         pl->tail_nw = pl->tail_pt = 0;
-        const int64_t n_tiles = (O + fwh::kObsTile - 1) / fwh::kObsTile, bpt = (P + 255) / 256;
+        const int64_t n_tiles = (O + fwh::kObsTile - 1) / fwh::kObsTile,
+                      bpt = (P + fwh::tile_window_panels() - 1) / fwh::tile_window_panels();
         if (O - (n_tiles - 1) * fwh::kObsTile <= fwh::kObsTile / 2) {
             int wt = 0;
             for (int64_t b = (n_tiles - 1) * bpt; b < n_tiles * bpt; ++b) wt = wblk[b] > wt ? wblk[b] : wt;

@@ -952,12 +952,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     adj_gather_mfma_body(cases[c].adj, g * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
-// out[o][k] = sum_z partial[z][o][k] in fixed order.
+// out[o][k] = sum_z partial[z][o][k] in fixed order.  Eight loads are issued before they are
+// added (the sum keeps its order), so each thread has eight reads in flight instead of one.
+__device__ __forceinline__ float sum_splits(const float *__restrict__ partial, int splits, int64_t total,
+                                            int64_t i) {
+    double s = 0.0;
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = partial[(int64_t)(z + j) * total + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += (double)v[j];
+    }
+    for (; z < splits; ++z) s += (double)partial[(int64_t)z * total + i];
+    return (float)s;
+}
+
 __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int64_t i) {
     if (i >= a.total) return;
-    double s = 0.0;
-    for (int z = 0; z < a.splits; ++z) s += (double)a.partial[(int64_t)z * a.total + i];
-    a.out[i] = (float)s;
+    a.out[i] = sum_splits(a.partial, a.splits, a.total, i);
 }
 
 __global__ __launch_bounds__(256) void reduce_batched(const BatchCase *__restrict__ cases,
@@ -970,9 +984,7 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float *__restr
                                                             int64_t total, float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += (double)partial[(int64_t)z * total + i];
-    out[i] = (float)s;
+    out[i] = sum_splits(partial, splits, total, i);
 }
 
 }  // namespace

@@ -182,18 +182,18 @@ struct BatchIndex {
 hipError_t launch_delay(const double *y, const double *x_obs, int64_t P, int64_t O, Flow f, double *D,
                         hipStream_t stream);
 hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hipStream_t stream);
-// mode 0: FP64 tables (K64 [O][P][8], W64 [O][P][4], N0 [O][P]); mode 1/2: PairRec [O][P].
+// mode 0: FP64 tables (K64 [O][P][8], W64 [O][P][4], N0 [O][P]); mode 1/2: PairRec [O][P] (and
+// rbf, if not null), plus per (observer tile t, panel p) the lo/hi of n0 over the tile's observers
+// -> tw[t][p], and per block of tile_window_panels() panels of one tile the largest hi - lo ->
+// wblk[block] (tile_window_blocks(P, O) blocks, tile-major).
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, PairBf *rbf, hipStream_t stream);
-
-// Per (observer tile t, panel p): lo/hi of n0 over the tile's observers -> tw[t][p];
-// per block of 256 (t, p) entries the largest hi - lo -> wblk[block].
-hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
-                              hipStream_t stream);
-// blocks of the tile-window reduction: ceil(P / 256) per tile of kObsTile observers
+                         int32_t *N0, PairRec *rec_op, PairBf *rbf, int2 *tw, int32_t *wblk, hipStream_t stream);
+// blocks of the FP32/BF16 table kernel, which also reduces the tile windows: ceil(P / 8) per tile of
+// kObsTile observers (8 panels x 32 observers per block)
+inline int64_t tile_window_panels() { return 256 / kObsTile; }
 inline int64_t tile_window_blocks(int64_t P, int64_t O) {
-    return (O + kObsTile - 1) / kObsTile * ((P + 255) / 256);
+    return (O + kObsTile - 1) / kObsTile * ((P + tile_window_panels() - 1) / tile_window_panels());
 }
 
 // Chunked source stage (FP32/BF16 modes).  A block owns kSrcPanels panels and

@@ -80,16 +80,16 @@ __global__ __launch_bounds__(256) void minmax_kernel(const double *__restrict__ 
 //   Ldot_i: M0 Rhat_i/(R om^2)         L_i: (Rhat_i - M_i)/(R^2 om^2) + Rhat_i (M_R - M0^2)/(R^2 om^3)
 // with om = 1 - M_R (the L_M term is L . M, Eq. (LM)).  With rbf (BF16 mode)
 // the weights are also stored split into bfloat16 high and low parts.
-__global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__restrict__ y,
-                                                     const double *__restrict__ dS, const double *__restrict__ x_obs,
-                                                     const double *__restrict__ t_start,
-                                                     const int32_t *__restrict__ nt, int64_t P, int64_t O,
-                                                     int64_t N, Flow f, double *__restrict__ K64,
-                                                     double *__restrict__ W64, int32_t *__restrict__ N0,
-                                                     PairRec *__restrict__ rec_op, PairBf *__restrict__ rbf) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * O) return;
-    const int64_t o = i / P, p = i - o * P;
+struct PairTab {
+    double K[8], w[4];
+    int32_t n0;
+};
+
+__device__ __forceinline__ PairTab pair_tables(const double *__restrict__ y, const double *__restrict__ dS,
+                                               const double *__restrict__ x_obs, const double *__restrict__ t_start,
+                                               const int32_t *__restrict__ nt, int64_t N, const Flow &f, int64_t o,
+                                               int64_t p) {
+    PairTab pt;
     double R, Rh[3], MR;
     pair_geometry(x_obs + 3 * o, y + 3 * p, f, R, Rh, MR);
     double D;
@@ -104,35 +104,70 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
     if (nf > nmax) nf = nmax;
     double t = s0 - nf;
     if (t > 1.0) t = 1.0;
-    const int32_t n0 = (int32_t)nf;
+    pt.n0 = (int32_t)nf;
     const double u = 1.0 - t;
-    double w[4];
-    w[0] = u * u * u / 6.0;
-    w[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
-    w[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
-    w[3] = t * t * t / 6.0;
+    pt.w[0] = u * u * u / 6.0;
+    pt.w[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+    pt.w[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+    pt.w[3] = t * t * t / 6.0;
 
     const double M0 = f.M0, M2 = f.M0 * f.M0;
     const double Mv[3] = {-M0 * f.ca, -M0 * f.sa, 0.0};
     const double om = 1.0 - MR, om2 = om * om, om3 = om2 * om;
     const double ws = dS[p] / (4.0 * kPi);
-    double K[8];
-    K[0] = ws / (R * om2);
-    K[1] = ws * (MR - M2) / (M0 * R * R * om3);
+    pt.K[0] = ws / (R * om2);
+    pt.K[1] = ws * (MR - M2) / (M0 * R * R * om3);
     for (int c = 0; c < 3; ++c) {
-        K[2 + c] = ws * M0 * Rh[c] / (R * om2);
-        K[5 + c] = ws * ((Rh[c] - Mv[c]) / (R * R * om2) + Rh[c] * (MR - M2) / (R * R * om3));
+        pt.K[2 + c] = ws * M0 * Rh[c] / (R * om2);
+        pt.K[5 + c] = ws * ((Rh[c] - Mv[c]) / (R * R * om2) + Rh[c] * (MR - M2) / (R * R * om3));
     }
-    if (mode == 0) {
-        for (int c = 0; c < 8; ++c) K64[i * 8 + c] = K[c];
-        for (int j = 0; j < 4; ++j) W64[i * 4 + j] = w[j];
-        N0[i] = n0;
-    } else {
+    return pt;
+}
+
+// plain FP64 form: the tables as FP64 arrays [O][P]
+__global__ __launch_bounds__(256) void tables_f64_kernel(const double *__restrict__ y, const double *__restrict__ dS,
+                                                         const double *__restrict__ x_obs,
+                                                         const double *__restrict__ t_start,
+                                                         const int32_t *__restrict__ nt, int64_t P, int64_t O,
+                                                         int64_t N, Flow f, double *__restrict__ K64,
+                                                         double *__restrict__ W64, int32_t *__restrict__ N0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * O) return;
+    const int64_t o = i / P, p = i - o * P;
+    const PairTab pt = pair_tables(y, dS, x_obs, t_start, nt, N, f, o, p);
+    for (int c = 0; c < 8; ++c) K64[i * 8 + c] = pt.K[c];
+    for (int j = 0; j < 4; ++j) W64[i * 4 + j] = pt.w[j];
+    N0[i] = pt.n0;
+}
+
+// FP32/BF16 forms: block = one observer tile (kObsTile observers) x kTabPanels panels; thread
+// (observer slot j, panel q) writes the pair record [o][p] (and, with rbf, the bfloat16 high/low
+// split of the weights), then the block reduces n0 over the tile's observers per panel: tw[t][p] =
+// (min n0, max n0), and wblk[block] = the widest window of the block's panels (blocks t * bpt ..
+// t * bpt + bpt - 1 belong to tile t, bpt = ceil(P / kTabPanels)).
+constexpr int kTabPanels = 256 / kObsTile;
+__global__ __launch_bounds__(256) void tables_tile_kernel(const double *__restrict__ y, const double *__restrict__ dS,
+                                                          const double *__restrict__ x_obs,
+                                                          const double *__restrict__ t_start,
+                                                          const int32_t *__restrict__ nt, int64_t P, int64_t O,
+                                                          int64_t N, Flow f, int64_t bpt, PairRec *__restrict__ rec_op,
+                                                          PairBf *__restrict__ rbf, int2 *__restrict__ tw,
+                                                          int32_t *__restrict__ wblk) {
+    const int64_t t = blockIdx.x / bpt;
+    const int j = threadIdx.x / kTabPanels, q = threadIdx.x % kTabPanels;
+    const int64_t o = t * kObsTile + j, p = (blockIdx.x - t * bpt) * kTabPanels + q;
+    __shared__ int sn0[kObsTile][kTabPanels];
+    __shared__ int sw[kTabPanels];
+    int n0 = 0;
+    if (o < O && p < P) {
+        const PairTab pt = pair_tables(y, dS, x_obs, t_start, nt, N, f, o, p);
+        n0 = pt.n0;
         PairRec r;
-        for (int c = 0; c < 8; ++c) r.K[c] = (float)K[c];
-        for (int j = 0; j < 4; ++j) r.w[j] = (float)w[j];
-        r.n0 = n0;
+        for (int c = 0; c < 8; ++c) r.K[c] = (float)pt.K[c];
+        for (int jj = 0; jj < 4; ++jj) r.w[jj] = (float)pt.w[jj];
+        r.n0 = pt.n0;
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        const int64_t i = o * P + p;
         rec_op[i] = r;
         if (rbf) {
             // bfloat16 by round-to-nearest-even of the FP32 value (weights are finite)
@@ -140,61 +175,44 @@ __global__ __launch_bounds__(256) void tables_kernel(int mode, const double *__r
                 const uint32_t b = __float_as_uint((float)v);
                 return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
             };
-            PairBf q;
+            PairBf qb;
             for (int c = 0; c < 4; ++c) {
                 uint32_t h[2], l[2];
                 for (int e = 0; e < 2; ++e) {
-                    h[e] = bf16(K[2 * c + e]);
-                    l[e] = bf16(K[2 * c + e] - (double)__uint_as_float(h[e] << 16));
+                    h[e] = bf16(pt.K[2 * c + e]);
+                    l[e] = bf16(pt.K[2 * c + e] - (double)__uint_as_float(h[e] << 16));
                 }
-                q.hi[c] = h[0] | (h[1] << 16);
-                q.lo[c] = l[0] | (l[1] << 16);
+                qb.hi[c] = h[0] | (h[1] << 16);
+                qb.lo[c] = l[0] | (l[1] << 16);
             }
-            rbf[i] = q;
+            rbf[i] = qb;
         }
     }
-}
-
-// Window of the fractional-delay index over an observer tile, per panel; wblk[b] = the widest
-// window of block b, and a block covers panels of one tile only (blocks t * bpt .. t * bpt +
-// bpt - 1 belong to tile t, bpt = ceil(P / 256)), so every tile's widest window can be read off.
-__global__ __launch_bounds__(256) void tile_window_kernel(const PairRec *__restrict__ rec_op, int64_t P, int64_t O,
-                                                          int64_t bpt, int2 *__restrict__ tw,
-                                                          int32_t *__restrict__ wblk) {
-    const int64_t t = blockIdx.x / bpt;
-    const int64_t p = (blockIdx.x - t * bpt) * 256 + threadIdx.x;
-    int width = 0;
-    if (p < P) {
-        const int64_t i = t * P + p;
-        const int64_t o0 = t * kObsTile;
-        const int64_t o1 = o0 + kObsTile < O ? o0 + kObsTile : O;
-        int lo = INT_MAX, hi = INT_MIN;
-        for (int64_t o = o0; o < o1; ++o) {
-            const int n0 = rec_op[o * P + p].n0;
-            lo = n0 < lo ? n0 : lo;
-            hi = n0 > hi ? n0 : hi;
-        }
-        tw[i] = make_int2(lo, hi);
-        width = hi - lo;
-    }
-    __shared__ int sw[256];
-    sw[threadIdx.x] = width;
+    sn0[j][q] = n0;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sw[threadIdx.x] = sw[threadIdx.x] > sw[threadIdx.x + s] ? sw[threadIdx.x] : sw[threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x < kTabPanels) {
+        const int64_t nobs = O - t * kObsTile < kObsTile ? O - t * kObsTile : kObsTile;
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int jj = 0; jj < nobs; ++jj) {
+            lo = sn0[jj][q] < lo ? sn0[jj][q] : lo;
+            hi = sn0[jj][q] > hi ? sn0[jj][q] : hi;
+        }
+        int width = 0;
+        if (p < P) {
+            tw[t * P + p] = make_int2(lo, hi);
+            width = hi - lo;
+        }
+        sw[q] = width;
     }
-    if (threadIdx.x == 0) wblk[blockIdx.x] = sw[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int qq = 0; qq < kTabPanels; ++qq) m = sw[qq] > m ? sw[qq] : m;
+        wblk[blockIdx.x] = m;
+    }
 }
 
 }  // namespace
-
-hipError_t launch_tile_window(const PairRec *rec_op, int64_t P, int64_t O, int2 *tw, int32_t *wblk,
-                              hipStream_t stream) {
-    tile_window_kernel<<<dim3((unsigned)tile_window_blocks(P, O)), dim3(256), 0, stream>>>(rec_op, P, O,
-                                                                                         (P + 255) / 256, tw, wblk);
-    return hipGetLastError();
-}
 
 hipError_t launch_delay(const double *y, const double *x_obs, int64_t P, int64_t O, Flow f, double *D,
                         hipStream_t stream) {
@@ -210,10 +228,15 @@ hipError_t launch_minmax(const double *D, int64_t P, int64_t O, double *dmm, hip
 
 hipError_t launch_tables(int mode, const double *y, const double *dS, const double *x_obs, const double *t_start,
                          const int32_t *nt, int64_t P, int64_t O, int64_t N, Flow f, double *K64, double *W64,
-                         int32_t *N0, PairRec *rec_op, PairBf *rbf, hipStream_t stream) {
-    const int64_t n = P * O;
-    tables_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(mode, y, dS, x_obs, t_start, nt, P, O, N,
-                                                                            f, K64, W64, N0, rec_op, rbf);
+                         int32_t *N0, PairRec *rec_op, PairBf *rbf, int2 *tw, int32_t *wblk, hipStream_t stream) {
+    if (mode == 0) {
+        const int64_t n = P * O;
+        tables_f64_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(y, dS, x_obs, t_start, nt, P,
+                                                                                        O, N, f, K64, W64, N0);
+    } else {
+        tables_tile_kernel<<<dim3((unsigned)tile_window_blocks(P, O)), dim3(256), 0, stream>>>(
+            y, dS, x_obs, t_start, nt, P, O, N, f, (P + kTabPanels - 1) / kTabPanels, rec_op, rbf, tw, wblk);
+    }
     return hipGetLastError();
 }
 
