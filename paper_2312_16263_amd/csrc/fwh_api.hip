@@ -95,6 +95,14 @@ int64_t split_cap(int64_t P) {
     return std::max<int64_t>(1, std::min<int64_t>(fwh::kMaxPanelSplits, (P + kMinSplitPanels - 1) / kMinSplitPanels));
 }
 
+// shortest observer window of a set-up plan (every observer's gradient reaches the coefficient
+// indices [N - shortest, shortest + 2])
+int64_t nt_min(const fwh_plan *pl) {
+    int64_t m = pl->n_t_max;
+    for (int64_t v : pl->n_t) m = v < m ? v : m;
+    return m;
+}
+
 int layout(fwh_plan *pl) {
     const size_t P = (size_t)pl->P, O = (size_t)pl->O, N = (size_t)pl->N, NS = (size_t)pl->NS;
     size_t off = 0;
@@ -541,8 +549,9 @@ int fwh_adjoint(fwh_plan *pl, int32_t in_dtype, const void *rho, const void *u, 
                                        pl->at<double>(pl->off_coef), st);
     else
         e = fwh::launch_adj_gather(pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<int32_t>(pl->off_nt),
-                                       static_cast<const float *>(grad_p), pl->P, pl->O, pl->N, pl->NS, pl->n_t_max,
-                                       pl->at<float>(pl->off_gpad), pl->at<float>(pl->off_coef), st);
+                                       static_cast<const float *>(grad_p), pl->P, pl->O, pl->N, pl->NS,
+                                       nt_min(pl), pl->n_t_max, pl->at<float>(pl->off_gpad),
+                                       pl->at<float>(pl->off_coef), st);
     }
     if (e) return hip_fail("fwh_adjoint: transposed gather", e);
     {
@@ -789,7 +798,7 @@ int fwh_batch_bind(fwh_batch *b, void *workspace, size_t workspace_bytes, void *
         d.pad = fwh::PadArgs{static_cast<const float *>(k.grad_p), pl->at<int32_t>(pl->off_nt), O, ntm, LR, padlo,
                              pl->at<float>(pl->off_gpad)};
         d.adj = fwh::AdjArgs{pl->at<fwh::PairRec>(pl->off_rec_op), pl->at<float>(pl->off_gpad), P, O, NS, LR, padlo,
-                             nib, pl->at<float>(pl->off_coef)};
+                             nib, pl->at<float>(pl->off_coef), ntm, N - nt_min(pl), nt_min(pl) + 2};
         d.sadj = fwh::SrcAdjArgs{pl->at<float>(pl->off_coef), k.rho, k.u, pl->at<double>(pl->off_n), P, N, NS,
                                  pl->flow, pl->at<double>(pl->off_cp), k.g_rho, k.g_u, k.g_p};
         const int64_t src_int = fwh::src_interior_chunks(N);

@@ -871,13 +871,31 @@ __device__ __forceinline__ void adj_gather_mfma_body(const AdjArgs &a, int64_t w
         for (int u = 0; u < kAdjMW; ++u) b.x[u] = *reinterpret_cast<const AdjF4 *>(go + uoff[u]);
         if (s == 0) b.pv = *reinterpret_cast<const AdjF4 *>(go - 4);
     };
+    // Waves near either end of the index range (check): 64-index blocks u_lo .. u_hi, those
+    // that some observer of the group reaches (observer o + q adds to indices [n0, n0 + N_t + 2]
+    // only; n0 from dword 12 of each row's record, N_t bounded by the longest window); the others
+    // would get exact zeros and are skipped.  Inside [edge_lo, edge_hi] every block is reached.
+    const bool check = ib < a.edge_lo || ib + 64 * kAdjMW - 1 > a.edge_hi;  // wave-uniform
     auto compute = [&](int64_t o, const AdjGroup &b) {
         const float kb = (o + q < O && s < 8) ? b.rv : 0.f;
         const float w0 = adj_row_bcast<8>(b.rv), w1 = adj_row_bcast<9>(b.rv), w2 = adj_row_bcast<10>(b.rv),
                     w3 = adj_row_bcast<11>(b.rv);
+        int u_lo = 0, u_hi = nsub - 1;
+        if (check) {
+            int n0lo = __builtin_amdgcn_readlane(__float_as_int(b.rv), 12), n0hi = n0lo;
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const int v = __builtin_amdgcn_readlane(__float_as_int(b.rv), 16 * r + 12);
+                n0lo = min(n0lo, v);
+                n0hi = max(n0hi, v);
+            }
+            const int ibi = (int)ib;
+            u_lo = max(0, (n0lo - ibi) >> 6);
+            u_hi = min(nsub - 1, (n0hi + (int)a.nt_max + 2 - ibi) >> 6);
+        }
 #pragma unroll
         for (int u = 0; u < kAdjMW; ++u) {
-            if (u < nsub) {
+            if (u >= u_lo && u <= u_hi) {
                 const AdjF4 xv = b.x[u];
                 // lane 0's values below e: its own load (u = 0) or lane 15's of block u - 1
                 const AdjF4 &xp = b.x[u > 0 ? u - 1 : 0];
@@ -1158,14 +1176,16 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
 }
 
 hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
-                                 int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream) {
+                                 int64_t N, int64_t NS, int64_t nt_min, int64_t nt_max, float *gpad, float *cbar,
+                                 hipStream_t stream) {
+    const int64_t edge_lo = N - nt_min, edge_hi = nt_min + 2;
     const int64_t LR = adj_pad_row(N, NS), padlo = adj_pad_lo(N);
     const PadArgs pa{gbar, nt, O, nt_max, LR, padlo, gpad};
     pad_grad_kernel<<<dim3((unsigned)((O * LR + 255) / 256)), dim3(256), 0, stream>>>(pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nib = adj_blocks(NS);
-    const AdjArgs aa{rec_op, gpad, P, O, NS, LR, padlo, nib, cbar};
+    const AdjArgs aa{rec_op, gpad, P, O, NS, LR, padlo, nib, cbar, nt_max, edge_lo, edge_hi};
     adj_gather_mfma_kernel<<<dim3((unsigned)((P * nib + 3) / 4)), dim3(256), 0, stream>>>(aa);
     return hipGetLastError();
 }

@@ -120,6 +120,10 @@ struct AdjArgs {
     const float *gpad;
     int64_t P, O, NS, LR, padlo, nib;
     float *cbar;
+    int64_t nt_max;  // longest observer window (bounds the indices an observer's gradient reaches)
+    // every observer's gradient reaches every index in [edge_lo, edge_hi] (N - shortest window, and
+    // shortest window + 2): index blocks inside need no check for blocks that get only zeros
+    int64_t edge_lo, edge_hi;
 };
 
 struct PreAdjArgs {
@@ -314,8 +318,10 @@ constexpr int kAdjMW = 4;
 constexpr int kAdjPT = 64;  // panels per tile of the transposed gather's wave order
 inline int64_t adj_blocks(int64_t NS) { return (NS + 64 * kAdjMW - 1) / (64 * kAdjMW); }
 inline int64_t adj_pad_row(int64_t N, int64_t NS) { return ((N + NS + 8 + 64 * (kAdjMW + 1) + 63) / 64) * 64; }
+// nt_min, nt_max: shortest and longest observer window
 hipError_t launch_adj_gather(const PairRec *rec_op, const int32_t *nt, const float *gbar, int64_t P, int64_t O,
-                                 int64_t N, int64_t NS, int64_t nt_max, float *gpad, float *cbar, hipStream_t stream);
+                                 int64_t N, int64_t NS, int64_t nt_min, int64_t nt_max, float *gpad, float *cbar,
+                                 hipStream_t stream);
 
 // Adjoint of the source stage: coefficient adjoints [8][P][NS] -> gradients (time-major, in_dtype).
 // real_type 0 = double (cbar and scratch double), 1 = float.
