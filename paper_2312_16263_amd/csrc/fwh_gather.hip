@@ -380,11 +380,12 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     int nsub = (int)((nt_wave - k0 + kLdsLanesOut - 1) / kLdsLanesOut);
     nsub = __builtin_amdgcn_readfirstlane(nsub < 0 ? 0 : (nsub > SUBW ? SUBW : nsub));
     // one panel of the stage for this wave's first NOBS observers, NSUB sub-rows.  The window
-    // elements are addressed by one byte offset from the stage buffer `sb` (e0: the lane's first
-    // element of the panel's first channel group, less n0; the second group is NW elements
-    // later): a longer chain of pointer arithmetic hides from the compiler which of the two buffers
-    // a read touches, and it then makes the read wait for the copies into the other one.
-    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const unsigned char *sb, int e0, int q) {
+    // elements are addressed by one byte offset from the stage buffer `sb` (qb: the byte offset of
+    // the lane's element in panel slot q's first channel group at n0 = lo; the pair record carries
+    // n0 - lo in bytes; the second group is NW elements later): a longer chain of pointer
+    // arithmetic hides from the compiler which of the two buffers a read touches, and it then makes
+    // the read wait for the copies into the other one.
+    auto panel_work = [&](auto nobs_c, auto nsub_c, const float4 *lrec, const unsigned char *sb, int qb, int q) {
         constexpr int NOBS = decltype(nobs_c)::value;
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
@@ -392,7 +393,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
             const int slot = q * TILE + j * kLdsWaves + wv;
             const float4 *R = lrec + slot * 4;
             const float4 W = R[2];
-            const int b0 = (e0 + __float_as_int(R[3].x)) * EB;
+            const int b0 = qb + __float_as_int(R[3].y);
             const QT *P0 = reinterpret_cast<const QT *>(sb + b0);
             const QT *P1 = reinterpret_cast<const QT *>(sb + (b0 + NW * EB));
             float4 Ka, Kb;
@@ -447,31 +448,17 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NSUB = decltype(nsub_c)::value;
         int cnt = 0;
         bool flushed = false;  // some chunk sum is already in the outputs
-        // window starts of a stage's panels, lane q <-> panel ps + q, loaded with the stage
-        auto load_lo = [&](int64_t ps) {
-            const int64_t q = ps + lane < pe ? ps + lane : pe - 1;
-            return twt[q].x;
-        };
-        int lo_cur = 0;
-        if (pb < pe) {
-            fill(pb, stA);
-            lo_cur = load_lo(pb);
-        }
+        if (pb < pe) fill(pb, stA);
         // one stage from buffer `cur` while the next one is copied into `nxt`
         auto stage = [&](int64_t ps, const unsigned char *cur, unsigned char *nxt) __attribute__((always_inline)) {
             const int np = (int)(pe - ps < PT ? pe - ps : PT);
             __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of stage ps have landed
             __syncthreads();                // ... and every wave's; the other buffer is free
-            const int lo_stage = lo_cur;
-            if (ps + PT < pe) {
-                fill(ps + PT, nxt);
-                lo_cur = load_lo(ps + PT);
-            }
+            if (ps + PT < pe) fill(ps + PT, nxt);
             const unsigned char *base = cur;
             const float4 *lrec = reinterpret_cast<const float4 *>(base + (size_t)PT * win_bytes);
             for (int q = 0; q < np; ++q) {
-                const int lo = __builtin_amdgcn_readlane(lo_stage, q);
-                panel_work(nobs_c, nsub_c, lrec, base, (int)(q * win_bytes / EB) + lane - lo, q);
+                panel_work(nobs_c, nsub_c, lrec, base, (int)(q * win_bytes) + lane * EB, q);
                 if (++cnt == kLdsChunk) {
 #pragma unroll
                     for (int j = 0; j < NOBS; ++j)

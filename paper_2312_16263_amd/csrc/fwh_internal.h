@@ -18,7 +18,10 @@ struct alignas(64) PairRec {
     float K[8];
     float w[4];
     int32_t n0;
-    int32_t pad[3];
+    // byte offset of the pair's element n0 in its panel's staged window of the LDS-staged gather:
+    // (n0 - lo) x 16 (FP32) or x 8 (BF16), lo = min n0 over the pair's 32-observer tile
+    int32_t n0w;
+    int32_t pad[2];
 };
 static_assert(sizeof(PairRec) == 64, "PairRec must be 64 bytes");
 

@@ -141,10 +141,11 @@ __global__ __launch_bounds__(256) void tables_f64_kernel(const double *__restric
 }
 
 // FP32/BF16 forms: block = one observer tile (kObsTile observers) x kTabPanels panels; thread
-// (observer slot j, panel q) writes the pair record [o][p] (and, with rbf, the bfloat16 high/low
-// split of the weights), then the block reduces n0 over the tile's observers per panel: tw[t][p] =
-// (min n0, max n0), and wblk[block] = the widest window of the block's panels (blocks t * bpt ..
-// t * bpt + bpt - 1 belong to tile t, bpt = ceil(P / kTabPanels)).
+// (observer slot j, panel q) computes the pair's tables, the block reduces n0 over the tile's
+// observers per panel: tw[t][p] = (lo, hi) = (min n0, max n0), and wblk[block] = the widest window
+// of the block's panels (blocks t * bpt .. t * bpt + bpt - 1 belong to tile t, bpt = ceil(P /
+// kTabPanels)); then each thread writes its pair record [o][p] with n0 - lo in staged bytes (and,
+// with rbf, the bfloat16 high/low split of the weights).
 constexpr int kTabPanels = 256 / kObsTile;
 __global__ __launch_bounds__(256) void tables_tile_kernel(const double *__restrict__ y, const double *__restrict__ dS,
                                                           const double *__restrict__ x_obs,
@@ -157,16 +158,36 @@ __global__ __launch_bounds__(256) void tables_tile_kernel(const double *__restri
     const int j = threadIdx.x / kTabPanels, q = threadIdx.x % kTabPanels;
     const int64_t o = t * kObsTile + j, p = (blockIdx.x - t * bpt) * kTabPanels + q;
     __shared__ int sn0[kObsTile][kTabPanels];
+    __shared__ int slo[kTabPanels];
     __shared__ int sw[kTabPanels];
-    int n0 = 0;
-    if (o < O && p < P) {
-        const PairTab pt = pair_tables(y, dS, x_obs, t_start, nt, N, f, o, p);
-        n0 = pt.n0;
+    const bool valid = o < O && p < P;
+    PairTab pt;
+    if (valid) pt = pair_tables(y, dS, x_obs, t_start, nt, N, f, o, p);
+    sn0[j][q] = valid ? pt.n0 : 0;
+    __syncthreads();
+    if (threadIdx.x < kTabPanels) {
+        const int64_t nobs = O - t * kObsTile < kObsTile ? O - t * kObsTile : kObsTile;
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int jj = 0; jj < nobs; ++jj) {
+            lo = sn0[jj][q] < lo ? sn0[jj][q] : lo;
+            hi = sn0[jj][q] > hi ? sn0[jj][q] : hi;
+        }
+        int width = 0;
+        if (p < P) {
+            tw[t * P + p] = make_int2(lo, hi);
+            width = hi - lo;
+        }
+        sw[q] = width;
+        slo[q] = lo;
+    }
+    __syncthreads();
+    if (valid) {
         PairRec r;
         for (int c = 0; c < 8; ++c) r.K[c] = (float)pt.K[c];
         for (int jj = 0; jj < 4; ++jj) r.w[jj] = (float)pt.w[jj];
         r.n0 = pt.n0;
-        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        r.n0w = (pt.n0 - slo[q]) * (rbf ? 8 : 16);
+        r.pad[0] = r.pad[1] = 0;
         const int64_t i = o * P + p;
         rec_op[i] = r;
         if (rbf) {
@@ -188,23 +209,6 @@ __global__ __launch_bounds__(256) void tables_tile_kernel(const double *__restri
             rbf[i] = qb;
         }
     }
-    sn0[j][q] = n0;
-    __syncthreads();
-    if (threadIdx.x < kTabPanels) {
-        const int64_t nobs = O - t * kObsTile < kObsTile ? O - t * kObsTile : kObsTile;
-        int lo = INT_MAX, hi = INT_MIN;
-        for (int jj = 0; jj < nobs; ++jj) {
-            lo = sn0[jj][q] < lo ? sn0[jj][q] : lo;
-            hi = sn0[jj][q] > hi ? sn0[jj][q] : hi;
-        }
-        int width = 0;
-        if (p < P) {
-            tw[t * P + p] = make_int2(lo, hi);
-            width = hi - lo;
-        }
-        sw[q] = width;
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
         int m = 0;
         for (int qq = 0; qq < kTabPanels; ++qq) m = sw[qq] > m ? sw[qq] : m;
