@@ -856,7 +856,9 @@ __device__ __forceinline__ void adj_gather_mfma_body(const AdjArgs &a, int64_t w
         const float *go = g + min(o + q, O - 1) * LR - n0;
 #pragma unroll
         for (int u = 0; u < kAdjMW; ++u) b.x[u] = *reinterpret_cast<const AdjF4 *>(go + uoff[u]);
-        if (s == 0) b.pv = *reinterpret_cast<const AdjF4 *>(go - 4);
+        // only lane 0 of each row uses pv; every lane loads it (in bounds: the row's lead pad holds
+        // N + 4 floats and n0 <= N), so the register is not merged with its old value
+        b.pv = *reinterpret_cast<const AdjF4 *>(go - 4);
     };
     // Waves near either end of the index range (check): 64-index blocks u_lo .. u_hi, those
     // that some observer of the group reaches (observer o + q adds to indices [n0, n0 + N_t + 2]
