@@ -293,11 +293,14 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     const int64_t k0 = kb * KB;
     const int64_t pb = z * p_chunk;
     const int64_t pe = pb + p_chunk < P ? pb + p_chunk : P;
-    // wave wv takes the tile's observers wv, wv + 8, ... (OPW of them), so that a partly filled
-    // tile spreads its observers over all waves
     const int64_t tbase = t * kObsTile;
     const int2 *twt = tw + t * P;
     const int64_t ot_last = (O - 1 - tbase) < TILE - 1 ? (O - 1 - tbase) : TILE - 1;
+    // observer slot (offset in the tile) of the wave's j-th observer.  4 x 4 shape: the wave takes
+    // 4 adjacent observers, whose windows are alike, so fewer of its sub-rows lie past the shorter
+    // ones.  2 x 8 shape (a last tile of at most 16 observers): observers wv, wv + 8, which spreads
+    // a few observers over all waves.  Either way a wave's valid observers are a prefix j < nobs.
+    auto slot_of = [&](int j) { return OPW == 4 ? wv * OPW + j : j * kLdsWaves + wv; };
 
     // issue the loads of the stage starting at panel ps into the stage buffer `base`
     auto fill = [&](int64_t ps, unsigned char *base) {
@@ -361,7 +364,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     };
     // this wave's output element of observer slot j, sub-row m (null outside the output)
     auto out_ptr = [&](int j, int m) -> float * {
-        const int64_t o = tbase + j * kLdsWaves + wv;
+        const int64_t o = tbase + slot_of(j);
         const int64_t k = k0 + m * kLdsLanesOut + lane;
         return (lane < kLdsLanesOut && o < O && k < nt_max) ? partial + (z * O + o) * nt_max + k : nullptr;
     };
@@ -370,7 +373,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     int nt_wave = 0, nobs = 0;
 #pragma unroll
     for (int j = 0; j < OPW; ++j) {
-        const int64_t o = tbase + j * kLdsWaves + wv;
+        const int64_t o = tbase + slot_of(j);
         if (o < O) {
             nt_wave = nt[o] > nt_wave ? nt[o] : nt_wave;
             nobs = j + 1;
@@ -390,7 +393,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         constexpr int NSUB = decltype(nsub_c)::value;
 #pragma unroll
         for (int j = 0; j < NOBS; ++j) {
-            const int slot = q * TILE + j * kLdsWaves + wv;
+            const int slot = q * TILE + slot_of(j);
             const float4 *R = lrec + slot * 4;
             const float4 W = R[2];
             const int b0 = qb + __float_as_int(R[3].y);
@@ -481,7 +484,7 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
         // final sums; outputs past an observer's window are zero
 #pragma unroll
         for (int j = 0; j < OPW; ++j) {
-            const int64_t o = tbase + j * kLdsWaves + wv;
+            const int64_t o = tbase + slot_of(j);
             const int64_t ntl = o < O ? nt[o] : 0;
 #pragma unroll
             for (int m = 0; m < SUBW; ++m) {
