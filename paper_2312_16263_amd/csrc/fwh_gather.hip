@@ -271,7 +271,7 @@ __device__ __forceinline__ void copy_to_lds(const unsigned char *src, int64_t la
 // The two stage buffers are separate static LDS arrays (stA, stB): the compiler
 // can then tell that the direct global->LDS loads into one buffer do not alias
 // the LDS reads of the other, and does not make those reads wait for the loads.
-template <typename TS, int OPW = kObsPerWave, int SUBW = kLdsSub>
+template <typename TS, int OPW = kObsPerWave, int SUBW = kLdsSub, bool ADJ = false>
 __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, int64_t kb, int64_t z,
                                                 unsigned char *stA, unsigned char *stB) {
     constexpr int TILE = kLdsWaves * OPW;         // observer slots of the block
@@ -296,11 +296,14 @@ __device__ __forceinline__ void gather_lds_body(const GatherArgs &a, int64_t t, 
     const int64_t tbase = t * kObsTile;
     const int2 *twt = tw + t * P;
     const int64_t ot_last = (O - 1 - tbase) < TILE - 1 ? (O - 1 - tbase) : TILE - 1;
-    // observer slot (offset in the tile) of the wave's j-th observer.  4 x 4 shape: the wave takes
-    // 4 adjacent observers, whose windows are alike, so fewer of its sub-rows lie past the shorter
-    // ones.  2 x 8 shape (a last tile of at most 16 observers): observers wv, wv + 8, which spreads
-    // a few observers over all waves.  Either way a wave's valid observers are a prefix j < nobs.
-    auto slot_of = [&](int j) { return OPW == 4 ? wv * OPW + j : j * kLdsWaves + wv; };
+    // observer slot (offset in the tile) of the wave's j-th observer.  ADJ: the wave takes OPW
+    // adjacent observers, whose windows are alike, so fewer of its sub-rows lie past the shorter
+    // ones (the single-case 4 x 4 launch, whose tiles are full but for the last).  Otherwise
+    // observers wv, wv + 8, ..., which spreads the few observers of a partly filled tile over all
+    // waves (the 2 x 8 shape, for a last tile of at most 16 observers, and the batched gather,
+    // where many cases end in such a tile).  Either way a wave's valid observers are a prefix
+    // j < nobs.
+    auto slot_of = [&](int j) { return ADJ ? wv * OPW + j : j * kLdsWaves + wv; };
 
     // issue the loads of the stage starting at panel ps into the stage buffer `base`
     auto fill = [&](int64_t ps, unsigned char *base) {
@@ -551,7 +554,7 @@ void gather_lds_kernel(GatherArgs a, int64_t t0, int64_t tiles, int64_t kblocks)
     const int64_t L = xcd_block(blockIdx.x, gridDim.x);
     const int64_t t = L % tiles, rest = L / tiles;
     if constexpr (SHAPE == 0)
-        gather_lds_body<TS, 4, 4>(a, t0 + t, rest % kblocks, rest / kblocks, stA, stB);
+        gather_lds_body<TS, 4, 4, true>(a, t0 + t, rest % kblocks, rest / kblocks, stA, stB);
     else
         gather_lds_body<TS, 2, 8>(a, t0 + t, rest % kblocks, rest / kblocks, stA, stB);
 }
