@@ -944,7 +944,7 @@ __device__ __forceinline__ void adj_gather_mfma_body(const AdjArgs &a, int64_t w
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void adj_gather_mfma_kernel(AdjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void adj_gather_mfma_kernel(AdjArgs a) {
     // consecutive blocks (neighbouring index blocks and panels) regrouped per XCD
     adj_gather_mfma_body(a, xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
@@ -955,9 +955,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
 // The items are sorted by their work (the paper's greedy partition by size) and
 // blocks are dispatched in order, so every compute unit takes the longest item
 // left when one of its blocks ends.  (A persistent form pulling items through a
-// counter keeps the case arguments live across items: 193 registers per lane,
-// against 122 here.)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void adj_gather_listed(const BatchCase *__restrict__ cases,
+// counter keeps the case arguments live across items: it needs more registers per
+// lane than the three waves per SIMD this launch runs with allow.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void adj_gather_listed(const BatchCase *__restrict__ cases,
                                                          const int2 *__restrict__ items) {
     const int2 w = items[blockIdx.x];
     const int c = __builtin_amdgcn_readfirstlane(w.x);

@@ -317,7 +317,7 @@ hipError_t launch_adj_gather_f64(const double *K64, const double *W64, const int
 inline int64_t adj_pad_lo(int64_t N) { return N + 4; }
 // blocks of 64 coefficient indices per wave of the transposed gather; a gpad row covers every
 // position it reads (from -n0 - 4 to NS - 1 - n0 past padlo, n0 < N)
-constexpr int kAdjMW = 4;
+constexpr int kAdjMW = 5;
 constexpr int kAdjPT = 64;  // panels per tile of the transposed gather's wave order
 inline int64_t adj_blocks(int64_t NS) { return (NS + 64 * kAdjMW - 1) / (64 * kAdjMW); }
 inline int64_t adj_pad_row(int64_t N, int64_t NS) { return ((N + NS + 8 + 64 * (kAdjMW + 1) + 63) / 64) * 64; }
