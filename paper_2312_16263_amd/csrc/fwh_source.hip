@@ -639,11 +639,18 @@ struct AdjLane {
 constexpr int kAdjSlab = 32;            // storage indices per staged slab
 constexpr int kAdjSlabRS = kAdjSlab + 1;
 
-// Interior chunk: rows [m0 - kAdjLo, m0 - kAdjLo + kAdjW) inside [kSrcPivotRows, N - 3];
-// the coefficient adjoints come in through LDS slabs of 32 indices x 256 rows
-// (8 lanes per 128-byte row segment), the reduced right-hand sides stay in registers.
-template <typename TIn>
-__device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pbk, int64_t k, float *lds) {
+// One chunk of kSrcTC frames m0 .. m0 + 63 for 32 panels: window rows s = 0 .. kAdjW - 1 are
+// system rows r = m0 - kAdjLo + s (storage index r + 1).  The coefficient adjoints come in
+// through LDS slabs of 32 indices x 256 rows (8 lanes per 128-byte row segment); the reduced
+// right-hand sides, then z, then Xbar stay in registers (the window loops are unrolled, so every
+// row position is a compile-time index).
+// GEN = false (interior chunk, every row in [kSrcPivotRows, N - 3]): constant pivot, no end rows.
+// GEN = true (either record end in reach, or a short record): the exact pivots cp[r], the end
+// rows' right-hand-side corrections, fbar_0 and fbar_{N-1}, one-sided differences at the first
+// and last frames, as block-uniform predicates on the row; slab indices outside the row are
+// clamped into it (those rows are never used).
+template <typename TIn, bool GEN>
+__device__ __forceinline__ void src_adj_chunk(const SrcAdjArgs &a, int64_t pbk, int64_t k, float *lds) {
     const int64_t P = a.P, NS = a.NS;
     const int pl = threadIdx.x & 31;
     const int64_t pbase = pbk * kSrcPanels;
@@ -658,7 +665,9 @@ __device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pb
             const int e = threadIdx.x + 256 * j;
             const int row = e >> 3, qd = e & 7;
             const int64_t pr = min(pbase + (row & 31), P - 1);
-            const float *src = a.cbar + ((int64_t)(row >> 5) * P + pr) * NS + i_lo + t * kAdjSlab + 4 * qd;
+            int64_t idx = i_lo + t * kAdjSlab + 4 * qd;  // a multiple of 4, as NS is
+            if constexpr (GEN) idx = idx < 0 ? 0 : (idx > NS - 4 ? NS - 4 : idx);
+            const float *src = a.cbar + ((int64_t)(row >> 5) * P + pr) * NS + idx;
             v[j] = *reinterpret_cast<const float4 *>(src);
         }
     };
@@ -674,6 +683,19 @@ __device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pb
         }
     };
     const int myrow = L.ch * 32 + pl;
+    // GEN: end data of this thread's row (a_{-1}, a_0, a_{N-1}, a_N) and 32-bit row positions
+    const int Ni = (int)a.N, R0i = (int)(m0 - kAdjLo);
+    const double *__restrict__ cp = a.cp;
+    double am1 = 0.0, a0 = 0.0, aN1 = 0.0, aN = 0.0;
+    if constexpr (GEN) {
+        const float *row = a.cbar + ((int64_t)L.ch * P + min(pbase + pl, P - 1)) * NS;
+        am1 = row[0];
+        a0 = row[1];
+        aN1 = row[Ni];
+        aN = row[Ni + 1];
+    }
+    auto inside = [&](int r) { return (unsigned)(r - 1) < (unsigned)(Ni - 2); };  // 1 <= r <= N - 2
+    auto pivot = [&](int r) { return r < 64 ? cp[r] : cpi; };
     float dv[kAdjW];
     double dprev = 0.0;
     float4 cur[8], nxt[8];
@@ -686,26 +708,85 @@ __device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pb
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kAdjSlab; ++q) {
-            const double d = ((double)lds[myrow * kAdjSlabRS + q] - dprev) * cpi;
-            dprev = d;
-            dv[t * kAdjSlab + q] = (float)d;
+            const double c = (double)lds[myrow * kAdjSlabRS + q];
+            if constexpr (!GEN) {
+                const double d = (c - dprev) * cpi;
+                dprev = d;
+                dv[t * kAdjSlab + q] = (float)d;
+            } else {
+                const int r = R0i + t * kAdjSlab + q;
+                float v = 0.f;
+                if (inside(r)) {
+                    double cc = c;
+                    if (r == 1) cc -= am1;
+                    if (r == Ni - 2) cc -= aN;
+                    const double d = (cc - dprev) * pivot(r);
+                    dprev = d;
+                    v = (float)d;
+                }
+                dv[t * kAdjSlab + q] = v;
+            }
         }
         if (t + 1 < kAdjW / kAdjSlab) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) cur[j] = nxt[j];
         }
     }
-    // back substitution; Xbar_m once fbar_{m-1} is known (window row s = m - m0 + kAdjLo - 1),
-    // kept in place of the consumed right-hand side dv[s]
-    double z = 0.0, fp1 = 0.0, fc = 0.0;
+    if constexpr (!GEN) {
+        // back substitution; Xbar_m once fbar_{m-1} is known (window row s = m - m0 + kAdjLo - 1),
+        // kept in place of the consumed right-hand side dv[s]
+        double z = 0.0, fp1 = 0.0, fc = 0.0;
 #pragma unroll
-    for (int s = kAdjW - 1; s >= 0; --s) {
-        z = (double)dv[s] - cpi * z;
-        const double fm1 = 6.0 * z;
-        const int ml = s - kAdjLo + 1;  // frame m = m0 + ml has fbar_{m-1} = fm1
-        if (ml >= 0 && ml < kSrcTC) dv[s] = (float)(L.s_val * fc + L.s_der * (fm1 - fp1));
-        fp1 = fc;
-        fc = fm1;
+        for (int s = kAdjW - 1; s >= 0; --s) {
+            z = (double)dv[s] - cpi * z;
+            const double fm1 = 6.0 * z;
+            const int ml = s - kAdjLo + 1;  // frame m = m0 + ml has fbar_{m-1} = fm1
+            if (ml >= 0 && ml < kSrcTC) dv[s] = (float)(L.s_val * fc + L.s_der * (fm1 - fp1));
+            fp1 = fc;
+            fc = fm1;
+        }
+    } else {
+        // back substitution (z rounded to FP32 in place), then fbar and Xbar_m, which overwrites
+        // the row of fbar_{m-1} (no later frame needs it)
+        double z = 0.0, z1 = 0.0, zN2 = 0.0;
+#pragma unroll
+        for (int s = kAdjW - 1; s >= 0; --s) {
+            const int r = R0i + s;
+            if (inside(r)) {
+                z = (double)dv[s] - pivot(r) * z;
+                dv[s] = (float)z;
+                if (r == 1) z1 = z;
+                if (r == Ni - 2) zN2 = z;
+            }
+        }
+        const double fb0 = a0 + 2.0 * am1 - z1, fbN1 = aN1 + 2.0 * aN - zN2;
+        // fbar_j of window row s = j - (m0 - kAdjLo)
+        auto fbar = [&](int j, int s_) -> double {
+            if (j == 0) return fb0;
+            if (j == Ni - 1) return fbN1;
+            if (inside(j)) return 6.0 * (double)dv[s_];
+            return 0.0;
+        };
+        const double sd = L.s_der;
+#pragma unroll
+        for (int ml = 0; ml < kSrcTC; ++ml) {
+            const int m = R0i + kAdjLo + ml;
+            double xb = 0.0;
+            if (m < Ni) {
+                const double fm = fbar(m, ml + kAdjLo);
+                double dx = 0.0;
+                if (inside(m - 1)) dx += fbar(m - 1, ml + kAdjLo - 1);
+                if (inside(m + 1)) dx -= fbar(m + 1, ml + kAdjLo + 1);
+                if (m == 0) dx -= 3.0 * fb0;
+                if (m == 1) dx += 4.0 * fb0;
+                if (m == 2) dx -= fb0;
+                if (m == Ni - 1) dx += 3.0 * fbN1;
+                if (m == Ni - 2) dx -= 4.0 * fbN1;
+                if (m == Ni - 3) dx += fbN1;
+                xb = L.s_val * fm + sd * dx;
+            }
+            dv[ml + kAdjLo - 1] = (float)xb;
+        }
     }
     // chain rule in two halves of kSrcTC / 2 frames through a [kSrcTC / 2][kSrcRS] tile
     constexpr int HT = kSrcTC / 2;
@@ -719,91 +800,18 @@ __device__ __forceinline__ void src_adj_interior(const SrcAdjArgs &a, int64_t pb
     }
 }
 
-// General chunk (either record end in reach, or short records): exact end rows
-// and pivots; reduced right-hand sides and then z in the LDS window
-// [kAdjW][kSrcRS]; Xbar_m overwrites the row of fbar_{m-1}, so the Xbar tile
-// starts at window row kAdjLo - 1.
-template <typename TIn>
-__device__ __forceinline__ void src_adj_general(const SrcAdjArgs &a, int64_t pbk, int64_t k, float *lds) {
-    const int64_t P = a.P, N = a.N, NS = a.NS;
-    const int pl = threadIdx.x & 31;
-    const int64_t pbase = pbk * kSrcPanels;
-    const int64_t pc = min(pbase + pl, P - 1);
-    const AdjLane L(a.f.dtau);
-    const double *__restrict__ cp = a.cp;
-    const double cpi = 2.0 - sqrt(3.0);
-    const int myrow = L.ch * 32 + pl;
-    const float *row = a.cbar + ((int64_t)L.ch * P + pc) * NS;
-    const int64_t m0 = k * kSrcTC;
-    const int64_t R0 = m0 - kAdjLo;
-    const double am1 = row[0], a0 = row[1], aN1 = row[N], aN = row[N + 1];
-    double dprev = 0.0;
-    for (int s = 0; s < kAdjW; ++s) {
-        const int64_t r = R0 + s;
-        float v = 0.f;
-        if (r >= 1 && r <= N - 2) {
-            double c = (double)row[r + 1];
-            if (r == 1) c -= am1;
-            if (r == N - 2) c -= aN;
-            const double d = (c - dprev) * (r < 64 ? cp[r] : cpi);
-            dprev = d;
-            v = (float)d;
-        }
-        lds[s * kSrcRS + myrow] = v;
-    }
-    double z = 0.0, z1 = 0.0, zN2 = 0.0;
-    for (int s = kAdjW - 1; s >= 0; --s) {
-        const int64_t r = R0 + s;
-        if (r >= 1 && r <= N - 2) {
-            z = (double)lds[s * kSrcRS + myrow] - (r < 64 ? cp[r] : cpi) * z;
-            lds[s * kSrcRS + myrow] = (float)z;
-            if (r == 1) z1 = z;
-            if (r == N - 2) zN2 = z;
-        }
-    }
-    const double fb0 = a0 + 2.0 * am1 - z1, fbN1 = aN1 + 2.0 * aN - zN2;
-    auto fbar = [&](int64_t j) -> double {  // j within the window rows
-        if (j == 0) return fb0;
-        if (j == N - 1) return fbN1;
-        if (j >= 1 && j <= N - 2) return 6.0 * (double)lds[(j - R0) * kSrcRS + myrow];
-        return 0.0;
-    };
-    const double sd = L.s_der;
-    for (int ml = 0; ml < kSrcTC; ++ml) {
-        const int64_t m = m0 + ml;
-        double xb = 0.0;
-        if (m < N) {
-            const double fm = fbar(m);
-            double dx = 0.0;
-            if (m - 1 >= 1 && m - 1 <= N - 2) dx += fbar(m - 1);
-            if (m + 1 >= 1 && m + 1 <= N - 2) dx -= fbar(m + 1);
-            if (m == 0) dx -= 3.0 * fb0;
-            if (m == 1) dx += 4.0 * fb0;
-            if (m == 2) dx -= fb0;
-            if (m == N - 1) dx += 3.0 * fbN1;
-            if (m == N - 2) dx -= 4.0 * fbN1;
-            if (m == N - 3) dx += fbN1;
-            xb = L.s_val * fm + sd * dx;
-        }
-        // row of fbar_{m-1} is no longer needed by frames >= m
-        lds[(ml + kAdjLo - 1) * kSrcRS + myrow] = (float)xb;
-    }
-}
-
+// slabs [256][kAdjSlabRS], then the Xbar tile [kSrcTC / 2][kSrcRS]
+constexpr int kAdjWords = 256 * kAdjSlabRS > (kSrcTC / 2) * kSrcRS ? 256 * kAdjSlabRS : (kSrcTC / 2) * kSrcRS;
 template <typename TIn>
 __device__ __forceinline__ void src_adj_interior_block(const SrcAdjArgs &a, int64_t pbk, int64_t k) {
-    // slabs [256][kAdjSlabRS], then the Xbar tile [kSrcTC / 2][kSrcRS]
-    constexpr int kWords = 256 * kAdjSlabRS > (kSrcTC / 2) * kSrcRS ? 256 * kAdjSlabRS : (kSrcTC / 2) * kSrcRS;
-    __shared__ float lds[kWords];
-    src_adj_interior<TIn>(a, pbk, k, lds);
+    __shared__ float lds[kAdjWords];
+    src_adj_chunk<TIn, false>(a, pbk, k, lds);
 }
 
 template <typename TIn>
 __device__ __forceinline__ void src_adj_general_block(const SrcAdjArgs &a, int64_t pbk, int64_t k) {
-    __shared__ float lds[kAdjW * kSrcRS];
-    src_adj_general<TIn>(a, pbk, k, lds);
-    __syncthreads();
-    src_adj_chain_out<TIn>(lds + (kAdjLo - 1) * kSrcRS, a, pbk * kSrcPanels, k * kSrcTC);
+    __shared__ float lds[kAdjWords];
+    src_adj_chunk<TIn, true>(a, pbk, k, lds);
 }
 
 // 1-D grid of (panel block, interior chunk) pairs, chunks fastest, renumbered per XCD: the chunks of
