@@ -388,12 +388,11 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     using Raw = typename SrcLane<TIn>::Raw;
     const double cpi = 2.0 - sqrt(3.0);
     const int64_t R0 = i0 - 1 - kSrcH;
-    // Exact Thomas pivots of tridiag(1, 4, 1) (GEN): c'_1 = 1/4, c'_n = 1/(4 - c'_{n-1}), in closed
-    // form c'_n = cpi (1 - q^n) / (1 - q^(n+1)) with q = cpi^2, carried as a running power of q
-    // (equal to cpi to double precision past n = 14)
-    const double q = cpi * cpi;
-    double qf = 0.0;  // q^rr of the next forward row rr >= 1
-    if constexpr (GEN) qf = exp((double)max<int64_t>(R0, 1) * log(q));
+    // Exact Thomas pivots of tridiag(1, 4, 1) (GEN): c'_1 = 1/4, c'_n = 1/(4 - c'_{n-1}), from the
+    // plan's table a.cp (a uniform load; equal to cpi to double precision past n = 30, so rows from
+    // 64 on take cpi)
+    const double *__restrict__ cpt = a.cp;
+    auto pivot = [&](int rr) { return rr < 64 ? cpt[rr] : cpi; };
     // 32-bit copies for the block-uniform end rules (records are far below 2^31 frames)
     const int R0i = (int)R0, Ni = (int)N;
     // two buffers of [rho, u1, u2, u3, p'] x kSrcG rows x 32 panels; group m in buffer m & 1
@@ -409,14 +408,10 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     }
     const SrcDma<TIn> dma(a, wv);
     dma.issue(0, ring0, wv, lane_row, lane_off, R0, N);
-    // reduced right-hand sides, then coefficients, of window rows s: registers (interior) or the
-    // LDS tile dvt[s][kSrcRS] (GEN, whose end rules would otherwise keep too much live)
+    // reduced right-hand sides, then coefficients, of window rows s, in registers
     const int col = L.ch * 32 + pl;
-    float dvr[GEN ? 1 : kSrcW];
-    auto DV = [&](int s_) -> float & {
-        if constexpr (GEN) return dvt[s_ * kSrcRS + col];
-        else return dvr[s_];
-    };
+    float dvr[kSrcW];
+    auto DV = [&](int s_) -> float & { return dvr[s_]; };
     // Forward sweep over source-term rows k (record row R0 - 3 + k).  Step it (it = 0 .. kSrcW + 1,
     // right-hand side of frame n = R0 - 1 + it) takes X of frames n - 2 .. n + 2 = rows it .. it + 4.
     double Xa = 0.0, Xb = 0.0, Xc = 0.0, Xd = 0.0, Xe = 0.0;
@@ -467,22 +462,17 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                             double rhs = 6.0 * fprev;
                             if (rr == 1) rhs -= f0;
                             if (rr == Ni - 2) rhs -= fn;
-                            const double piv = cpi * (1.0 - qf) / (1.0 - qf * q);
-                            qf *= q;
+                            const double piv = pivot(rr);
                             const double d = (rhs - dprev) * piv;
                             dprev = d;
                             dvs = (float)d;
                             if (rr == Ni - 2) dN2 = d;
                         }
                     }
-                    if constexpr (GEN) {
-                        DV(it - 2) = dvs;
-                    } else {
-                        dvr[it - 2] = dvs;
-                        // computed here, not sunk to the back substitution (which would keep
-                        // every row's inputs live)
-                        asm volatile("" : "+v"(dvr[it - 2]));
-                    }
+                    dvr[it - 2] = dvs;
+                    // computed here, not sunk to the back substitution (which would keep every
+                    // row's inputs live)
+                    asm volatile("" : "+v"(dvr[it - 2]));
                 }
                 fprev = fn;
             }
@@ -510,9 +500,6 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     }
     // back substitution from the top of the window; window row s holds coefficient index i = R0 + s + 1
     double x = 0.0;
-    double qb = 0.0;  // q^rr of the current backward row (GEN; underflows harmlessly to 0 for large rr)
-    if constexpr (GEN) qb = exp((double)(R0 + kSrcW - 1) * log(q));
-    const double iq = 1.0 / q;
 #pragma unroll
     for (int s = kSrcW - 1; s >= 0; --s) {
         if constexpr (!GEN) {
@@ -520,8 +507,7 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
             dvr[s] = (float)x;
         } else {
             const int rr = R0i + s;
-            if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) x = (double)DV(s) - cpi * (1.0 - qb) / (1.0 - qb * q) * x;
-            qb *= iq;
+            if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) x = (double)DV(s) - pivot(rr) * x;
             if (s >= kSrcH && s < kSrcH + kSrcTC) {
                 const int i = rr + 1;
                 double v;
@@ -536,19 +522,14 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
         }
     }
     TOut *coef = static_cast<TOut *>(a.coef);
-    if constexpr (GEN) {
+    constexpr int QT = kSrcTC / 4;
+#pragma unroll
+    for (int qt = 0; qt < 4; ++qt) {
+        __syncthreads();  // the previous quarter's tile has been read
+#pragma unroll
+        for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dvr[kSrcH + qt * QT + q];
         __syncthreads();
-        src_flush(dvt + kSrcH * kSrcRS, coef, pbase, P, a.NS, i0);
-    } else {
-        constexpr int QT = kSrcTC / 4;
-#pragma unroll
-        for (int qt = 0; qt < 4; ++qt) {
-            __syncthreads();  // the previous quarter's tile has been read
-#pragma unroll
-            for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dvr[kSrcH + qt * QT + q];
-            __syncthreads();
-            src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
-        }
+        src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
     }
 }
 
@@ -556,7 +537,7 @@ template <typename TIn, typename TOut, bool GEN>
 __device__ __forceinline__ void src_chunk_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
     __shared__ TIn ring0[kSrcGV];
     __shared__ TIn ring1[kSrcGV];
-    __shared__ float tile[GEN ? kSrcW * kSrcRS : (kSrcTC / 4) * kSrcRS];
+    __shared__ float tile[(kSrcTC / 4) * kSrcRS];
     src_chunk<TIn, TOut, GEN>(a, pbk, k * kSrcTC, ring0, ring1, tile, tile);
 }
 
@@ -1008,7 +989,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 }
 // grid (panel blocks, general chunks)
 template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) void src_general_kernel(SrcFwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void src_general_kernel(SrcFwdArgs a) {
     src_chunk_block<TIn, TOut, true>(a, blockIdx.x, src_general_chunk(blockIdx.y, src_interior_chunks(a.N)));
 }
 // batched: blocks of case c are [start[c], start[c+1]), panel block major
@@ -1022,7 +1003,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     src_chunk_block<TIn, TOut, false>(cases[c].src, pbk, 1 + local - pbk * nk);
 }
 template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) void src_general_batched(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void src_general_batched(const BatchCase *__restrict__ cases,
                                                            const int64_t *__restrict__ start, int n) {
     const int c = find_case(start, n, blockIdx.x);
     const int64_t local = (int64_t)blockIdx.x - start[c];
