@@ -212,9 +212,9 @@ __device__ __forceinline__ void source_fwd_body(const SrcFwdArgs &a, int64_t bx,
 // window that reaches row 1 is exact) and back-substitutes from the top of the
 // window (exact when it reaches row N-2).  Starting elsewhere from zero moves
 // the chunk's coefficients by about (2 - sqrt 3)^kSrcH = 7e-10 of their local
-// scale, below the FP32/BF16 storage rounding.  No scratch: the coefficients
-// leave through an LDS tile [kSrcTC][257] as 16-byte (8-byte for BF16) quads
-// of the interleaved layout.
+// scale, below the FP32/BF16 storage rounding.  No workspace buffer: the
+// coefficients leave through an LDS tile [kSrcTC / 4][257], a quarter of the
+// chunk at a time, as 16-byte (8-byte for BF16) quads of the interleaved layout.
 constexpr int kSrcRS = 257;  // LDS row: 8 channels x 32 panels + 1
 
 // Per-thread source-term form X = a p' + rho (b.u - g) u.n - d, which covers
@@ -378,7 +378,7 @@ struct SrcDma {
 
 template <typename TIn, typename TOut, bool GEN>
 __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0, TIn *ring1,
-                                          float *tile, float *dvt) {
+                                          float *tile) {
     const int64_t P = a.P, N = a.N;
     const int pl = threadIdx.x & 31;
     const int half = (threadIdx.x >> 5) & 1;  // row of a pair this half-wave computes X for
@@ -538,7 +538,7 @@ __device__ __forceinline__ void src_chunk_block(const SrcFwdArgs &a, int64_t pbk
     __shared__ TIn ring0[kSrcGV];
     __shared__ TIn ring1[kSrcGV];
     __shared__ float tile[(kSrcTC / 4) * kSrcRS];
-    src_chunk<TIn, TOut, GEN>(a, pbk, k * kSrcTC, ring0, ring1, tile, tile);
+    src_chunk<TIn, TOut, GEN>(a, pbk, k * kSrcTC, ring0, ring1, tile);
 }
 
 // ------------------------------------------------ chunked source adjoint stage
