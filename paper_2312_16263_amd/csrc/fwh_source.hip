@@ -376,9 +376,13 @@ struct SrcDma {
     }
 };
 
-template <typename TIn, typename TOut, bool GEN>
+// ENDS (GEN): which record ends the chunk's rows can reach, bit 0 the first frame (R0 <= 3), bit 1
+// the last (R0 + kSrcW >= N - 1); the rules of an end out of reach are compiled out (they would be
+// false at run time), which keeps a one-ended chunk within 3 waves' registers.
+template <typename TIn, typename TOut, bool GEN, int ENDS = 3>
 __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0, TIn *ring1,
                                           float *tile) {
+    constexpr bool kStart = (ENDS & 1) != 0, kEnd = (ENDS & 2) != 0;
     const int64_t P = a.P, N = a.N;
     const int pl = threadIdx.x & 31;
     const int half = (threadIdx.x >> 5) & 1;  // row of a pair this half-wave computes X for
@@ -442,12 +446,12 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                 } else {
                     fn = 0.0;
                     if ((unsigned)n < (unsigned)Ni) {
-                        const double dx = n == 0 ? -3.0 * Xc + 4.0 * Xd - Xe
-                                                 : (n == Ni - 1 ? 3.0 * Xc - 4.0 * Xb + Xa : Xd - Xb);
+                        const double dx = (kStart && n == 0) ? -3.0 * Xc + 4.0 * Xd - Xe
+                                          : ((kEnd && n == Ni - 1) ? 3.0 * Xc - 4.0 * Xb + Xa : Xd - Xb);
                         fn = L.s_der * dx + L.s_val * Xc;
                     }
-                    if (n == 0) f0 = fn;
-                    if (n == Ni - 1) fN1 = fn;
+                    if (kStart && n == 0) f0 = fn;
+                    if (kEnd && n == Ni - 1) fN1 = fn;
                 }
                 if (it >= 2) {
                     float dvs;
@@ -460,13 +464,13 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                         dvs = 0.f;
                         if ((unsigned)(rr - 1) < (unsigned)(Ni - 2)) {
                             double rhs = 6.0 * fprev;
-                            if (rr == 1) rhs -= f0;
-                            if (rr == Ni - 2) rhs -= fn;
+                            if (kStart && rr == 1) rhs -= f0;
+                            if (kEnd && rr == Ni - 2) rhs -= fn;
                             const double piv = pivot(rr);
                             const double d = (rhs - dprev) * piv;
                             dprev = d;
                             dvs = (float)d;
-                            if (rr == Ni - 2) dN2 = d;
+                            if (kEnd && rr == Ni - 2) dN2 = d;
                         }
                     }
                     dvr[it - 2] = dvs;
@@ -511,11 +515,11 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
             if (s >= kSrcH && s < kSrcH + kSrcTC) {
                 const int i = rr + 1;
                 double v;
-                if (i == 0) v = 2.0 * f0 - x;
-                else if (i == 1) v = f0;
+                if (kStart && i == 0) v = 2.0 * f0 - x;
+                else if (kStart && i == 1) v = f0;
                 else if (i < Ni) v = x;
-                else if (i == Ni) v = fN1;
-                else if (i == Ni + 1) v = 2.0 * fN1 - dN2;
+                else if (kEnd && i == Ni) v = fN1;
+                else if (kEnd && i == Ni + 1) v = 2.0 * fN1 - dN2;
                 else v = 0.0;
                 DV(s) = (float)v;
             }
@@ -533,12 +537,12 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     }
 }
 
-template <typename TIn, typename TOut, bool GEN>
+template <typename TIn, typename TOut, bool GEN, int ENDS = 3>
 __device__ __forceinline__ void src_chunk_block(const SrcFwdArgs &a, int64_t pbk, int64_t k) {
     __shared__ TIn ring0[kSrcGV];
     __shared__ TIn ring1[kSrcGV];
     __shared__ float tile[(kSrcTC / 4) * kSrcRS];
-    src_chunk<TIn, TOut, GEN>(a, pbk, k * kSrcTC, ring0, ring1, tile);
+    src_chunk<TIn, TOut, GEN, ENDS>(a, pbk, k * kSrcTC, ring0, ring1, tile);
 }
 
 // ------------------------------------------------ chunked source adjoint stage
@@ -987,10 +991,12 @@ template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_kernel(SrcFwdArgs a) {
     src_chunk_block<TIn, TOut, false>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
 }
-// grid (panel blocks, general chunks)
-template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void src_general_kernel(SrcFwdArgs a) {
-    src_chunk_block<TIn, TOut, true>(a, blockIdx.x, src_general_chunk(blockIdx.y, src_interior_chunks(a.N)));
+// one general chunk k for every panel block; ENDS as in src_chunk (a chunk reaching both record ends,
+// a short record, needs more registers: 2 waves per SIMD)
+template <typename TIn, typename TOut, int ENDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ENDS == 1 ? 3 : 2))) void src_general_kernel(
+    SrcFwdArgs a, int64_t k) {
+    src_chunk_block<TIn, TOut, true, ENDS>(a, blockIdx.x, k);
 }
 // batched: blocks of case c are [start[c], start[c+1]), panel block major
 template <typename TIn, typename TOut>
@@ -1033,8 +1039,17 @@ hipError_t source_chunk_launch_t(const SrcFwdArgs &a, hipStream_t stream) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    src_general_kernel<TIn, TOut><<<dim3(pb, (unsigned)ngen), dim3(256), 0, stream>>>(a);
-    return hipGetLastError();
+    // one launch per general chunk, with the end rules it can reach
+    for (int64_t g = 0; g < ngen; ++g) {
+        const int64_t k = src_general_chunk(g, nint), R0 = k * kSrcTC - 1 - kSrcH;
+        const bool s_in = R0 <= 3, e_in = R0 + kSrcW >= a.N - 1;
+        if (s_in && e_in) src_general_kernel<TIn, TOut, 3><<<dim3(pb), dim3(256), 0, stream>>>(a, k);
+        else if (e_in) src_general_kernel<TIn, TOut, 2><<<dim3(pb), dim3(256), 0, stream>>>(a, k);
+        else src_general_kernel<TIn, TOut, 1><<<dim3(pb), dim3(256), 0, stream>>>(a, k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename TIn, typename TScr, typename TOut>
