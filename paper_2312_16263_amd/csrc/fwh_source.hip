@@ -378,10 +378,10 @@ struct SrcDma {
 
 // ENDS (GEN): which record ends the chunk's rows can reach, bit 0 the first frame (R0 <= 3), bit 1
 // the last (R0 + kSrcW >= N - 1); the rules of an end out of reach are compiled out (they would be
-// false at run time), which keeps a one-ended chunk within 3 waves' registers.
+// false at run time).
 template <typename TIn, typename TOut, bool GEN, int ENDS = 3>
 __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int64_t i0, TIn *ring0, TIn *ring1,
-                                          float *tile) {
+                                          float *tile, double *endv) {
     constexpr bool kStart = (ENDS & 1) != 0, kEnd = (ENDS & 2) != 0;
     const int64_t P = a.P, N = a.N;
     const int pl = threadIdx.x & 31;
@@ -419,7 +419,7 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     // Forward sweep over source-term rows k (record row R0 - 3 + k).  Step it (it = 0 .. kSrcW + 1,
     // right-hand side of frame n = R0 - 1 + it) takes X of frames n - 2 .. n + 2 = rows it .. it + 4.
     double Xa = 0.0, Xb = 0.0, Xc = 0.0, Xd = 0.0, Xe = 0.0;
-    double fprev = 0.0, dprev = 0.0, f0 = 0.0, fN1 = 0.0, dN2 = 0.0;
+    double fprev = 0.0, dprev = 0.0, f0 = 0.0;
 #pragma unroll
     for (int m = 0; m < kSrcNG; ++m) {
         // this wave's copies of group m have landed; the barrier makes every wave's visible
@@ -451,7 +451,9 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                         fn = L.s_der * dx + L.s_val * Xc;
                     }
                     if (kStart && n == 0) f0 = fn;
-                    if (kEnd && n == Ni - 1) fN1 = fn;
+                    // f_{N-1} and (below) d_{N-2} wait in LDS for the end coefficients: held in
+                    // registers across the back substitution they cost it about 110 registers
+                    if (kEnd && n == Ni - 1) endv[col] = fn;
                 }
                 if (it >= 2) {
                     float dvs;
@@ -470,7 +472,7 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                             const double d = (rhs - dprev) * piv;
                             dprev = d;
                             dvs = (float)d;
-                            if (kEnd && rr == Ni - 2) dN2 = d;
+                            if (kEnd && rr == Ni - 2) endv[256 + col] = d;
                         }
                     }
                     dvr[it - 2] = dvs;
@@ -518,9 +520,7 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
                 if (kStart && i == 0) v = 2.0 * f0 - x;
                 else if (kStart && i == 1) v = f0;
                 else if (i < Ni) v = x;
-                else if (kEnd && i == Ni) v = fN1;
-                else if (kEnd && i == Ni + 1) v = 2.0 * fN1 - dN2;
-                else v = 0.0;
+                else v = 0.0;  // c_N and c_{N+1} are set as the coefficients leave (below)
                 DV(s) = (float)v;
             }
         }
@@ -531,7 +531,17 @@ __device__ __forceinline__ void src_chunk(const SrcFwdArgs &a, int64_t pbk, int6
     for (int qt = 0; qt < 4; ++qt) {
         __syncthreads();  // the previous quarter's tile has been read
 #pragma unroll
-        for (int q = 0; q < QT; ++q) tile[q * kSrcRS + col] = dvr[kSrcH + qt * QT + q];
+        for (int q = 0; q < QT; ++q) {
+            float c = dvr[kSrcH + qt * QT + q];
+            if constexpr (GEN && kEnd) {
+                // the last frame's end coefficients c_N = f_{N-1}, c_{N+1} = 2 f_{N-1} - d_{N-2} (both
+                // rows lie in the window of a chunk that holds index N or N + 1)
+                const int i = (int)i0 + qt * QT + q;
+                if (i == Ni) c = (float)endv[col];
+                else if (i == Ni + 1) c = (float)(2.0 * endv[col] - endv[256 + col]);
+            }
+            tile[q * kSrcRS + col] = c;
+        }
         __syncthreads();
         src_flush<TOut, QT>(tile, coef, pbase, P, a.NS, i0 + qt * QT);
     }
@@ -542,7 +552,8 @@ __device__ __forceinline__ void src_chunk_block(const SrcFwdArgs &a, int64_t pbk
     __shared__ TIn ring0[kSrcGV];
     __shared__ TIn ring1[kSrcGV];
     __shared__ float tile[(kSrcTC / 4) * kSrcRS];
-    src_chunk<TIn, TOut, GEN, ENDS>(a, pbk, k * kSrcTC, ring0, ring1, tile);
+    __shared__ double endv[GEN && (ENDS & 2) ? 2 * 256 : 1];  // f_{N-1}, d_{N-2} per thread
+    src_chunk<TIn, TOut, GEN, ENDS>(a, pbk, k * kSrcTC, ring0, ring1, tile, endv);
 }
 
 // ------------------------------------------------ chunked source adjoint stage
@@ -991,10 +1002,9 @@ template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_interior_kernel(SrcFwdArgs a) {
     src_chunk_block<TIn, TOut, false>(a, blockIdx.x, 1 + (int64_t)blockIdx.y);
 }
-// one general chunk k for every panel block; ENDS as in src_chunk (a chunk reaching both record ends,
-// a short record, needs more registers: 2 waves per SIMD)
+// one general chunk k for every panel block; ENDS as in src_chunk
 template <typename TIn, typename TOut, int ENDS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ENDS == 1 ? 3 : 2))) void src_general_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_general_kernel(
     SrcFwdArgs a, int64_t k) {
     src_chunk_block<TIn, TOut, true, ENDS>(a, blockIdx.x, k);
 }
@@ -1009,7 +1019,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     src_chunk_block<TIn, TOut, false>(cases[c].src, pbk, 1 + local - pbk * nk);
 }
 template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void src_general_batched(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void src_general_batched(const BatchCase *__restrict__ cases,
                                                            const int64_t *__restrict__ start, int n) {
     const int c = find_case(start, n, blockIdx.x);
     const int64_t local = (int64_t)blockIdx.x - start[c];
